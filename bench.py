@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: fused decode + mixed-precision GEMV over a zfp-compressed matrix.
+
+Workload (the plain path at scale): M is 65536 x 65536 FP32 from
+M[i,j] = exp(-|p_i - q_j| / 32) + N(0, 1e-4) on two 256 x 256 unit lattices,
+held resident in HBM as a WHZ1 fixed-rate stream (8 bits/value: 4.29 GB);
+u is 65536 values U[0,1).  One step = one wh_gemv over all rows (decode of
+every block, FP32 block MAC, FP64 row accumulation, FP32 y).  Inputs are
+resident before timing starts; 4 different u vectors rotate across steps.
+
+Prints one JSON line.  `value` is the effective bandwidth in the paper's
+decoder convention (uncompressed FP32 bytes of M per second, Sec. 4.3);
+`roofline` prices the kernel's algorithmic bytes (compressed stream + u + y)
+against the 8 TB/s HBM peak; `cpu_baseline` times the CPU oracle on a
+bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rate", type=int, default=8)
+    ap.add_argument("--size", type=int, default=65536, help="rows = cols (256x256 lattices at 65536)")
+    ap.add_argument("--flags", type=int, default=0, help="wh_gemv flags (0 default, 1 FP64, 2 TwoSum, 4 Fig. 7)")
+    ap.add_argument("--extra", type=int, default=1, help="also time rate 16 and the separate path")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                                           "traffic.json"))
+    return ap.parse_args()
+
+
+def time_gemv(ctx, mat, us, y, rows, steps, warmup, flags):
+    """Event-timed wh_gemv launches on torch's current stream (the stream the
+    library launches on).  Returns (wall ms/step, per-launch event ms list)."""
+    import torch
+    from paper_1902_08018_amd import wh
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        wh.wh_gemv(ctx, mat, us[i % len(us)], y, 0, rows, flags)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        wh.wh_gemv(ctx, mat, us[i % len(us)], y, 0, rows, flags)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    return wall_ms, [a.elapsed_time(b) for a, b in ev]
+
+
+def cpu_baseline(size, rate):
+    """The CPU oracle (decode + FP64 GEMV, threads over block-rows) on a
+    bounded sample: whole rows of the same matrix, encoded by the oracle."""
+    import numpy as np
+    import oracle
+    from paper_1902_08018_amd import synth
+    spec = synth.LARGE if size == 65536 else synth.MatrixSpec(size, size, int(round(size ** 0.5)), 32.0)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    nrows = 16 * cores  # 4 block-rows per thread
+    M = synth.matrix_rows(spec, 0, nrows)
+    s = oracle.encode(M, rate)
+    u = synth.u_vector(spec)
+    oracle.gemv_fp64(s, nrows, spec.cols, rate, u, nthreads=cores)  # warm
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.gemv_fp64(s, nrows, spec.cols, rate, u, nthreads=cores)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el * cores >= 10.0 or reps >= 50:
+            break
+    sec = el / reps
+    eff_gbs = nrows * spec.cols * 4 / sec / 1e9
+    return {"value": round(eff_gbs, 4), "unit": "GB/s effective (uncompressed FP32 bytes/s)", "cores": cores,
+            "kind": "oracle",
+            "sample": f"rows 0..{nrows} of the {spec.rows}x{spec.cols} matrix (all columns), rate {rate}, "
+                      f"oracle decode + FP64 GEMV, {reps} reps, {el:.1f} s wall",
+            "gflops": round(nrows * (2 * spec.cols - 1) / sec / 1e9, 4)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+              "row sharding across GPUs is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1902_08018_amd import synth, wh, workload
+
+    size, rate = args.size, args.rate
+    spec = synth.LARGE if size == 65536 else synth.MatrixSpec(size, size, int(round(size ** 0.5)), 32.0)
+    rows, cols = spec.rows, spec.cols
+    ctx = wh.wh_create(0, 0)
+    print(f"# building rate-{rate} stream of {rows}x{cols} on the GPU", file=sys.stderr, flush=True)
+    stream = workload.build_stream(ctx, spec, rate)
+    mat = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, stream)
+    us = [workload.u_device(spec, synth.STREAM_U, k * cols) for k in range(4)]
+    y = torch.empty(rows, dtype=torch.float32, device="cuda")
+    print("# timing", file=sys.stderr, flush=True)
+    wall_ms, ev_ms = time_gemv(ctx, mat, us, y, rows, args.steps, args.warmup, args.flags)
+    kern_ms = sum(ev_ms) / len(ev_ms)
+    stream_bytes = stream.numel()
+    alg_bytes = stream_bytes + 4 * cols + 4 * rows
+    eff_gbs = 4.0 * rows * cols / (wall_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    flop = rows * (2 * cols - 1)
+    traffic = None
+    try:
+        with open(args.traffic_json) as f:
+            tj = json.load(f).get(f"whz_gemv_rate{rate}_{rows}x{cols}")
+            if tj:
+                traffic = tj.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    out = {
+        "metric": "decode+GEMV effective GB/s (frac of HBM peak), GFLOP/s; p99 latency vs deadline",
+        "value": round(eff_gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"fused WHZ1 decode+GEMV, {rows}x{cols} FP32 response matrix "
+                               f"(256x256 lattices, ell 32, sigma 1e-4), zfp-style fixed rate {rate} bits/value "
+                               f"({stream_bytes / 1e9:.2f} GB resident), u 65536 U[0,1)",
+                   "rate": rate, "rows": rows, "cols": cols, "acc": "fp64" if args.flags in (0, 1) else args.flags,
+                   "parallelism": "single GPU"},
+        "gflops": round(flop / (wall_ms * 1e-3) / 1e9, 2),
+        "compressed_gbs": round(stream_bytes / (kern_ms * 1e-3) / 1e9, 2),
+        "kernel_ms": round(kern_ms, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+    }
+    wh.wh_unload(ctx, mat)
+    del stream
+    torch.cuda.empty_cache()
+
+    if args.extra:
+        extra = {}
+        # rate 16 on the same matrix
+        print("# rate 16", file=sys.stderr, flush=True)
+        s16 = workload.build_stream(ctx, spec, 16)
+        m16 = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, 16, s16)
+        w16, e16 = time_gemv(ctx, m16, us, y, rows, max(5, args.steps // 2), 2, args.flags)
+        k16 = sum(e16) / len(e16)
+        extra["rate16"] = {"effective_gbs": round(4.0 * rows * cols / (k16 * 1e-3) / 1e9, 2),
+                           "kernel_ms": round(k16, 4),
+                           "hbm_frac": round((s16.numel() + 8 * cols) / (k16 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "gflops": round(flop / (k16 * 1e-3) / 1e9, 2)}
+        # separate path: decode to dense FP32, then dense GEMV (rate 8)
+        print("# separate path", file=sys.stderr, flush=True)
+        wh.wh_unload(ctx, m16)
+        del s16
+        torch.cuda.empty_cache()
+        s8 = workload.build_stream(ctx, spec, rate)
+        m8 = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, s8)
+        dense = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
+        dm = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_F32, 0, dense)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        for _ in range(2):
+            wh.wh_decode(ctx, m8, dense)
+            wh.wh_gemv(ctx, dm, us[0], y, 0, rows)
+        torch.cuda.synchronize()
+        reps = 3
+        td = tg = 0.0
+        for i in range(reps):
+            e0.record()
+            wh.wh_decode(ctx, m8, dense)
+            e1.record()
+            wh.wh_gemv(ctx, dm, us[i % 4], y, 0, rows)
+            e2.record()
+            torch.cuda.synchronize()
+            td += e0.elapsed_time(e1)
+            tg += e1.elapsed_time(e2)
+        td, tg = td / reps, tg / reps
+        extra["separate_rate8"] = {"decode_ms": round(td, 4), "dense_gemv_ms": round(tg, 4),
+                                   "total_ms": round(td + tg, 4),
+                                   "effective_gbs": round(4.0 * rows * cols / ((td + tg) * 1e-3) / 1e9, 2),
+                                   "dense_gemv_hbm_frac": round((4.0 * rows * cols + 8 * cols) / (tg * 1e-3) / 1e9
+                                                                / HBM_PEAK_GBS, 4)}
+        out["extra"] = extra
+        wh.wh_unload(ctx, dm)
+        wh.wh_unload(ctx, m8)
+        del dense, s8
+
+    if args.cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(size, rate)
+    wh.wh_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

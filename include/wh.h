@@ -1,0 +1,190 @@
+/*
+ * wh.h -- C ABI of libwh: on-the-fly decompression + mixed-precision GEMV
+ * for very large dense model matrices on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper: "GPU Acceleration of Real-Time Control Loops",
+ * Bamakhrama et al., ECRTS 2019):
+ *   - Sec. 2.1, Eq. 2: the deformation model is a dense matrix-vector
+ *     product Delta_d = C_d . S_{k+1}, evaluated every light-stage
+ *     millisecond; all real data are single precision.
+ *   - Sec. 2.1 (field/slit divide and conquer) and Fig. 2: the product
+ *     uses a resident sub-matrix and a subset of its rows each millisecond.
+ *   - Sec. 4.3: the matrix is stored zfp-compressed (fixed-rate mode:
+ *     exactly BPV bits per value) and encoded offline.
+ *   - Sec. 4.4, Eq. 5, Fig. 7: mixed-precision GEMV -- FP32 inputs and
+ *     outputs, FP32 multiplies, a wide (FP64) reduction.
+ *   - Sec. 1 / Sec. 4.2: a firm real-time loop with a per-step deadline.
+ *
+ * Conventions (every entry point):
+ *   - Returns a wh_status; no C++ exception crosses the ABI.  Out-params are
+ *     written only when WH_OK is returned.
+ *   - Pointers named d_* are device pointers (HIP/torch allocations on the
+ *     context's device); other pointers are host pointers.  `stream` is a
+ *     hipStream_t (NULL = the null stream).  GEMV/decode/encode calls are
+ *     asynchronous and stream-ordered: argument errors are returned at once;
+ *     a failed launch puts the context into a sticky failed state in which
+ *     every later call returns WH_ERR_DEVICE.
+ *   - The caller owns every d_* buffer it passes; the library owns its
+ *     workspaces and any matrix it copied in (WH_HOST).
+ *   - Matrices are row-major, rows x cols; v1 requires rows and cols to be
+ *     multiples of 4 (else WH_ERR_SHAPE).
+ *   - A context is used from one host thread at a time, except wh_submit /
+ *     wh_poll which are thread-safe.
+ */
+#ifndef WH_H_
+#define WH_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wh_status;
+#define WH_OK 0
+#define WH_PENDING 1
+#define WH_ERR_INVALID (-1)   /* bad argument (NULL, range, unsupported)  */
+#define WH_ERR_SHAPE (-2)     /* dimensions not multiples of 4 / mismatch  */
+#define WH_ERR_FORMAT (-3)    /* unknown format / rate / byte count        */
+#define WH_ERR_NOMEM (-4)     /* device allocation failed                  */
+#define WH_ERR_BUDGET (-5)    /* serving admission: over the HBM budget    */
+#define WH_ERR_DEVICE (-6)    /* HIP error; the context is now failed      */
+#define WH_ERR_NOT_FOUND (-7) /* unknown matrix handle or ticket           */
+
+/* Storage formats of a resident matrix. */
+typedef enum {
+    /* WHZ1: zfp-style fixed-rate code of FP32 values in 4x4 blocks (block
+     * floating point, decorrelating lift, sequency order, negabinary,
+     * embedded bit-plane group testing).  Exactly 16*rate bits per block,
+     * blocks in raster order b = (i/4)*(cols/4) + (j/4).  Sec. 4.3,
+     * Table 2 ("fixed rate"). */
+    WH_FMT_ZFP_FIXED_RATE = 1,
+    WH_FMT_F32 = 2,          /* dense FP32, row-major                       */
+    WH_FMT_F16 = 3,          /* dense IEEE half, RNE from FP32              */
+    WH_FMT_BF16 = 4,         /* dense bfloat16, RNE from FP32               */
+    WH_FMT_FP8E4M3_BS4 = 5   /* OCP FP8 e4m3 codes, 4x4-block tiled (16 B per
+                              * block, raster block order, v = 4r + c inside),
+                              * followed by one FP32 scale per block */
+} wh_format;
+
+typedef struct {
+    uint32_t rows, cols;
+    int32_t fmt;   /* wh_format */
+    uint32_t rate; /* bits per value, WH_FMT_ZFP_FIXED_RATE only; the GPU
+                      decoder supports even rates 2..32 */
+} wh_matrix_desc;
+
+typedef struct wh_ctx wh_ctx;
+typedef uint64_t wh_mat; /* matrix handle, never 0 */
+
+#define WH_HOST 0   /* bytes are host memory: copied, the library owns it   */
+#define WH_DEVICE 1 /* bytes are device memory: borrowed, the caller keeps it
+                       alive and unchanged until wh_unload                   */
+
+/* GEMV flags (accumulation of the cross-block row sums, Sec. 4.4). */
+#define WH_ACC_DEFAULT 0u
+#define WH_ACC_FP64 1u     /* FP32 block partial sums, FP64 accumulation    */
+#define WH_ACC_TWOSUM 2u   /* FP32 block partial sums, compensated FP32
+                              (TwoSum) accumulation                          */
+#define WH_PAPER_MP 4u     /* Fig. 7 exactly: every FP32 product added to an
+                              FP64 sum; slowest; zfp and F32 formats only    */
+
+/* Status text (static storage, never NULL). */
+const char *wh_status_str(wh_status st);
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds
+ * the device memory the serving loop may hold for request buffers (0 = 1 GiB
+ * default).  No GPU / bad device -> WH_ERR_DEVICE. */
+wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx **out);
+
+/* Destroy a context: waits for its work, frees what it owns. */
+wh_status wh_destroy(wh_ctx *ctx);
+
+/* Bytes a matrix of this description occupies (exact). */
+wh_status wh_storage_bytes(const wh_matrix_desc *desc, uint64_t *nbytes);
+
+/* Register a resident matrix (Sec. 2.1 field matrix; Sec. 4.3 offline
+ * encoding).  `nbytes` must equal wh_storage_bytes(desc).  where = WH_HOST:
+ * the bytes are copied to device memory the library owns (synchronously);
+ * WH_DEVICE: the device buffer is borrowed. */
+wh_status wh_load_compressed(wh_ctx *ctx, const wh_matrix_desc *desc, const void *bytes, uint64_t nbytes,
+                             int where, wh_mat *out);
+
+/* Forget a matrix (frees library-owned memory after pending work). */
+wh_status wh_unload(wh_ctx *ctx, wh_mat m);
+
+/* y[i - row_begin] = sum_j M[i, j] u[j] for rows [row_begin, row_end)
+ * (Eq. 2 / Eq. 5 over the slit rows of a resident field matrix, Fig. 2).
+ * d_u: cols FP32; d_y: (row_end - row_begin) FP32.  Both bounds multiples
+ * of 4, row_begin <= row_end <= rows.  Compressed formats are decoded on
+ * the fly inside the kernel; products are FP32; the row sums are FP32
+ * within a 4x4 block and FP64 or compensated FP32 across blocks; y is
+ * rounded once to FP32 (Fig. 7). */
+wh_status wh_gemv(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t row_begin, uint32_t row_end,
+                  uint32_t flags, void *stream);
+
+/* Y = M U for k right-hand sides (Sec. 4.4, batched).  d_U: k vectors of
+ * cols values, vector r at d_U + r*ldu (ldu >= cols), dtype 0 = FP32,
+ * 1 = BF16.  d_Y: k vectors of rows FP32 at d_Y + r*ldy (ldy >= rows).
+ * 1 <= k <= 64.  zfp format only. */
+#define WH_U_F32 0
+#define WH_U_BF16 1
+wh_status wh_gemv_batched(wh_ctx *ctx, wh_mat m, const void *d_U, int u_dtype, uint32_t k, uint32_t ldu,
+                          float *d_Y, uint32_t ldy, uint32_t flags, void *stream);
+
+/* Bit-exactness probe: decode blocks [block_begin, block_begin + nblocks)
+ * of a zfp matrix into d_out[nblocks][16] FP32 (v = 4r + c in a block). */
+wh_status wh_decode_debug(wh_ctx *ctx, wh_mat m, uint64_t block_begin, uint64_t nblocks, float *d_out,
+                          void *stream);
+
+/* Decode a whole zfp matrix into a dense row-major FP32 matrix d_out
+ * (rows x cols) -- the "decode, then GEMV" path of Fig. 11. */
+wh_status wh_decode(wh_ctx *ctx, wh_mat m, float *d_out, void *stream);
+
+/* Offline encoder (Sec. 4.3: encoding happens before the loop starts), run
+ * on the GPU: WHZ1 fixed-rate code of the dense FP32 matrix d_M (rows x
+ * cols, row-major) into d_stream (wh_storage_bytes bytes; every byte is
+ * written).  NaN/Inf values encode as zero blocks and are counted in
+ * *d_bad (device uint32, may be NULL; not cleared by the call). */
+wh_status wh_encode(wh_ctx *ctx, const float *d_M, uint32_t rows, uint32_t cols, uint32_t rate, void *d_stream,
+                    uint32_t *d_bad, void *stream);
+
+/* Quantise a dense FP32 matrix into a reduced-precision storage format
+ * (WH_FMT_F16 / BF16 / FP8E4M3_BS4); d_out holds wh_storage_bytes. */
+wh_status wh_quantize(wh_ctx *ctx, const float *d_M, uint32_t rows, uint32_t cols, int32_t fmt, void *d_out,
+                      void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Serving loop (Sec. 1: firm deadlines; Fig. 2: per-millisecond calls) */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    wh_mat mat;          /* target resident matrix                         */
+    const float *U;      /* k dose vectors of cols FP32, contiguous         */
+    int u_on_device;     /* 0: U is host memory (staged by the library)    */
+    uint32_t k;          /* 1..8 right-hand sides                           */
+    float *Y;            /* k x rows FP32 result                            */
+    int y_on_device;     /* 0: Y is host memory (copied back)               */
+    uint64_t deadline_ns;/* relative deadline from arrival                  */
+    uint64_t arrival_ns; /* 0 = stamp on submit (CLOCK_MONOTONIC ns)        */
+} wh_request;
+
+typedef struct {
+    wh_status status;    /* WH_PENDING, WH_OK or an error                   */
+    uint64_t t_arrive_ns, t_start_ns, t_done_ns;
+    int32_t missed;      /* 1 if t_done > arrival + deadline (still valid)  */
+    uint32_t batch_size; /* requests in the launch that served this one     */
+} wh_result;
+
+/* Enqueue a request; returns a ticket.  Thread-safe, never blocks on the GPU.
+ * Rejected at once with WH_ERR_BUDGET if it can never fit the HBM budget. */
+wh_status wh_submit(wh_ctx *ctx, const wh_request *req, uint64_t *ticket);
+
+/* Non-blocking: WH_PENDING until the request's result is in Y, then WH_OK
+ * (result filled; the ticket is then retired) or the request's error. */
+wh_status wh_poll(wh_ctx *ctx, uint64_t ticket, wh_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WH_H_ */

@@ -1,0 +1,378 @@
+// wh_api.hip -- the C ABI of libwh (declared in include/wh.h).
+//
+// Context = one HIP device, a table of resident matrices, and workspaces
+// (FP64 slab partials of the fused GEMV).  Every entry point validates its
+// arguments before anything is launched, returns a wh_status, and never lets
+// a C++ exception escape.  A failed HIP call marks the context failed
+// (sticky): later calls return WH_ERR_DEVICE.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+
+#include "../../include/wh.h"
+#include "wh_internal.hpp"
+#include "wh_ctx.hpp"
+
+using namespace wh;
+
+namespace wh {
+
+wh_status device_error(wh_ctx* ctx, hipError_t e)
+{
+    if (e == hipSuccess)
+        return WH_OK;
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return WH_ERR_NOMEM;
+    }
+    ctx->failed.store(true);
+    return WH_ERR_DEVICE;
+}
+
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
+wh_status storage_bytes(const wh_matrix_desc& d, uint64_t& nbytes)
+{
+    if (d.rows == 0 || d.cols == 0)
+        return WH_ERR_SHAPE;
+    if (d.rows % 4 || d.cols % 4)
+        return WH_ERR_SHAPE;
+    const uint64_t n = (uint64_t)d.rows * d.cols;
+    const uint64_t nb = n / 16;
+    switch (d.fmt) {
+    case WH_FMT_ZFP_FIXED_RATE:
+        if (!whz_rate_supported(d.rate))
+            return WH_ERR_FORMAT;
+        nbytes = nb * 2u * d.rate;
+        return WH_OK;
+    case WH_FMT_F32:
+        nbytes = n * 4;
+        return WH_OK;
+    case WH_FMT_F16:
+    case WH_FMT_BF16:
+        nbytes = n * 2;
+        return WH_OK;
+    case WH_FMT_FP8E4M3_BS4:
+        nbytes = nb * 16 + nb * 4;
+        return WH_OK;
+    default:
+        return WH_ERR_FORMAT;
+    }
+}
+
+wh_status ensure_partials(wh_ctx* ctx, size_t count)
+{
+    if (count <= ctx->part_cap)
+        return WH_OK;
+    if (ctx->part) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess)
+            return device_error(ctx, e);
+        (void)hipFree(ctx->part);
+        ctx->part = nullptr;
+        ctx->part_cap = 0;
+    }
+    size_t cap = count < (1u << 16) ? (1u << 16) : count;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&ctx->part), cap * sizeof(double));
+    if (e != hipSuccess) {
+        ctx->part = nullptr;
+        return device_error(ctx, e);
+    }
+    ctx->part_cap = cap;
+    return WH_OK;
+}
+
+Matrix* find_matrix(wh_ctx* ctx, wh_mat m)
+{
+    auto it = ctx->mats.find(m);
+    return it == ctx->mats.end() ? nullptr : &it->second;
+}
+
+} // namespace wh
+
+#define WH_GUARD(ctx)                                                                                               \
+    do {                                                                                                             \
+        if (!(ctx))                                                                                                  \
+            return WH_ERR_INVALID;                                                                                   \
+        if ((ctx)->failed.load())                                                                                    \
+            return WH_ERR_DEVICE;                                                                                    \
+        if (hipSetDevice((ctx)->device) != hipSuccess)                                                               \
+            return WH_ERR_DEVICE;                                                                                    \
+    } while (0)
+
+extern "C" {
+
+const char* wh_status_str(wh_status st)
+{
+    switch (st) {
+    case WH_OK:
+        return "ok";
+    case WH_PENDING:
+        return "pending";
+    case WH_ERR_INVALID:
+        return "invalid argument";
+    case WH_ERR_SHAPE:
+        return "bad shape (rows/cols must be positive multiples of 4; row range multiple of 4)";
+    case WH_ERR_FORMAT:
+        return "unsupported format, rate or byte count";
+    case WH_ERR_NOMEM:
+        return "device out of memory";
+    case WH_ERR_BUDGET:
+        return "request exceeds the HBM budget";
+    case WH_ERR_DEVICE:
+        return "HIP device error (context failed)";
+    case WH_ERR_NOT_FOUND:
+        return "unknown matrix handle or ticket";
+    default:
+        return "unknown status";
+    }
+}
+
+wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
+{
+    if (!out)
+        return WH_ERR_INVALID;
+    try {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+            (void)hipGetLastError();
+            return WH_ERR_DEVICE;
+        }
+        if (hip_device < 0 || hip_device >= ndev)
+            return WH_ERR_INVALID;
+        if (hipSetDevice(hip_device) != hipSuccess)
+            return WH_ERR_DEVICE;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess)
+            return WH_ERR_DEVICE;
+        wh_ctx* ctx = new wh_ctx();
+        ctx->device = hip_device;
+        ctx->num_cus = prop.multiProcessorCount;
+        ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (1ull << 30);
+        *out = ctx;
+        return WH_OK;
+    } catch (const std::bad_alloc&) {
+        return WH_ERR_NOMEM;
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
+wh_status wh_destroy(wh_ctx* ctx)
+{
+    if (!ctx)
+        return WH_ERR_INVALID;
+    try {
+        (void)hipSetDevice(ctx->device);
+        serve_shutdown(ctx);
+        (void)hipDeviceSynchronize();
+        for (auto& kv : ctx->mats)
+            if (kv.second.owned && kv.second.dptr)
+                (void)hipFree(kv.second.dptr);
+        if (ctx->part)
+            (void)hipFree(ctx->part);
+        delete ctx;
+        return WH_OK;
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
+wh_status wh_storage_bytes(const wh_matrix_desc* desc, uint64_t* nbytes)
+{
+    if (!desc || !nbytes)
+        return WH_ERR_INVALID;
+    uint64_t n = 0;
+    wh_status st = storage_bytes(*desc, n);
+    if (st == WH_OK)
+        *nbytes = n;
+    return st;
+}
+
+wh_status wh_load_compressed(wh_ctx* ctx, const wh_matrix_desc* desc, const void* bytes, uint64_t nbytes, int where,
+                             wh_mat* out)
+{
+    WH_GUARD(ctx);
+    if (!desc || !bytes || !out || (where != WH_HOST && where != WH_DEVICE))
+        return WH_ERR_INVALID;
+    try {
+        uint64_t need = 0;
+        wh_status st = storage_bytes(*desc, need);
+        if (st != WH_OK)
+            return st;
+        if (nbytes != need)
+            return WH_ERR_FORMAT;
+        Matrix m{};
+        m.desc = *desc;
+        m.nbytes = need;
+        if (where == WH_DEVICE) {
+            if (!aligned(bytes, 16))
+                return WH_ERR_INVALID;
+            m.dptr = const_cast<void*>(bytes);
+            m.owned = false;
+        } else {
+            void* d = nullptr;
+            hipError_t e = hipMalloc(&d, need);
+            if (e != hipSuccess)
+                return device_error(ctx, e);
+            e = hipMemcpy(d, bytes, need, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(d);
+                return device_error(ctx, e);
+            }
+            m.dptr = d;
+            m.owned = true;
+        }
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        const wh_mat id = ctx->next_id++;
+        ctx->mats.emplace(id, m);
+        *out = id;
+        return WH_OK;
+    } catch (const std::bad_alloc&) {
+        return WH_ERR_NOMEM;
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
+wh_status wh_unload(wh_ctx* ctx, wh_mat m)
+{
+    WH_GUARD(ctx);
+    try {
+        Matrix mat;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            auto it = ctx->mats.find(m);
+            if (it == ctx->mats.end())
+                return WH_ERR_NOT_FOUND;
+            mat = it->second;
+            ctx->mats.erase(it);
+        }
+        if (mat.owned) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess)
+                return device_error(ctx, e);
+            (void)hipFree(mat.dptr);
+        }
+        return WH_OK;
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
+wh_status wh_gemv(wh_ctx* ctx, wh_mat m, const float* d_u, float* d_y, uint32_t row_begin, uint32_t row_end,
+                  uint32_t flags, void* stream)
+{
+    WH_GUARD(ctx);
+    if (!d_u || !d_y || !aligned(d_u, 16))
+        return WH_ERR_INVALID;
+    if (flags & ~(WH_ACC_FP64 | WH_ACC_TWOSUM | WH_PAPER_MP))
+        return WH_ERR_INVALID;
+    if ((flags & WH_ACC_FP64) && (flags & WH_ACC_TWOSUM))
+        return WH_ERR_INVALID;
+    try {
+        Matrix mat;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            Matrix* p = find_matrix(ctx, m);
+            if (!p)
+                return WH_ERR_NOT_FOUND;
+            mat = *p;
+        }
+        if (row_begin % 4 || row_end % 4 || row_begin > row_end || row_end > mat.desc.rows)
+            return WH_ERR_SHAPE;
+        if (row_begin == row_end)
+            return WH_OK;
+        const AccMode mode = (flags & WH_PAPER_MP)     ? AccMode::PaperMp
+                             : (flags & WH_ACC_TWOSUM) ? AccMode::TwoSum
+                                                       : AccMode::Fp64;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (mat.desc.fmt == WH_FMT_ZFP_FIXED_RATE) {
+            const GemvPlan pl = whz_gemv_plan(mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus);
+            double* part = nullptr;
+            if (pl.nslab > 1) {
+                wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * (row_end - row_begin));
+                if (s2 != WH_OK)
+                    return s2;
+                part = ctx->part;
+            }
+            return device_error(ctx, whz_gemv(mat.desc.rate, pl, mode, mat.dptr, d_u, d_y, part, st));
+        }
+        return dense_gemv_dispatch(ctx, mat, mode, d_u, d_y, row_begin, row_end, st);
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
+wh_status wh_decode_debug(wh_ctx* ctx, wh_mat m, uint64_t block_begin, uint64_t nblocks, float* d_out, void* stream)
+{
+    WH_GUARD(ctx);
+    if (!d_out || !aligned(d_out, 16))
+        return WH_ERR_INVALID;
+    try {
+        Matrix mat;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            Matrix* p = find_matrix(ctx, m);
+            if (!p)
+                return WH_ERR_NOT_FOUND;
+            mat = *p;
+        }
+        if (mat.desc.fmt != WH_FMT_ZFP_FIXED_RATE)
+            return WH_ERR_FORMAT;
+        const uint64_t nb = (uint64_t)(mat.desc.rows / 4) * (mat.desc.cols / 4);
+        if (block_begin > nb || nblocks > nb - block_begin)
+            return WH_ERR_INVALID;
+        if (nblocks == 0)
+            return WH_OK;
+        return device_error(ctx, whz_decode_blocks(mat.desc.rate, mat.dptr, block_begin, nblocks, d_out,
+                                                   static_cast<hipStream_t>(stream)));
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
+wh_status wh_decode(wh_ctx* ctx, wh_mat m, float* d_out, void* stream)
+{
+    WH_GUARD(ctx);
+    if (!d_out || !aligned(d_out, 16))
+        return WH_ERR_INVALID;
+    try {
+        Matrix mat;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            Matrix* p = find_matrix(ctx, m);
+            if (!p)
+                return WH_ERR_NOT_FOUND;
+            mat = *p;
+        }
+        if (mat.desc.fmt != WH_FMT_ZFP_FIXED_RATE)
+            return WH_ERR_FORMAT;
+        return device_error(ctx, whz_decode_matrix(mat.desc.rate, mat.dptr, mat.desc.rows, mat.desc.cols, d_out,
+                                                   static_cast<hipStream_t>(stream)));
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
+wh_status wh_encode(wh_ctx* ctx, const float* d_M, uint32_t rows, uint32_t cols, uint32_t rate, void* d_stream,
+                    uint32_t* d_bad, void* stream)
+{
+    WH_GUARD(ctx);
+    if (!d_M || !d_stream || !aligned(d_M, 16) || !aligned(d_stream, 4))
+        return WH_ERR_INVALID;
+    if (rows == 0 || cols == 0 || rows % 4 || cols % 4)
+        return WH_ERR_SHAPE;
+    if (!whz_rate_supported(rate))
+        return WH_ERR_FORMAT;
+    try {
+        return device_error(ctx, whz_encode(rate, d_M, rows, cols, d_stream, d_bad, static_cast<hipStream_t>(stream)));
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
+} // extern "C"

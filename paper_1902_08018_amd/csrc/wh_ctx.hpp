@@ -1,0 +1,49 @@
+// wh_ctx.hpp -- the library context (opaque wh_ctx of include/wh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+
+#include "../../include/wh.h"
+#include "wh_internal.hpp"
+
+namespace wh {
+
+struct Matrix {
+    wh_matrix_desc desc;
+    void* dptr;      // device storage (stream, dense values, or codes+scales)
+    uint64_t nbytes; // == storage bytes of desc
+    bool owned;      // copied in by the library (WH_HOST)
+};
+
+struct Server; // serving loop state (serve.hip)
+
+wh_status device_error(wh_ctx* ctx, hipError_t e);
+wh_status ensure_partials(wh_ctx* ctx, size_t count);
+Matrix* find_matrix(wh_ctx* ctx, wh_mat m);
+bool aligned(const void* p, uintptr_t a);
+
+// Dense-storage GEMV (FP32 / FP16 / BF16 / FP8 block-scaled), dense_kernels.hip.
+wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, const float* d_u, float* d_y,
+                              uint32_t row_begin, uint32_t row_end, hipStream_t st);
+
+void serve_shutdown(wh_ctx* ctx);
+
+} // namespace wh
+
+struct wh_ctx {
+    int device = 0;
+    int num_cus = 256;
+    uint64_t budget = 0;
+    std::mutex mu; // guards mats / next_id
+    std::unordered_map<wh_mat, wh::Matrix> mats;
+    wh_mat next_id = 1;
+    double* part = nullptr; // FP64 slab partials
+    size_t part_cap = 0;
+    std::atomic<bool> failed{false};
+    wh::Server* server = nullptr; // owned; freed by serve_shutdown
+};

@@ -1,0 +1,293 @@
+// whz_device.hpp -- WHZ1 block codec, device side (gfx950).
+//
+// WHZ1 is this library's zfp-style fixed-rate code for FP32 matrices in 4x4
+// blocks (the paper stores its matrices zfp-compressed in fixed-rate mode,
+// Sec. 4.3, Table 2).  Per block, exactly maxbits = 16*rate bits, LSB-first:
+//   bit 0          1 if any value is nonzero (else the block is all +0)
+//   bits 1..8      E = emax + 127, emax = max binade exponent, >= -126
+//   bits 9..       embedded bit-plane code of the 16 transform coefficients,
+//                  planes 31 -> 0, truncated at maxbits, zero padded.
+// Coefficients: i = trunc(f * 2^(30 - emax)); a 4-point lift along every
+// block row then every block column; sequency order; negabinary.
+//
+// One lane decodes one block.  The bits of the lane's block sit in a
+// lane-private LDS row (words 0..NW-1 plus three zero words), so a 64-bit
+// window can be read at any bit position with two funnel shifts.
+//
+// Included by the .hip translation units after <hip/hip_runtime.h>.
+#pragma once
+
+#include <stdint.h>
+
+namespace wh {
+
+constexpr uint32_t kNega = 0xAAAAAAAAu;
+
+// Sequency order: coefficient number s of the code is the transform output
+// at local index kOrder(s) = 4r + c (c: horizontal frequency, r: vertical).
+// Ordered by c + r, then c^2 + r^2, then larger c first.
+__device__ __forceinline__ constexpr int order_of(int s)
+{
+    constexpr int t[16] = {0, 1, 4, 5, 2, 8, 6, 9, 3, 12, 10, 7, 13, 11, 14, 15};
+    return t[s];
+}
+
+// ((hi:lo) >> sh) & 0xffffffff for sh in [0, 31]
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh)
+{
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+__device__ __forceinline__ uint32_t asr1(uint32_t v) { return (uint32_t)((int32_t)v >> 1); }
+
+// ---------------------------------------------------------------- lifting
+// Forward lift on (x, y, z, w), modulo 2^32, floor halving.
+__device__ __forceinline__ void fwd_lift(uint32_t& x, uint32_t& y, uint32_t& z, uint32_t& w)
+{
+    x = asr1(x + w);
+    w -= x;
+    z = asr1(z + y);
+    y -= z;
+    x = asr1(x + z);
+    z -= x;
+    w = asr1(w + y);
+    y -= w;
+    w += asr1(y);
+    y -= asr1(w);
+}
+
+// Inverse lift.  Each "a <- a + b; b <- 2b - a" pair is written in its
+// equivalent form "a' = a + b; b' = b - a" (both modulo 2^32).
+__device__ __forceinline__ void inv_lift(uint32_t& x, uint32_t& y, uint32_t& z, uint32_t& w)
+{
+    y += asr1(w);
+    w -= asr1(y);
+    uint32_t t = y;
+    y += w;
+    w -= t;
+    t = z;
+    z += x;
+    x -= t;
+    t = y;
+    y += z;
+    z -= t;
+    t = w;
+    w += x;
+    x -= t;
+}
+
+// 2-D inverse transform, local index v = 4r + c: columns, then rows.
+__device__ __forceinline__ void inv_xform(uint32_t (&v)[16])
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        inv_lift(v[c], v[c + 4], v[c + 8], v[c + 12]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        inv_lift(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
+}
+
+__device__ __forceinline__ void fwd_xform(uint32_t (&v)[16])
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        fwd_lift(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        fwd_lift(v[c], v[c + 4], v[c + 8], v[c + 12]);
+}
+
+// ------------------------------------------------------ bit-matrix transpose
+// A[q] holds plane q in bits 0..15 and plane q+16 in bits 16..31 (bit s of a
+// plane = coefficient s).  Afterwards A[s] is coefficient s: bit p = its bit
+// in plane p.  Both 16x16 halves are transposed at once (the masks repeat in
+// each 16-bit half, and every shifted bit that crosses a half is masked off).
+__device__ __forceinline__ void transpose_planes(uint32_t (&A)[16])
+{
+#pragma unroll
+    for (int d = 8; d >= 1; d >>= 1) {
+        const uint32_t m = d == 8 ? 0x00FF00FFu : d == 4 ? 0x0F0F0F0Fu : d == 2 ? 0x33333333u : 0x55555555u;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if ((i & d) == 0) {
+                const uint32_t a = A[i], b = A[i + d];
+                A[i] = (a & m) | ((b << d) & ~m);
+                A[i + d] = ((a >> d) & m) | (b & ~m);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- decoding
+// Decode the block whose words are at lw[0..NW-1] (lw[NW..NW+2] == 0); w0 ==
+// lw[0].  Outputs the 16 integers of the block after the inverse transform
+// (local index 4r + c) and emax.  Returns false for an all-zero block (then
+// iv[] is all 0).  Every bit pattern decodes (the function is total).
+template <int NW>
+__device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, uint32_t w0, int& emax, uint32_t (&iv)[16])
+{
+    constexpr uint32_t kMaxBits = 32u * NW;
+    const bool nz = (w0 & 1u) != 0;
+    emax = (int)((w0 >> 1) & 0xFFu) - 127;
+    uint32_t left = nz ? kMaxBits - 9u : 0u; // bits of the plane code still to read
+    uint32_t pos = 9u;                        // bit position in the block
+    uint32_t nsig = 0u;                       // coefficients 0..nsig-1 significant
+    uint32_t A[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        A[q] = 0u;
+
+#pragma unroll
+    for (int p = 31; p >= 0; --p) {
+        if (!__any(left != 0u))
+            break;
+        if (left != 0u) {
+            // 64-bit window at pos
+            const uint32_t q = pos >> 5, o = pos & 31u;
+            const uint32_t d0 = lw[q], d1 = lw[q + 1], d2 = lw[q + 2];
+            uint32_t lo = funnel(d1, d0, o), hi = funnel(d2, d1, o);
+            // (i) verbatim bits of the significant coefficients
+            const uint32_t m = nsig < left ? nsig : left;
+            uint32_t x = lo & ((1u << m) - 1u);
+            lo = funnel(hi, lo, m);
+            hi >>= m;
+            left -= m;
+            pos += m;
+            // (ii) group tests: each "1" opens a run of zeros that ends at
+            // the next newly significant coefficient
+            while (nsig < 16u && left != 0u) {
+                if ((lo & 1u) == 0u) { // group bit 0: plane done
+                    lo = funnel(hi, lo, 1u);
+                    hi >>= 1;
+                    left -= 1u;
+                    pos += 1u;
+                    break;
+                }
+                const uint32_t run = (uint32_t)__builtin_ctz((lo >> 1) | 0x10000u);
+                const uint32_t room = left - 1u;
+                uint32_t cap = 15u - nsig;
+                cap = cap < room ? cap : room;
+                const uint32_t r = run < cap ? run : cap;
+                // the terminating 1 is read only when the run ends before the
+                // cap; at the cap (position 15, or no bits left) it is implied
+                const uint32_t used = 1u + r + (run < cap ? 1u : 0u);
+                x |= 1u << (nsig + r);
+                nsig += r + 1u;
+                left -= used;
+                pos += used;
+                lo = funnel(hi, lo, used);
+                hi >>= used;
+            }
+            if (p >= 16)
+                A[p - 16] |= x << 16;
+            else
+                A[p] |= x;
+        }
+    }
+
+    transpose_planes(A);
+    // negabinary -> two's complement, undo the sequency order
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        iv[order_of(s)] = (A[s] ^ kNega) - kNega;
+    inv_xform(iv);
+    return nz;
+}
+
+// --------------------------------------------------------------- encoding
+// Bit writer over a lane-private word array of NW words (zeroed first).
+template <int NW>
+struct BitSink {
+    uint32_t w[NW];
+    uint32_t pos;
+
+    __device__ __forceinline__ void put(uint32_t bits, uint32_t k) // k <= 16
+    {
+        if (k == 0u)
+            return;
+        const uint32_t q = pos >> 5, o = pos & 31u;
+        w[q] |= bits << o;
+        if (o + k > 32u)
+            w[q + 1] |= bits >> (32u - o);
+        pos += k;
+    }
+};
+
+// Biased exponent field F of a value.  For a normal value the binade
+// exponent is e = F - 126 (|f| in [2^(e-1), 2^e)); a subnormal has F = 0 and
+// e <= -126, which the clamp at -126 turns into F - 126 as well.  So
+// emax = max over nonzero values of F, minus 126.
+__device__ __forceinline__ uint32_t exp_field(float f) { return (__float_as_uint(f) >> 23) & 0xFFu; }
+
+// Encode 16 values (local index 4r + c) into out (NW words).  Returns false
+// if a value is NaN or Inf (the block is then written as a zero block).
+template <int NW>
+__device__ __forceinline__ bool encode_block(const float (&f)[16], uint32_t (&out)[NW])
+{
+    constexpr uint32_t kMaxBits = 32u * NW;
+    BitSink<NW> sink;
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+        sink.w[k] = 0u;
+    sink.pos = 0u;
+    bool finite = true, nonzero = false;
+    uint32_t emax_field = 0u;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const uint32_t e = exp_field(f[v]);
+        finite = finite && e != 0xFFu;
+        if (f[v] != 0.0f) {
+            nonzero = true;
+            emax_field = e > emax_field ? e : emax_field;
+        }
+    }
+    if (finite && nonzero) {
+        const int emax = (int)emax_field - 126;
+        sink.put(1u, 1u);
+        sink.put((uint32_t)(emax + 127), 8u);
+        uint32_t iv[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            iv[v] = (uint32_t)(int32_t)__builtin_truncf(__builtin_ldexpf(f[v], 30 - emax));
+        fwd_xform(iv);
+        uint32_t nb[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            nb[s] = (iv[order_of(s)] + kNega) ^ kNega;
+        uint32_t left = kMaxBits - 9u, nsig = 0u;
+        for (int p = 31; p >= 0 && left != 0u; --p) {
+            uint32_t x = 0u;
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                x |= ((nb[s] >> p) & 1u) << s;
+            const uint32_t m = nsig < left ? nsig : left;
+            sink.put(x & ((1u << m) - 1u), m);
+            x >>= m;
+            left -= m;
+            while (nsig < 16u && left != 0u) {
+                const uint32_t g = x != 0u;
+                sink.put(g, 1u);
+                left -= 1u;
+                if (!g)
+                    break;
+                while (nsig < 15u && left != 0u) {
+                    const uint32_t bit = x & 1u;
+                    sink.put(bit, 1u);
+                    left -= 1u;
+                    if (bit)
+                        break;
+                    x >>= 1;
+                    nsig += 1u;
+                }
+                x >>= 1;
+                nsig += 1u;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+        out[k] = sink.w[k];
+    return finite;
+}
+
+} // namespace wh

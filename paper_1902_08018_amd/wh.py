@@ -1,0 +1,219 @@
+"""Python binding of libwh (include/wh.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does
+nothing but check Python-side types, pass raw pointers (torch tensors give
+device memory, `torch.cuda.current_stream()` gives the stream) and turn a
+non-OK status into `WhError`.  All the work runs in the HIP library; there is
+no fallback: if libwh.so is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # loads the HIP runtime that libwh.so shares  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwh.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libwh.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+WH_OK, WH_PENDING = 0, 1
+WH_ERR_INVALID, WH_ERR_SHAPE, WH_ERR_FORMAT, WH_ERR_NOMEM = -1, -2, -3, -4
+WH_ERR_BUDGET, WH_ERR_DEVICE, WH_ERR_NOT_FOUND = -5, -6, -7
+
+WH_FMT_ZFP_FIXED_RATE, WH_FMT_F32, WH_FMT_F16, WH_FMT_BF16, WH_FMT_FP8E4M3_BS4 = 1, 2, 3, 4, 5
+WH_HOST, WH_DEVICE = 0, 1
+WH_ACC_DEFAULT, WH_ACC_FP64, WH_ACC_TWOSUM, WH_PAPER_MP = 0, 1, 2, 4
+WH_U_F32, WH_U_BF16 = 0, 1
+
+
+class WhError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {wh_status_str(status)} ({status})")
+
+
+class wh_matrix_desc(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_uint32), ("cols", ctypes.c_uint32), ("fmt", ctypes.c_int32),
+                ("rate", ctypes.c_uint32)]
+
+
+class wh_request(ctypes.Structure):
+    _fields_ = [("mat", ctypes.c_uint64), ("U", ctypes.c_void_p), ("u_on_device", ctypes.c_int),
+                ("k", ctypes.c_uint32), ("Y", ctypes.c_void_p), ("y_on_device", ctypes.c_int),
+                ("deadline_ns", ctypes.c_uint64), ("arrival_ns", ctypes.c_uint64)]
+
+
+class wh_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("t_arrive_ns", ctypes.c_uint64), ("t_start_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("missed", ctypes.c_int32), ("batch_size", ctypes.c_uint32)]
+
+
+_P, _U32, _U64, _I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+_sig = {
+    "wh_status_str": ([_I32], ctypes.c_char_p),
+    "wh_create": ([ctypes.c_int, _U64, ctypes.POINTER(ctypes.c_void_p)], _I32),
+    "wh_destroy": ([_P], _I32),
+    "wh_storage_bytes": ([ctypes.POINTER(wh_matrix_desc), ctypes.POINTER(_U64)], _I32),
+    "wh_load_compressed": ([_P, ctypes.POINTER(wh_matrix_desc), _P, _U64, ctypes.c_int, ctypes.POINTER(_U64)],
+                           _I32),
+    "wh_unload": ([_P, _U64], _I32),
+    "wh_gemv": ([_P, _U64, _P, _P, _U32, _U32, _U32, _P], _I32),
+    "wh_gemv_batched": ([_P, _U64, _P, ctypes.c_int, _U32, _U32, _P, _U32, _U32, _P], _I32),
+    "wh_decode_debug": ([_P, _U64, _U64, _U64, _P, _P], _I32),
+    "wh_decode": ([_P, _U64, _P, _P], _I32),
+    "wh_encode": ([_P, _P, _U32, _U32, _U32, _P, _P, _P], _I32),
+    "wh_quantize": ([_P, _P, _U32, _U32, _I32, _P, _P], _I32),
+    "wh_submit": ([_P, ctypes.POINTER(wh_request), ctypes.POINTER(_U64)], _I32),
+    "wh_poll": ([_P, _U64, ctypes.POINTER(wh_result)], _I32),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_sig)
+
+
+def _check(st: int, where: str) -> int:
+    if st < 0:
+        raise WhError(st, where)
+    return st
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dptr(t: torch.Tensor, dtype=None, name: str = "tensor") -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def wh_status_str(st: int) -> str:
+    return _lib.wh_status_str(st).decode()
+
+
+def wh_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.wh_create(device, hbm_budget_bytes, ctypes.byref(h)), "wh_create")
+    return h.value
+
+
+def wh_destroy(ctx: int) -> None:
+    _check(_lib.wh_destroy(ctx), "wh_destroy")
+
+
+def wh_storage_bytes(rows: int, cols: int, fmt: int, rate: int = 0) -> int:
+    d = wh_matrix_desc(rows, cols, fmt, rate)
+    n = _U64()
+    _check(_lib.wh_storage_bytes(ctypes.byref(d), ctypes.byref(n)), "wh_storage_bytes")
+    return n.value
+
+
+def wh_load_compressed(ctx: int, rows: int, cols: int, fmt: int, rate: int, data) -> int:
+    """`data`: a CUDA tensor (borrowed; keep it alive) or a host numpy/CPU
+    tensor (copied).  Returns the matrix handle."""
+    d = wh_matrix_desc(rows, cols, fmt, rate)
+    h = _U64()
+    if isinstance(data, torch.Tensor) and data.is_cuda:
+        ptr, nbytes, where = _dptr(data, name="data"), data.numel() * data.element_size(), WH_DEVICE
+    else:
+        import numpy as np
+        arr = data.numpy() if isinstance(data, torch.Tensor) else data
+        arr = np.ascontiguousarray(arr)
+        ptr, nbytes, where = arr.ctypes.data, arr.nbytes, WH_HOST
+    _check(_lib.wh_load_compressed(ctx, ctypes.byref(d), ptr, nbytes, where, ctypes.byref(h)), "wh_load_compressed")
+    return h.value
+
+
+def wh_unload(ctx: int, mat: int) -> None:
+    _check(_lib.wh_unload(ctx, mat), "wh_unload")
+
+
+def wh_gemv(ctx: int, mat: int, u: torch.Tensor, y: torch.Tensor, row_begin: int, row_end: int,
+            flags: int = WH_ACC_DEFAULT, stream=None) -> None:
+    _check(_lib.wh_gemv(ctx, mat, _dptr(u, torch.float32, "u"), _dptr(y, torch.float32, "y"), row_begin, row_end,
+                        flags, _stream(stream)), "wh_gemv")
+
+
+def wh_gemv_batched(ctx: int, mat: int, U: torch.Tensor, Y: torch.Tensor, flags: int = WH_ACC_DEFAULT,
+                    stream=None) -> None:
+    """U: (k, ldu>=cols) float32 or bfloat16; Y: (k, ldy>=rows) float32."""
+    if U.dim() != 2 or Y.dim() != 2 or U.shape[0] != Y.shape[0]:
+        raise ValueError("U and Y must be (k, n) with the same k")
+    if U.dtype == torch.float32:
+        dt = WH_U_F32
+    elif U.dtype == torch.bfloat16:
+        dt = WH_U_BF16
+    else:
+        raise TypeError("U must be float32 or bfloat16")
+    if U.stride(1) != 1 or Y.stride(1) != 1:
+        raise ValueError("rows of U and Y must be contiguous")
+    _check(_lib.wh_gemv_batched(ctx, mat, U.data_ptr(), dt, U.shape[0], U.stride(0), _dptr(Y.view(-1) if
+                                Y.is_contiguous() else Y, torch.float32, "Y") if Y.is_contiguous() else Y.data_ptr(),
+                                Y.stride(0), flags, _stream(stream)), "wh_gemv_batched")
+
+
+def wh_decode_debug(ctx: int, mat: int, block_begin: int, nblocks: int, out: torch.Tensor, stream=None) -> None:
+    _check(_lib.wh_decode_debug(ctx, mat, block_begin, nblocks, _dptr(out, torch.float32, "out"), _stream(stream)),
+           "wh_decode_debug")
+
+
+def wh_decode(ctx: int, mat: int, out: torch.Tensor, stream=None) -> None:
+    _check(_lib.wh_decode(ctx, mat, _dptr(out, torch.float32, "out"), _stream(stream)), "wh_decode")
+
+
+def wh_encode(ctx: int, M: torch.Tensor, rate: int, stream_out: torch.Tensor, bad: torch.Tensor | None = None,
+              stream=None) -> None:
+    rows, cols = M.shape
+    _check(_lib.wh_encode(ctx, _dptr(M, torch.float32, "M"), rows, cols, rate, _dptr(stream_out, name="stream_out"),
+                          None if bad is None else _dptr(bad, torch.int32, "bad"), _stream(stream)), "wh_encode")
+
+
+def wh_quantize(ctx: int, M: torch.Tensor, fmt: int, out: torch.Tensor, stream=None) -> None:
+    rows, cols = M.shape
+    _check(_lib.wh_quantize(ctx, _dptr(M, torch.float32, "M"), rows, cols, fmt, _dptr(out, name="out"),
+                            _stream(stream)), "wh_quantize")
+
+
+def wh_submit(ctx: int, req: wh_request) -> int:
+    t = _U64()
+    _check(_lib.wh_submit(ctx, ctypes.byref(req), ctypes.byref(t)), "wh_submit")
+    return t.value
+
+
+def wh_poll(ctx: int, ticket: int) -> tuple[int, wh_result]:
+    r = wh_result()
+    st = _check(_lib.wh_poll(ctx, ticket, ctypes.byref(r)), "wh_poll")
+    return st, r
+
+
+# ------------------------------------------------------------- convenience
+@dataclass
+class Matrix:
+    ctx: int
+    handle: int
+    rows: int
+    cols: int
+    fmt: int
+    rate: int
+    storage: object  # keeps a borrowed device buffer alive
+
+
+def stream_bytes(rows: int, cols: int, rate: int) -> int:
+    return wh_storage_bytes(rows, cols, WH_FMT_ZFP_FIXED_RATE, rate)

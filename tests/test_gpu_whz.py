@@ -1,0 +1,273 @@
+"""GPU parity of the WHZ1 path against the CPU oracle (through the C ABI).
+
+  decode     bit-exact (uint32 views) vs the oracle's decode: real streams,
+             random byte strings (the decoder is total), extreme exponents
+  encode     the library's GPU encoder writes the oracle's bytes exactly
+  gemv       y within relative L2 1e-6 of the FP64 oracle over the
+             oracle-decoded matrix (FP32 storage, FP32 products, FP64 or
+             compensated reduction); Fig. 7 mode within 1 ulp of the oracle's
+             Fig. 7 output
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1902_08018_amd import synth, wh
+
+pytestmark = pytest.mark.gpu
+
+REL_L2_FP32 = 1e-6  # FP32 storage + FP32 products, wide reduction
+
+
+def rel_l2(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+
+
+def load_stream(ctx, stream_np, rows, cols, rate):
+    d = torch.from_numpy(np.ascontiguousarray(stream_np)).cuda()
+    return wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, d), d
+
+
+def gpu_decode_blocks(ctx, mat, b0, n):
+    out = torch.empty((n, 16), dtype=torch.float32, device="cuda")
+    wh.wh_decode_debug(ctx, mat, b0, n, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def blocks_of(M):
+    R, C = M.shape
+    return M.reshape(R // 4, 4, C // 4, 4).transpose(0, 2, 1, 3).reshape(-1, 16)
+
+
+# ------------------------------------------------------------------ decode
+@pytest.mark.parametrize("rate", [2, 4, 6, 8, 10, 12, 14, 16, 20, 24, 32])
+def test_decode_random_bytes_bitexact(gpu_ctx, rate):
+    rows, cols = 64, 256  # 1024 blocks: several workgroups, every rate
+    rng = np.random.default_rng(1000 + rate)
+    s = rng.integers(0, 256, size=oracle.stream_nbytes(rows, cols, rate), dtype=np.uint8)
+    mat, keep = load_stream(gpu_ctx, s, rows, cols, rate)
+    nb = (rows // 4) * (cols // 4)
+    got = gpu_decode_blocks(gpu_ctx, mat, 0, nb)
+    ref = oracle.decode_blocks(s, rate, 0, nb)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    # a ragged sub-range
+    got2 = gpu_decode_blocks(gpu_ctx, mat, 37, 301)
+    assert np.array_equal(got2.view(np.uint32), ref[37:338].view(np.uint32))
+    wh.wh_unload(gpu_ctx, mat)
+
+
+@pytest.mark.parametrize("rate", [4, 8, 16, 32])
+def test_decode_real_bitexact(gpu_ctx, rate):
+    M = synth.matrix_rows(synth.SMALL, 0, 64)
+    s = oracle.encode(M, rate)
+    mat, keep = load_stream(gpu_ctx, s, 64, 4096, rate)
+    nb = 16 * 1024
+    got = gpu_decode_blocks(gpu_ctx, mat, 0, nb)
+    ref = oracle.decode_blocks(s, rate, 0, nb)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    # whole-matrix decode into row-major FP32
+    dense = torch.empty((64, 4096), dtype=torch.float32, device="cuda")
+    wh.wh_decode(gpu_ctx, mat, dense)
+    torch.cuda.synchronize()
+    assert np.array_equal(dense.cpu().numpy().view(np.uint32), oracle.decode(s, 64, 4096, rate).view(np.uint32))
+    wh.wh_unload(gpu_ctx, mat)
+
+
+def extreme_matrix(seed):
+    rng = np.random.default_rng(seed)
+    nblk = 4096
+    scale = np.exp2(rng.integers(-149, 128, size=(nblk, 1)).astype(np.float64))
+    vals = rng.standard_normal((nblk, 16)) * scale
+    vals = np.clip(vals, -3.0e38, 3.0e38).astype(np.float32)
+    vals[rng.random((nblk, 16)) < 0.25] = 0.0
+    vals[:64] = (np.float32(1.4e-45) * rng.integers(-7, 8, size=(64, 16))).astype(np.float32)  # subnormal
+    vals[64:128] = np.float32(3.3e38) * rng.choice([-1.0, 1.0], size=(64, 16)).astype(np.float32)
+    vals[128:160] = 0.0
+    vals[160:192] = np.float32(-0.0)
+    vals[192:256] = rng.integers(-15, 16, size=(64, 1)).astype(np.float32)  # constant blocks
+    # blocks -> a 256 x 256 matrix (64 block-rows x 64 block-cols)
+    return vals.reshape(64, 64, 4, 4).transpose(0, 2, 1, 3).reshape(256, 256)
+
+
+@pytest.mark.parametrize("rate", [2, 8, 16, 32])
+def test_encode_decode_extremes_bitexact(gpu_ctx, rate):
+    M = extreme_matrix(rate)
+    ref_stream = oracle.encode(M, rate)
+    Md = torch.from_numpy(M).cuda()
+    out = torch.zeros(ref_stream.size, dtype=torch.uint8, device="cuda")
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    wh.wh_encode(gpu_ctx, Md, rate, out, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    assert np.array_equal(out.cpu().numpy(), ref_stream)
+    mat = wh.wh_load_compressed(gpu_ctx, 256, 256, wh.WH_FMT_ZFP_FIXED_RATE, rate, out)
+    got = gpu_decode_blocks(gpu_ctx, mat, 0, 4096)
+    ref = oracle.decode_blocks(ref_stream, rate, 0, 4096)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    wh.wh_unload(gpu_ctx, mat)
+
+
+def test_encode_counts_nonfinite(gpu_ctx):
+    M = np.ones((8, 8), dtype=np.float32)
+    M[0, 0] = np.nan
+    M[5, 6] = np.inf
+    out = torch.zeros(oracle.stream_nbytes(8, 8, 8), dtype=torch.uint8, device="cuda")
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    wh.wh_encode(gpu_ctx, torch.from_numpy(M).cuda(), 8, out, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 2
+
+
+@pytest.mark.parametrize("rate", [8, 16])
+def test_encode_synthetic_bitexact(gpu_ctx, rate):
+    M = synth.matrix_rows(synth.SMALL, 1024, 1280)
+    ref = oracle.encode(M, rate)
+    out = torch.zeros(ref.size, dtype=torch.uint8, device="cuda")
+    wh.wh_encode(gpu_ctx, torch.from_numpy(M).cuda(), rate, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
+# -------------------------------------------------------------------- gemv
+@pytest.fixture(scope="module")
+def small_case():
+    """4096 x 4096 on 64x64 lattices, ell 8, sigma 1e-4, seed 0; u U[0,1)."""
+    M = synth.matrix(synth.SMALL)
+    u = synth.u_vector(synth.SMALL)
+    return M, u, {r: oracle.encode(M, r) for r in (8, 16)}
+
+
+@pytest.mark.parametrize("rate", [8, 16])
+@pytest.mark.parametrize("flags", [wh.WH_ACC_DEFAULT, wh.WH_ACC_FP64, wh.WH_ACC_TWOSUM])
+def test_gemv_small_config(gpu_ctx, small_case, rate, flags):
+    M, u, streams = small_case
+    s = streams[rate]
+    ref = oracle.gemv_fp64(s, 4096, 4096, rate, u, nthreads=8)
+    mat, keep = load_stream(gpu_ctx, s, 4096, 4096, rate)
+    ud = torch.from_numpy(u).cuda()
+    y = torch.empty(4096, dtype=torch.float32, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, ud, y, 0, 4096, flags)
+    torch.cuda.synchronize()
+    err = rel_l2(y.cpu().numpy(), ref)
+    print(f"rate {rate} flags {flags}: rel-L2 vs FP64 oracle {err:.3e}")
+    assert err <= REL_L2_FP32
+    # slit rows of the resident field matrix (Fig. 2): a row range
+    y2 = torch.empty(1000, dtype=torch.float32, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, ud, y2, 1500, 2500, flags)
+    torch.cuda.synchronize()
+    err2 = rel_l2(y2.cpu().numpy(), ref[1500:2500])
+    print(f"rows 1500..2500: rel-L2 {err2:.3e}")
+    assert err2 <= REL_L2_FP32
+    wh.wh_unload(gpu_ctx, mat)
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (4, 1028), (260, 1028), (1028, 260), (68, 65540), (8, 12)])
+@pytest.mark.parametrize("rate", [8, 16])
+def test_gemv_ragged_shapes(gpu_ctx, shape, rate):
+    rows, cols = shape
+    spec = synth.MatrixSpec(rows, cols, 64, 8.0, seed=3)
+    M = synth.matrix(spec)
+    u = synth.uniform(cols, seed=3)
+    s = oracle.encode(M, rate)
+    ref = oracle.gemv_fp64(s, rows, cols, rate, u, nthreads=8)
+    mat, keep = load_stream(gpu_ctx, s, rows, cols, rate)
+    y = torch.empty(rows, dtype=torch.float32, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u).cuda(), y, 0, rows)
+    torch.cuda.synchronize()
+    err = rel_l2(y.cpu().numpy(), ref)
+    print(f"{shape} rate {rate}: rel-L2 {err:.3e}")
+    assert err <= REL_L2_FP32
+    wh.wh_unload(gpu_ctx, mat)
+
+
+@pytest.mark.parametrize("rate", [8, 16])
+def test_gemv_paper_mp(gpu_ctx, small_case, rate):
+    """Fig. 7 semantics: FP32 products, FP64 sum, FP32 result -- within one
+    FP32 ulp of the oracle's sequential Fig. 7 (the GPU sums in a different
+    order, so a result on a rounding tie may land on the neighbour)."""
+    M, u, streams = small_case
+    s = streams[rate]
+    ref = oracle.gemv_paper_mp(s, 4096, 4096, rate, u, nthreads=8)
+    mat, keep = load_stream(gpu_ctx, s, 4096, 4096, rate)
+    y = torch.empty(4096, dtype=torch.float32, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u).cuda(), y, 0, 4096, wh.WH_PAPER_MP)
+    torch.cuda.synchronize()
+    g = y.cpu().numpy()
+    ulp = np.spacing(np.abs(ref).astype(np.float32))
+    assert np.all(np.abs(g.astype(np.float64) - ref) <= ulp)
+    wh.wh_unload(gpu_ctx, mat)
+
+
+def test_gemv_zero_matrix_and_empty_range(gpu_ctx):
+    s = np.zeros(oracle.stream_nbytes(16, 32, 8), dtype=np.uint8)
+    mat, keep = load_stream(gpu_ctx, s, 16, 32, 8)
+    u = torch.rand(32, device="cuda")
+    y = torch.full((16,), 7.0, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, u, y, 0, 16)
+    wh.wh_gemv(gpu_ctx, mat, u, y, 8, 8)  # empty row range: no-op
+    torch.cuda.synchronize()
+    assert torch.all(y == 0)
+    wh.wh_unload(gpu_ctx, mat)
+
+
+def test_gemv_argument_errors(gpu_ctx):
+    s = np.zeros(oracle.stream_nbytes(16, 32, 8), dtype=np.uint8)
+    mat, keep = load_stream(gpu_ctx, s, 16, 32, 8)
+    u = torch.rand(32, device="cuda")
+    y = torch.empty(16, device="cuda")
+    for args, code in [((0, 6), wh.WH_ERR_SHAPE), ((4, 20), wh.WH_ERR_SHAPE), ((8, 4), wh.WH_ERR_SHAPE)]:
+        with pytest.raises(wh.WhError) as ei:
+            wh.wh_gemv(gpu_ctx, mat, u, y, *args)
+        assert ei.value.status == code
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_gemv(gpu_ctx, mat + 999, u, y, 0, 16)
+    assert ei.value.status == wh.WH_ERR_NOT_FOUND
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_gemv(gpu_ctx, mat, u, y, 0, 16, wh.WH_ACC_FP64 | wh.WH_ACC_TWOSUM)
+    assert ei.value.status == wh.WH_ERR_INVALID
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_load_compressed(gpu_ctx, 16, 32, wh.WH_FMT_ZFP_FIXED_RATE, 7, torch.zeros(448, dtype=torch.uint8,
+                                                                                          device="cuda"))
+    assert ei.value.status == wh.WH_ERR_FORMAT
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_load_compressed(gpu_ctx, 16, 32, wh.WH_FMT_ZFP_FIXED_RATE, 8, torch.zeros(10, dtype=torch.uint8,
+                                                                                          device="cuda"))
+    assert ei.value.status == wh.WH_ERR_FORMAT
+    wh.wh_unload(gpu_ctx, mat)
+
+
+def test_separate_decode_then_gemv(gpu_ctx, small_case):
+    """Fig. 11's two-stage path: decode to dense FP32, then a dense GEMV."""
+    M, u, streams = small_case
+    s = streams[8]
+    ref = oracle.gemv_fp64(s, 4096, 4096, 8, u, nthreads=8)
+    mat, keep = load_stream(gpu_ctx, s, 4096, 4096, 8)
+    dense = torch.empty((4096, 4096), dtype=torch.float32, device="cuda")
+    wh.wh_decode(gpu_ctx, mat, dense)
+    dm = wh.wh_load_compressed(gpu_ctx, 4096, 4096, wh.WH_FMT_F32, 0, dense)
+    y = torch.empty(4096, dtype=torch.float32, device="cuda")
+    wh.wh_gemv(gpu_ctx, dm, torch.from_numpy(u).cuda(), y, 0, 4096)
+    torch.cuda.synchronize()
+    err = rel_l2(y.cpu().numpy(), ref)
+    print(f"separate path rel-L2 {err:.3e}")
+    assert err <= REL_L2_FP32
+    wh.wh_unload(gpu_ctx, dm)
+    wh.wh_unload(gpu_ctx, mat)
+
+
+def test_device_generator_matches_host():
+    spec = synth.LARGE
+    table = synth.device_table(spec)
+    rows = [(0, 4), (30000, 30004), (65532, 65536)]
+    for r0, r1 in rows:
+        d = torch.empty((r1 - r0) * spec.cols, dtype=torch.float32, device="cuda")
+        synth.matrix_rows_device(spec, r0, r1, d, table)
+        h = synth.matrix_rows(spec, r0, r1)
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), h.reshape(-1).view(np.uint32))
+    ud = torch.empty(spec.cols, dtype=torch.float32, device="cuda")
+    synth.uniform_device(ud, spec.seed, synth.STREAM_U)
+    assert np.array_equal(ud.cpu().numpy(), synth.u_vector(spec))
