@@ -176,7 +176,12 @@ typedef struct {
 } wh_result;
 
 /* Enqueue a request; returns a ticket.  Thread-safe, never blocks on the GPU.
- * Rejected at once with WH_ERR_BUDGET if it can never fit the HBM budget. */
+ * The first request for a matrix sets up its serving state: device slots of
+ * 64 right-hand sides each (two if the context's HBM budget allows, one
+ * otherwise) and one captured hipGraph per k-bucket and slot.  Rejected at
+ * once with WH_ERR_BUDGET if not even one slot of that matrix fits the
+ * budget, or if k > 64.  U and Y must stay valid until wh_poll reports the
+ * request done.  zfp matrices only. */
 wh_status wh_submit(wh_ctx *ctx, const wh_request *req, uint64_t *ticket);
 
 /* Non-blocking: WH_PENDING until the request's result is in Y, then WH_OK

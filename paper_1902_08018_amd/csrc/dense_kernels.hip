@@ -314,7 +314,7 @@ __device__ __forceinline__ uint32_t f32_to_e4m3_rne(float x)
     const float k = __builtin_rintf(__builtin_ldexpf(a, -qexp));
     const float r = __builtin_ldexpf(k, qexp); // rounded magnitude (may step to the next binade)
     if (r == 0.0f)
-        return sign;
+        return 0u; // a value that rounds to zero has code 0 (never -0)
     int re;
     (void)__builtin_frexpf(r, &re);
     const int E = (re - 1) + 7; // biased exponent if normal
@@ -413,7 +413,7 @@ wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, cons
     hipError_t e = hipSuccess;
     uint32_t nslab = 1;
     if (fmt == WH_FMT_FP8E4M3_BS4) {
-        GemvPlan pl = whz_gemv_plan(mat.desc.rows, cols, row_begin, row_end, ctx->num_cus); // same block geometry
+        GemvPlan pl = whz_gemv_plan(mat.desc.rows, cols, row_begin, row_end, ctx->num_cus, kThreads);
         nslab = pl.nslab;
         double* part = nullptr;
         if (nslab > 1) {

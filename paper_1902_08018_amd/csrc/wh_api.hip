@@ -307,6 +307,47 @@ wh_status wh_gemv(wh_ctx* ctx, wh_mat m, const float* d_u, float* d_y, uint32_t 
     }
 }
 
+wh_status wh_gemv_batched(wh_ctx* ctx, wh_mat m, const void* d_U, int u_dtype, uint32_t k, uint32_t ldu, float* d_Y,
+                          uint32_t ldy, uint32_t flags, void* stream)
+{
+    WH_GUARD(ctx);
+    if (!d_U || !d_Y || k == 0 || k > kMaxRhs || (u_dtype != WH_U_F32 && u_dtype != WH_U_BF16))
+        return WH_ERR_INVALID;
+    if (flags & ~(WH_ACC_FP64 | WH_ACC_TWOSUM | WH_PAPER_MP))
+        return WH_ERR_INVALID;
+    try {
+        Matrix mat;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            Matrix* p = find_matrix(ctx, m);
+            if (!p)
+                return WH_ERR_NOT_FOUND;
+            mat = *p;
+        }
+        if (mat.desc.fmt != WH_FMT_ZFP_FIXED_RATE)
+            return WH_ERR_FORMAT;
+        if (ldu < mat.desc.cols || ldy < mat.desc.rows)
+            return WH_ERR_SHAPE;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (k == 1 && u_dtype == WH_U_F32 && aligned(d_U, 16)) // one vector: the fused k = 1 kernel
+            return wh_gemv(ctx, m, static_cast<const float*>(d_U), d_Y, 0, mat.desc.rows, flags, stream);
+        if (flags & WH_PAPER_MP)
+            return WH_ERR_INVALID; // Fig. 7 per-product sums exist for one vector only
+        const MrhsPlan pl = whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus);
+        double* part = nullptr;
+        if (pl.nslab > 1) {
+            wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * k * mat.desc.rows);
+            if (s2 != WH_OK)
+                return s2;
+            part = ctx->part;
+        }
+        return device_error(ctx, whz_mrhs(mat.desc.rate, pl, u_dtype == WH_U_BF16, mat.dptr, d_U, ldu, k, d_Y, ldy,
+                                          part, st));
+    } catch (...) {
+        return WH_ERR_INVALID;
+    }
+}
+
 wh_status wh_decode_debug(wh_ctx* ctx, wh_mat m, uint64_t block_begin, uint64_t nblocks, float* d_out, void* stream)
 {
     WH_GUARD(ctx);

@@ -102,89 +102,182 @@ __device__ __forceinline__ void fwd_xform(uint32_t (&v)[16])
 // plane = coefficient s).  Afterwards A[s] is coefficient s: bit p = its bit
 // in plane p.  Both 16x16 halves are transposed at once (the masks repeat in
 // each 16-bit half, and every shifted bit that crosses a half is masked off).
-__device__ __forceinline__ void transpose_planes(uint32_t (&A)[16])
+// One stage: rows i and i + D (i & D == 0) exchange their D-wide column
+// blocks; M selects the low D columns of every 2D-wide group.  Templates keep
+// every index a compile-time constant (no register indexing, no loop).
+template <int D, uint32_t M, int I>
+__device__ __forceinline__ void transpose_pairs(uint32_t (&A)[16])
 {
-#pragma unroll
-    for (int d = 8; d >= 1; d >>= 1) {
-        const uint32_t m = d == 8 ? 0x00FF00FFu : d == 4 ? 0x0F0F0F0Fu : d == 2 ? 0x33333333u : 0x55555555u;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if ((i & d) == 0) {
-                const uint32_t a = A[i], b = A[i + d];
-                A[i] = (a & m) | ((b << d) & ~m);
-                A[i + d] = ((a >> d) & m) | (b & ~m);
-            }
+    if constexpr (I < 16) {
+        if constexpr ((I & D) == 0) {
+            const uint32_t a = A[I], b = A[I + D];
+            A[I] = (a & M) | ((b << D) & ~M);
+            A[I + D] = ((a >> D) & M) | (b & ~M);
         }
+        transpose_pairs<D, M, I + 1>(A);
     }
 }
 
+__device__ __forceinline__ void transpose_planes(uint32_t (&A)[16])
+{
+    transpose_pairs<8, 0x00FF00FFu, 0>(A);
+    transpose_pairs<4, 0x0F0F0F0Fu, 0>(A);
+    transpose_pairs<2, 0x33333333u, 0>(A);
+    transpose_pairs<1, 0x55555555u, 0>(A);
+}
+
 // --------------------------------------------------------------- decoding
-// Decode the block whose words are at lw[0..NW-1] (lw[NW..NW+2] == 0); w0 ==
-// lw[0].  Outputs the 16 integers of the block after the inverse transform
-// (local index 4r + c) and emax.  Returns false for an all-zero block (then
-// iv[] is all 0).  Every bit pattern decodes (the function is total).
-template <int NW>
-__device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, uint32_t w0, int& emax, uint32_t (&iv)[16])
+// Group-test sections are decoded with a lookup table of 8 stream bits at a
+// time.  A section (after the verbatim bits of a plane) is a sequence of
+// tokens: "0" (next coefficient stays insignificant), "11" (it becomes
+// significant, another group follows), "10" (it becomes significant, the
+// plane ends); a group bit 0 at the start ends the plane at once, and when
+// the scan reaches coefficient 15 inside a run its 1 is implied.
+//
+// Table entry for (state, nsig, 8 bits), state 0 = at a group bit, 1 =
+// inside a run:
+//   bits  0..3   stream bits consumed (0..8)
+//   bits  4..7   coefficients passed (nsig advances by this much, 0..9)
+//   bits  8..17  the ones among them (relative to nsig)
+//   bit  18      the section ended
+//   bit  19      state to continue in when it did not end
+//   bit  20      it ended by the implied 1 at coefficient 15
+constexpr int kSecBits = 8;
+constexpr int kSecStates = 2;
+constexpr int kSecN = 17; // nsig 0..16
+constexpr int kSecEntries = kSecStates * kSecN * (1 << kSecBits);
+
+__host__ __device__ constexpr uint32_t section_entry(int state, int nsig, int bits)
+{
+    int used = 0, adv = 0, done = 0, implied = 0, st = state;
+    uint32_t ones = 0;
+    for (;;) {
+        if (st == 0) {
+            if (nsig + adv >= 16) { // every coefficient significant: no group bit
+                done = 1;
+                break;
+            }
+            if (used == kSecBits)
+                break;
+            const int g = (bits >> used) & 1;
+            ++used;
+            if (!g) {
+                done = 1;
+                break;
+            }
+            st = 1;
+        } else {
+            if (nsig + adv == 15) { // coefficient 15: its 1 is implied, not read
+                ones |= 1u << adv;
+                ++adv;
+                done = 1;
+                implied = 1;
+                break;
+            }
+            if (used == kSecBits)
+                break;
+            const int b = (bits >> used) & 1;
+            ++used;
+            if (b) {
+                ones |= 1u << adv;
+                st = 0;
+            }
+            ++adv;
+        }
+    }
+    return (uint32_t)used | (uint32_t)adv << 4 | ones << 8 | (uint32_t)done << 18 | (uint32_t)st << 19 |
+           (uint32_t)implied << 20;
+}
+
+struct SectionTable {
+    uint32_t e[kSecEntries];
+    constexpr SectionTable() : e()
+    {
+        for (int st = 0; st < kSecStates; ++st)
+            for (int n = 0; n < kSecN; ++n)
+                for (int b = 0; b < (1 << kSecBits); ++b)
+                    e[(st * kSecN + n) * (1 << kSecBits) + b] = section_entry(st, n, b);
+    }
+};
+
+// One bit plane of the embedded code (plane P, decoded in lockstep by all
+// lanes of the wave; P is a template argument so A[] is indexed at compile
+// time).  Every step is straight-line code for all lanes: a lane whose budget
+// is spent still reads (zero-padded, in-bounds) LDS but keeps its state.
+//
+// Bits past the end of the block read as zero.  That gives the exact result
+// everywhere except when the bit budget runs out inside a run: there the
+// zero bits walk on to coefficient 15 and set it, where the code sets the
+// coefficient the run had reached at the end of the budget.  The number of
+// zeros read past the end says which one that was, and the bit is moved.
+template <int NW, int P>
+__device__ __forceinline__ void decode_plane(const uint32_t* lw, const uint32_t* tab, uint32_t& pos, uint32_t& nsig,
+                                             uint32_t (&A)[16])
 {
     constexpr uint32_t kMaxBits = 32u * NW;
+    const bool act = pos < kMaxBits;
+    uint32_t q = pos >> 5;
+    const uint32_t lo = funnel(lw[q + 1], lw[q], pos & 31u), hi = funnel(lw[q + 2], lw[q + 1], pos & 31u);
+    // (i) verbatim bits of the significant coefficients
+    uint32_t x = __builtin_amdgcn_ubfe(lo, 0u, nsig);
+    // (ii) group tests, 8 bits per table lookup
+    uint32_t e = tab[(nsig << kSecBits) | (funnel(hi, lo, nsig) & 0xFFu)];
+    e = act ? e : (1u << 18);
+    uint32_t off = act ? nsig + (e & 15u) : 0u;
+    x = act ? x | (((e >> 8) & 0x3FFu) << nsig) : 0u;
+    nsig += (e >> 4) & 15u;
+    bool more = !(e & (1u << 18));
+    while (__any(more)) {
+        const uint32_t at = pos + off;
+        q = at >> 5;
+        const uint32_t bits = funnel(lw[q + 1], lw[q], at & 31u) & 0xFFu;
+        const uint32_t e2 = tab[(((e >> 19) & 1u) * kSecN + nsig) << kSecBits | bits];
+        const uint32_t adv = more ? (e2 >> 4) & 15u : 0u;
+        x |= more ? ((e2 >> 8) & 0x3FFu) << nsig : 0u;
+        off += more ? e2 & 15u : 0u;
+        nsig += adv;
+        e = more ? e2 : e;
+        more = more && !(e2 & (1u << 18));
+    }
+    pos += off;
+    if ((e & (1u << 20)) && pos > kMaxBits) // budget ended inside the run
+        x ^= 0x8000u | (1u << (15u - (pos - kMaxBits)));
+    if constexpr (P >= 16)
+        A[P - 16] |= x << 16;
+    else
+        A[P] |= x;
+}
+
+template <int NW, int P>
+__device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uint32_t* tab, uint32_t& pos,
+                                                   uint32_t& nsig, uint32_t (&A)[16])
+{
+    if constexpr (P >= 0) {
+        if (!__any(pos < 32u * NW))
+            return;
+        decode_plane<NW, P>(lw, tab, pos, nsig, A);
+        decode_planes_from<NW, P - 1>(lw, tab, pos, nsig, A);
+    }
+}
+
+// Decode the block whose words are at lw[0..NW-1] (lw[NW..NW+4] == 0); w0 ==
+// lw[0]; tab = the section table (in LDS).  Outputs the 16 integers of the
+// block after the inverse transform (local index 4r + c) and emax.  Returns
+// false for an all-zero block (then iv[] is all 0).  Every bit pattern
+// decodes (the function is total).
+template <int NW>
+__device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, const uint32_t* tab, uint32_t w0, int& emax,
+                                                  uint32_t (&iv)[16])
+{
     const bool nz = (w0 & 1u) != 0;
     emax = (int)((w0 >> 1) & 0xFFu) - 127;
-    uint32_t left = nz ? kMaxBits - 9u : 0u; // bits of the plane code still to read
-    uint32_t pos = 9u;                        // bit position in the block
-    uint32_t nsig = 0u;                       // coefficients 0..nsig-1 significant
+    uint32_t pos = nz ? 9u : 32u * NW; // next bit to read; decoding stops at 32*NW
+    uint32_t nsig = 0u;                 // coefficients 0..nsig-1 significant
     uint32_t A[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q)
         A[q] = 0u;
-
-#pragma unroll
-    for (int p = 31; p >= 0; --p) {
-        if (!__any(left != 0u))
-            break;
-        if (left != 0u) {
-            // 64-bit window at pos
-            const uint32_t q = pos >> 5, o = pos & 31u;
-            const uint32_t d0 = lw[q], d1 = lw[q + 1], d2 = lw[q + 2];
-            uint32_t lo = funnel(d1, d0, o), hi = funnel(d2, d1, o);
-            // (i) verbatim bits of the significant coefficients
-            const uint32_t m = nsig < left ? nsig : left;
-            uint32_t x = lo & ((1u << m) - 1u);
-            lo = funnel(hi, lo, m);
-            hi >>= m;
-            left -= m;
-            pos += m;
-            // (ii) group tests: each "1" opens a run of zeros that ends at
-            // the next newly significant coefficient
-            while (nsig < 16u && left != 0u) {
-                if ((lo & 1u) == 0u) { // group bit 0: plane done
-                    lo = funnel(hi, lo, 1u);
-                    hi >>= 1;
-                    left -= 1u;
-                    pos += 1u;
-                    break;
-                }
-                const uint32_t run = (uint32_t)__builtin_ctz((lo >> 1) | 0x10000u);
-                const uint32_t room = left - 1u;
-                uint32_t cap = 15u - nsig;
-                cap = cap < room ? cap : room;
-                const uint32_t r = run < cap ? run : cap;
-                // the terminating 1 is read only when the run ends before the
-                // cap; at the cap (position 15, or no bits left) it is implied
-                const uint32_t used = 1u + r + (run < cap ? 1u : 0u);
-                x |= 1u << (nsig + r);
-                nsig += r + 1u;
-                left -= used;
-                pos += used;
-                lo = funnel(hi, lo, used);
-                hi >>= used;
-            }
-            if (p >= 16)
-                A[p - 16] |= x << 16;
-            else
-                A[p] |= x;
-        }
-    }
-
+    decode_planes_from<NW, 31>(lw, tab, pos, nsig, A);
     transpose_planes(A);
     // negabinary -> two's complement, undo the sequency order
 #pragma unroll

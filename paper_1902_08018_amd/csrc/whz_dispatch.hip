@@ -14,13 +14,11 @@ namespace wh {
     hipError_t decode_matrix(const void*, uint32_t, uint32_t, float*, hipStream_t);                                  \
     hipError_t encode(const float*, uint32_t, uint32_t, void*, uint32_t*, hipStream_t);                              \
     hipError_t gemv(const GemvPlan&, AccMode, const void*, const float*, float*, double*, hipStream_t);              \
+    hipError_t mrhs(const MrhsPlan&, bool, const void*, const void*, uint32_t, uint32_t, float*, uint32_t, double*,     \
+                    hipStream_t);                                                                                      \
     }
 WH_FOR_EACH_NW(X)
 #undef X
-
-namespace {
-constexpr int kThreads = 256;
-}
 
 bool whz_rate_supported(uint32_t rate)
 {
@@ -77,9 +75,10 @@ hipError_t whz_encode(uint32_t rate, const float* M, uint32_t rows, uint32_t col
     }
 }
 
-GemvPlan whz_gemv_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus)
+GemvPlan whz_gemv_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t lanes)
 {
     (void)rows;
+    const uint32_t kThreads = lanes;
     GemvPlan pl{};
     pl.nbc = cols / 4;
     pl.bi_begin = row_begin / 4;
@@ -112,6 +111,47 @@ hipError_t whz_gemv(uint32_t rate, const GemvPlan& pl, AccMode mode, const void*
 #define X(k)                                                                                                         \
     case k:                                                                                                          \
         return nw##k::gemv(pl, mode, stream, u, y, part, st);
+        WH_FOR_EACH_NW(X)
+#undef X
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus)
+{
+    (void)rows;
+    MrhsPlan pl{};
+    pl.nbc = cols / 4;
+    pl.bi_begin = row_begin / 4;
+    pl.bi_end = row_end / 4;
+    const uint32_t nbr = pl.bi_end - pl.bi_begin;
+    pl.ntiles = (nbr + kMrhsTileBlockRows - 1) / kMrhsTileBlockRows;
+    const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 4;
+    const uint32_t max_slabs = (pl.nbc + 15) / 16;
+    uint32_t nslab = pl.ntiles ? (uint32_t)((want + pl.ntiles - 1) / pl.ntiles) : 1;
+    if (nslab < 1)
+        nslab = 1;
+    if (nslab > max_slabs)
+        nslab = max_slabs ? max_slabs : 1;
+    uint32_t slab_bc = (pl.nbc + nslab - 1) / nslab;
+    slab_bc = (slab_bc + 15) / 16 * 16;
+    pl.slab_bc = slab_bc ? slab_bc : 16;
+    pl.nslab = (pl.nbc + pl.slab_bc - 1) / pl.slab_bc;
+    if (pl.nslab < 1)
+        pl.nslab = 1;
+    return pl;
+}
+
+hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu,
+                    uint32_t k, float* Y, uint32_t ldy, double* part, hipStream_t st)
+{
+    if (pl.ntiles == 0)
+        return hipSuccess;
+    switch (rate / 2) {
+#define X(kw)                                                                                                        \
+    case kw:                                                                                                         \
+        return nw##kw::mrhs(pl, bf16, stream, U, ldu, k, Y, ldy, part, st);
         WH_FOR_EACH_NW(X)
 #undef X
     default:

@@ -28,8 +28,21 @@ constexpr int kThreads = 256;
 
 template <int NW>
 struct LdsRow {
-    static constexpr int kStride = NW + 3; // odd for even NW: no bank conflicts
+    // NW words + 5 zero words (the decoder reads up to word NW + 3); odd for
+    // even NW, so lane-strided accesses hit distinct banks
+    static constexpr int kStride = NW + 5;
 };
+
+// The section table, built at compile time; copied to LDS by every workgroup.
+__device__ const SectionTable g_section_table{};
+
+template <int THREADS>
+__device__ __forceinline__ void load_section_table(uint32_t* tab)
+{
+    for (int i = threadIdx.x; i < kSecEntries; i += THREADS)
+        tab[i] = g_section_table.e[i];
+    __syncthreads();
+}
 
 // Stage one block (NW words at g) into this lane's LDS row.
 template <int NW>
@@ -58,9 +71,9 @@ __device__ __forceinline__ void stage_block(uint32_t* row, const uint32_t* __res
 template <int NW>
 __device__ __forceinline__ void clear_pad(uint32_t* row)
 {
-    row[NW] = 0u;
-    row[NW + 1] = 0u;
-    row[NW + 2] = 0u;
+#pragma unroll
+    for (int k = NW; k < LdsRow<NW>::kStride; ++k)
+        row[k] = 0u;
 }
 
 // ------------------------------------------------------- decode kernels
@@ -69,15 +82,17 @@ __global__ void __launch_bounds__(kThreads) decode_blocks_kernel(const uint32_t*
                                                                  uint64_t nblocks, float* __restrict__ out)
 {
     __shared__ uint32_t lds[kThreads * LdsRow<NW>::kStride];
+    __shared__ uint32_t tab[kSecEntries];
     uint32_t* row = lds + threadIdx.x * LdsRow<NW>::kStride;
     clear_pad<NW>(row);
+    load_section_table<kThreads>(tab);
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < nblocks; i += stride) {
         uint32_t w[NW];
         stage_block<NW>(row, stream + (b0 + i) * NW, w);
         int emax;
         uint32_t iv[16];
-        decode_block_ints<NW>(row, w[0], emax, iv);
+        decode_block_ints<NW>(row, tab, w[0], emax, iv);
         float4* o = reinterpret_cast<float4*>(out + 16 * i);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -95,15 +110,17 @@ __global__ void __launch_bounds__(kThreads) decode_matrix_kernel(const uint32_t*
                                                                  float* __restrict__ out)
 {
     __shared__ uint32_t lds[kThreads * LdsRow<NW>::kStride];
+    __shared__ uint32_t tab[kSecEntries];
     uint32_t* row = lds + threadIdx.x * LdsRow<NW>::kStride;
     clear_pad<NW>(row);
+    load_section_table<kThreads>(tab);
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < nblocks; b += stride) {
         uint32_t w[NW];
         stage_block<NW>(row, stream + b * NW, w);
         int emax;
         uint32_t iv[16];
-        decode_block_ints<NW>(row, w[0], emax, iv);
+        decode_block_ints<NW>(row, tab, w[0], emax, iv);
         const uint64_t bi = b / nbc, bj = b % nbc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -186,16 +203,20 @@ struct TwoSumAcc {
     }
 };
 
+constexpr int kGemvThreads = (int)kGemvLanes;
+
 template <int NW, int TR, typename Acc>
-__global__ void __launch_bounds__(kThreads) gemv_kernel(const uint32_t* __restrict__ stream,
+__global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __restrict__ stream,
                                                         const float* __restrict__ u, float* __restrict__ y,
                                                         double* __restrict__ part, uint32_t nbc, uint32_t bi_begin,
                                                         uint32_t bi_end, uint32_t slab_bc, uint32_t nslab)
 {
-    __shared__ uint32_t lds[kThreads * LdsRow<NW>::kStride];
-    __shared__ double red[kThreads / 64][TR * 4];
+    __shared__ uint32_t lds[kGemvThreads * LdsRow<NW>::kStride];
+    __shared__ uint32_t tab[kSecEntries];
+    __shared__ double red[kGemvThreads / 64][TR * 4];
     uint32_t* row = lds + threadIdx.x * LdsRow<NW>::kStride;
     clear_pad<NW>(row);
+    load_section_table<kGemvThreads>(tab);
 
     const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
     const uint32_t bi0 = bi_begin + tile * TR;
@@ -210,34 +231,45 @@ __global__ void __launch_bounds__(kThreads) gemv_kernel(const uint32_t* __restri
         for (int r = 0; r < 4; ++r)
             acc[t][r].zero();
 
-    for (uint32_t bj = bc0 + threadIdx.x; bj < bc1; bj += kThreads) {
+    for (uint32_t bj = bc0 + threadIdx.x; bj < bc1; bj += kGemvThreads) {
         const float4 uu = reinterpret_cast<const float4*>(u)[bj];
+        // one copy of the decoder: the tile's block-rows go round a rolled
+        // loop, and the (wave-uniform) row index picks the accumulators
+#pragma unroll 1
+        for (uint32_t t = 0; t < nr; ++t) {
+            uint32_t w[NW];
+            stage_block<NW>(row, stream + ((uint64_t)(bi0 + t) * nbc + bj) * NW, w);
+            int emax;
+            uint32_t iv[16];
+            decode_block_ints<NW>(row, tab, w[0], emax, iv);
+            float pr[4][4];
 #pragma unroll
-        for (int t = 0; t < TR; ++t) {
-            if ((uint32_t)t < nr) {
-                uint32_t w[NW];
-                stage_block<NW>(row, stream + ((uint64_t)(bi0 + t) * nbc + bj) * NW, w);
-                int emax;
-                uint32_t iv[16];
-                decode_block_ints<NW>(row, w[0], emax, iv);
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if constexpr (Acc::kPerProduct) {
-                        // Fig. 7: each FP32 product of the decoded value and
-                        // u is added to the FP64 sum on its own
-                        const int k = emax - 30;
-                        acc[t][r].add(__builtin_ldexpf((float)(int32_t)iv[4 * r], k) * uu.x);
-                        acc[t][r].add(__builtin_ldexpf((float)(int32_t)iv[4 * r + 1], k) * uu.y);
-                        acc[t][r].add(__builtin_ldexpf((float)(int32_t)iv[4 * r + 2], k) * uu.z);
-                        acc[t][r].add(__builtin_ldexpf((float)(int32_t)iv[4 * r + 3], k) * uu.w);
-                    } else {
-                        // FP32 row sum inside the block; the power-of-two
-                        // block scale is applied once to that sum
-                        float p = (float)(int32_t)iv[4 * r] * uu.x;
-                        p = __builtin_fmaf((float)(int32_t)iv[4 * r + 1], uu.y, p);
-                        p = __builtin_fmaf((float)(int32_t)iv[4 * r + 2], uu.z, p);
-                        p = __builtin_fmaf((float)(int32_t)iv[4 * r + 3], uu.w, p);
-                        acc[t][r].add(__builtin_ldexpf(p, emax - 30));
+                for (int c = 0; c < 4; ++c)
+                    pr[r][c] = (float)(int32_t)iv[4 * r + c];
+            const int k = emax - 30;
+#pragma unroll
+            for (int tt = 0; tt < TR; ++tt) {
+                if (tt == (int)t) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if constexpr (Acc::kPerProduct) {
+                            // Fig. 7: each FP32 product of the decoded value
+                            // and u is added to the FP64 sum on its own
+                            acc[tt][r].add(__builtin_ldexpf(pr[r][0], k) * uu.x);
+                            acc[tt][r].add(__builtin_ldexpf(pr[r][1], k) * uu.y);
+                            acc[tt][r].add(__builtin_ldexpf(pr[r][2], k) * uu.z);
+                            acc[tt][r].add(__builtin_ldexpf(pr[r][3], k) * uu.w);
+                        } else {
+                            // FP32 row sum inside the block; the power-of-two
+                            // block scale is applied once to that sum
+                            float p = pr[r][0] * uu.x;
+                            p = __builtin_fmaf(pr[r][1], uu.y, p);
+                            p = __builtin_fmaf(pr[r][2], uu.z, p);
+                            p = __builtin_fmaf(pr[r][3], uu.w, p);
+                            acc[tt][r].add(__builtin_ldexpf(p, k));
+                        }
                     }
                 }
             }
@@ -261,7 +293,7 @@ __global__ void __launch_bounds__(kThreads) gemv_kernel(const uint32_t* __restri
         const int k = threadIdx.x;
         double s = red[0][k];
 #pragma unroll
-        for (int q = 1; q < kThreads / 64; ++q)
+        for (int q = 1; q < kGemvThreads / 64; ++q)
             s += red[q][k];
         const uint32_t out_row = (bi0 - bi_begin) * 4 + k;
         if (nslab == 1)
@@ -269,6 +301,175 @@ __global__ void __launch_bounds__(kThreads) gemv_kernel(const uint32_t* __restri
         else
             part[(uint64_t)slab * ((bi_end - bi_begin) * 4) + out_row] = s;
     }
+}
+
+// ---------------------------------------------------- multi-RHS (MFMA path)
+// Y = M U^T for k right-hand sides (Sec. 4.4 batched).  One workgroup = 4
+// waves = 16 block-rows (64 rows); per step every wave decodes a 4 x 16
+// tile of blocks (16 rows x 64 columns, one block per lane), writes the
+// decoded values to its LDS tile, and contracts the tile against the 64 x k
+// slice of U on the matrix cores:
+//   FP32 U   v_mfma_f32_16x16x4f32: A = decoded FP32 values (exact), 16 MFMAs
+//            per 16 right-hand sides and step
+//   BF16 U   v_mfma_f32_16x16x32_bf16: A = decoded values rounded to BF16,
+//            2 MFMAs per 16 right-hand sides and step
+// Operand layouts (16x16 output tile D[i][j], lane l):
+//   A[i][kk]  lane = i + 16*(kk/g), element kk % g   (g = 1 FP32, 8 BF16)
+//   B[kk][j]  lane = j + 16*(kk/g), element kk % g
+//   D[i][j]   lane = j + 16*(i/4), register i % 4
+// The FP32 MFMA accumulators cover one 64-column step; after every step they
+// are added into FP64 sums, so no FP32 chain is longer than 64 products.
+constexpr int kMrhsWaves = 4;
+constexpr int kMrhsThreads = 64 * kMrhsWaves;
+constexpr int kMrhsBlockRows = 4 * kMrhsWaves; // per workgroup
+constexpr int kATileStride = 64 + 4;           // floats per LDS row of a wave's A tile
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ __bf16 to_bf16_rne(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    const uint16_t h = (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+    return __builtin_bit_cast(__bf16, h);
+}
+
+template <int NW, bool BF16U, int NT>
+__global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __restrict__ stream,
+                                                            const void* __restrict__ Uv, uint32_t ldu, uint32_t k,
+                                                            float* __restrict__ Y, uint32_t ldy,
+                                                            double* __restrict__ part, uint32_t nbc,
+                                                            uint32_t bi_begin, uint32_t bi_end, uint32_t slab_bc,
+                                                            uint32_t nslab)
+{
+    __shared__ uint32_t lds[kMrhsThreads * LdsRow<NW>::kStride];
+    __shared__ uint32_t tab[kSecEntries];
+    __shared__ float atile[kMrhsWaves][16 * kATileStride];
+    uint32_t* row = lds + threadIdx.x * LdsRow<NW>::kStride;
+    clear_pad<NW>(row);
+    load_section_table<kMrhsThreads>(tab);
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
+    const uint32_t bw = bi_begin + tile * kMrhsBlockRows + 4 * wave; // first block-row of this wave
+    const uint32_t bc0 = slab * slab_bc;
+    const uint32_t bc1 = bc0 + slab_bc < nbc ? bc0 + slab_bc : nbc;
+    const uint32_t cols = nbc * 4;
+    const int t = lane >> 4, c = lane & 15; // this lane's block in the wave's 4 x 16 step tile
+    float* at = atile[wave];
+
+    mf32x4 acc[NT];
+    double sum[NT][4];
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            sum[n][j] = 0.0;
+
+    for (uint32_t cb = bc0; cb < bc1; cb += 16) {
+        // ---- decode one block per lane into the wave's A tile (16 x 64)
+        const uint32_t bi = bw + t, bj = cb + c;
+        const bool valid = bi < bi_end && bj < bc1;
+        uint32_t w[NW];
+        if (valid) {
+            stage_block<NW>(row, stream + ((uint64_t)bi * nbc + bj) * NW, w);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+                row[q] = 0u; // decodes as a zero block
+            w[0] = 0u;
+        }
+        int emax;
+        uint32_t iv[16];
+        decode_block_ints<NW>(row, tab, w[0], emax, iv);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+                at[(4 * t + r) * kATileStride + 4 * c + cc] = __builtin_ldexpf((float)(int32_t)iv[4 * r + cc], emax - 30);
+        // the tile is this wave's own: its LDS writes and reads stay in program
+        // order, so no barrier is needed between decode and contraction
+        // ---- contract: 16 rows x 64 columns x (16 * NT) right-hand sides
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+            acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
+        const uint32_t col0 = 4 * cb;
+        if constexpr (!BF16U) {
+            const float* U = static_cast<const float*>(Uv);
+#pragma unroll 4
+            for (int kb = 0; kb < 16; ++kb) {
+                const int kk = 4 * kb + (lane >> 4);
+                const float a = at[(lane & 15) * kATileStride + kk];
+                const uint32_t col = col0 + kk;
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const uint32_t rhs = 16 * n + (lane & 15);
+                    const float b = (rhs < k && col < cols) ? U[(uint64_t)rhs * ldu + col] : 0.0f;
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[n], 0, 0, 0);
+                }
+            }
+        } else {
+            const uint16_t* U = static_cast<const uint16_t*>(Uv);
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int kk0 = 32 * ks + 8 * (lane >> 4);
+                mbf16x8 a;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    a[e] = to_bf16_rne(at[(lane & 15) * kATileStride + kk0 + e]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const uint32_t rhs = 16 * n + (lane & 15);
+                    mbf16x8 b;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const uint32_t col = col0 + kk0 + e;
+                        const uint16_t h = (rhs < k && col < cols) ? U[(uint64_t)rhs * ldu + col] : (uint16_t)0;
+                        b[e] = __builtin_bit_cast(__bf16, h);
+                    }
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[n], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                sum[n][j] += (double)acc[n][j];
+    }
+
+    // ---- D[i][j]: lane holds rows 4*(lane/16) + j, right-hand side lane%16
+    const uint32_t nrows = (bi_end - bi_begin) * 4;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const uint32_t rhs = 16 * n + (lane & 15);
+        if (rhs >= k)
+            continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t r = (bw - bi_begin) * 4 + 4 * (lane >> 4) + j;
+            if (r >= nrows)
+                continue;
+            if (nslab == 1)
+                Y[(uint64_t)rhs * ldy + r] = (float)sum[n][j];
+            else
+                part[((uint64_t)slab * k + rhs) * nrows + r] = sum[n][j];
+        }
+    }
+}
+
+// Slab partials [nslab][k][nrows] -> Y (k x nrows, leading dimension ldy).
+__global__ void __launch_bounds__(kThreads) reduce_slabs_batched_kernel(const double* __restrict__ part,
+                                                                        uint32_t nrows, uint32_t k, uint32_t nslab,
+                                                                        float* __restrict__ Y, uint32_t ldy)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= (uint64_t)nrows * k)
+        return;
+    const uint32_t rhs = (uint32_t)(i / nrows), r = (uint32_t)(i % nrows);
+    double s = 0.0;
+    for (uint32_t q = 0; q < nslab; ++q)
+        s += part[((uint64_t)q * k + rhs) * nrows + r];
+    Y[(uint64_t)rhs * ldy + r] = (float)s;
 }
 
 __global__ void __launch_bounds__(kThreads) reduce_slabs_kernel(const double* __restrict__ part, uint32_t nrows,
@@ -320,7 +521,7 @@ template <int NW, int TR, typename Acc>
 hipError_t launch_gemv_t(const GemvPlan& pl, const uint32_t* s, const float* u, float* y, double* part,
                          hipStream_t st)
 {
-    hipLaunchKernelGGL((gemv_kernel<NW, TR, Acc>), dim3(pl.ntiles * pl.nslab), dim3(kThreads), 0, st, s, u, y, part,
+    hipLaunchKernelGGL((gemv_kernel<NW, TR, Acc>), dim3(pl.ntiles * pl.nslab), dim3(kGemvThreads), 0, st, s, u, y, part,
                        pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab);
     return hipGetLastError();
 }
@@ -336,6 +537,40 @@ hipError_t launch_gemv(const GemvPlan& pl, AccMode mode, const uint32_t* s, cons
         return e;
     const uint32_t nrows = (pl.bi_end - pl.bi_begin) * 4;
     hipLaunchKernelGGL(reduce_slabs_kernel, dim3(grid_for(nrows)), dim3(kThreads), 0, st, part, nrows, pl.nslab, y);
+    return hipGetLastError();
+}
+
+template <int NW, bool BF, int NT>
+hipError_t launch_mrhs_t(const MrhsPlan& pl, const uint32_t* s, const void* U, uint32_t ldu, uint32_t k, float* Y,
+                         uint32_t ldy, double* part, hipStream_t st)
+{
+    hipLaunchKernelGGL((mrhs_kernel<NW, BF, NT>), dim3(pl.ntiles * pl.nslab), dim3(kMrhsThreads), 0, st, s, U, ldu, k,
+                       Y, ldy, part, pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab);
+    return hipGetLastError();
+}
+
+template <int NW>
+hipError_t launch_mrhs(const MrhsPlan& pl, bool bf16, const uint32_t* s, const void* U, uint32_t ldu, uint32_t k,
+                       float* Y, uint32_t ldy, double* part, hipStream_t st)
+{
+    const int nt = (int)((k + 15) / 16);
+    hipError_t e = hipErrorInvalidValue;
+    switch (nt * 2 + (bf16 ? 1 : 0)) {
+    case 2: e = launch_mrhs_t<NW, false, 1>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    case 3: e = launch_mrhs_t<NW, true, 1>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    case 4: e = launch_mrhs_t<NW, false, 2>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    case 5: e = launch_mrhs_t<NW, true, 2>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    case 6: e = launch_mrhs_t<NW, false, 3>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    case 7: e = launch_mrhs_t<NW, true, 3>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    case 8: e = launch_mrhs_t<NW, false, 4>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    case 9: e = launch_mrhs_t<NW, true, 4>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess || pl.nslab == 1)
+        return e;
+    const uint32_t nrows = (pl.bi_end - pl.bi_begin) * 4;
+    hipLaunchKernelGGL(reduce_slabs_batched_kernel, dim3(grid_for((uint64_t)nrows * k)), dim3(kThreads), 0, st, part,
+                       nrows, k, pl.nslab, Y, ldy);
     return hipGetLastError();
 }
 
@@ -373,6 +608,12 @@ hipError_t gemv(const GemvPlan& pl, AccMode mode, const void* stream, const floa
                 hipStream_t st)
 {
     return launch_gemv<WH_NW>(pl, mode, static_cast<const uint32_t*>(stream), u, y, part, st);
+}
+
+hipError_t mrhs(const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu, uint32_t k, float* Y,
+                uint32_t ldy, double* part, hipStream_t st)
+{
+    return launch_mrhs<WH_NW>(pl, bf16, static_cast<const uint32_t*>(stream), U, ldu, k, Y, ldy, part, st);
 }
 
 } // namespace nwN

@@ -153,9 +153,12 @@ def wh_gemv(ctx: int, mat: int, u: torch.Tensor, y: torch.Tensor, row_begin: int
 
 def wh_gemv_batched(ctx: int, mat: int, U: torch.Tensor, Y: torch.Tensor, flags: int = WH_ACC_DEFAULT,
                     stream=None) -> None:
-    """U: (k, ldu>=cols) float32 or bfloat16; Y: (k, ldy>=rows) float32."""
+    """U: (k, ldu >= cols) float32 or bfloat16; Y: (k, ldy >= rows) float32;
+    rows of both contiguous."""
     if U.dim() != 2 or Y.dim() != 2 or U.shape[0] != Y.shape[0]:
         raise ValueError("U and Y must be (k, n) with the same k")
+    if not (U.is_cuda and Y.is_cuda) or Y.dtype != torch.float32:
+        raise TypeError("U and Y must be CUDA tensors; Y float32")
     if U.dtype == torch.float32:
         dt = WH_U_F32
     elif U.dtype == torch.bfloat16:
@@ -164,9 +167,8 @@ def wh_gemv_batched(ctx: int, mat: int, U: torch.Tensor, Y: torch.Tensor, flags:
         raise TypeError("U must be float32 or bfloat16")
     if U.stride(1) != 1 or Y.stride(1) != 1:
         raise ValueError("rows of U and Y must be contiguous")
-    _check(_lib.wh_gemv_batched(ctx, mat, U.data_ptr(), dt, U.shape[0], U.stride(0), _dptr(Y.view(-1) if
-                                Y.is_contiguous() else Y, torch.float32, "Y") if Y.is_contiguous() else Y.data_ptr(),
-                                Y.stride(0), flags, _stream(stream)), "wh_gemv_batched")
+    _check(_lib.wh_gemv_batched(ctx, mat, U.data_ptr(), dt, U.shape[0], U.stride(0), Y.data_ptr(), Y.stride(0),
+                                flags, _stream(stream)), "wh_gemv_batched")
 
 
 def wh_decode_debug(ctx: int, mat: int, block_begin: int, nblocks: int, out: torch.Tensor, stream=None) -> None:
