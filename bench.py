@@ -35,6 +35,11 @@ def parse():
     ap.add_argument("--flags", type=int, default=0, help="wh_gemv flags (0 default, 1 FP64, 2 TwoSum, 4 Fig. 7)")
     ap.add_argument("--extra", type=int, default=1, help="also time rate 16 and the separate path")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--serving", type=int, default=1, help="also run the Poisson serving load")
+    ap.add_argument("--serving-requests", type=int, default=20000)
+    ap.add_argument("--probe", type=int, default=0,
+                    help="counter-pass mode: 3 launches of the timed configuration, then 3 plain 4 GiB device "
+                         "copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE); prints no JSON")
     ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                                            "traffic.json"))
     return ap.parse_args()
@@ -94,6 +99,77 @@ def cpu_baseline(size, rate):
             "gflops": round(nrows * (2 * spec.cols - 1) / sec / 1e9, 4)}
 
 
+def bench_serving(n_measured=20000, warmup_s=1.0, rate_hz=2000.0, deadline_ms=5.0, budget_mb=96, seed=0):
+    """Open-loop Poisson load against three resident rate-8 matrices
+    (16384^2, 32768 x 16384, 65536^2); k ~ U{1..8} dose vectors in pinned
+    host memory; latency measured from the scheduled arrival time."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1902_08018_amd import synth, wh, workload
+    specs = [synth.MatrixSpec(16384, 16384, 128, 32.0), synth.MatrixSpec(32768, 16384, 128, 32.0), synth.LARGE]
+    ctx = wh.wh_create(0, budget_mb << 20)
+    streams, mats = [], []
+    for sp in specs:
+        st = workload.build_stream(ctx, sp, 8)
+        streams.append(st)
+        mats.append(wh.wh_load_compressed(ctx, sp.rows, sp.cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, st))
+    # trace (stream 3): exponential gaps, target matrix, k
+    n_warm = int(warmup_s * rate_hz)
+    n = n_warm + n_measured
+    uu = synth.uniform(3 * n, seed=seed, stream=synth.STREAM_TRACE).astype(np.float64)
+    gaps = -np.log1p(-uu[0::3]) / rate_hz
+    target = np.minimum((uu[1::3] * 3).astype(int), 2)
+    ks = 1 + np.minimum((uu[2::3] * 8).astype(int), 7)
+    arrive = np.cumsum(gaps)
+    # pinned host buffers, a pool per matrix reused round-robin
+    pool = 256
+    Ubuf = [torch.from_numpy(synth.uniform(8 * sp.cols, seed=seed + 1).reshape(8, sp.cols)).pin_memory() for sp in specs]
+    Ybuf = [[torch.empty((8, sp.rows), dtype=torch.float32).pin_memory() for _ in range(pool)] for sp in specs]
+    slot = [0, 0, 0]
+    outstanding = {}
+    lat, miss, bsz, rejected = [], 0, [], 0
+    t0 = time.monotonic_ns() + 50_000_000
+    i = 0
+    done_count = 0
+    while i < n or outstanding:
+        now = time.monotonic_ns()
+        while i < n and t0 + int(arrive[i] * 1e9) <= now:
+            j = int(target[i])
+            k = int(ks[i])
+            Y = Ybuf[j][slot[j] % pool]
+            slot[j] += 1
+            req = wh.wh_request(mat=mats[j], U=Ubuf[j].data_ptr(), u_on_device=0, k=k, Y=Y.data_ptr(), y_on_device=0,
+                                deadline_ns=int(deadline_ms * 1e6), arrival_ns=t0 + int(arrive[i] * 1e9))
+            try:
+                outstanding[wh.wh_submit(ctx, req)] = i
+            except wh.WhError:
+                rejected += 1
+            i += 1
+        for tk in list(outstanding):
+            st, r = wh.wh_poll(ctx, tk)
+            if st == wh.WH_OK:
+                idx = outstanding.pop(tk)
+                done_count += 1
+                if idx >= n_warm:
+                    lat.append((r.t_done_ns - r.t_arrive_ns) * 1e-6)
+                    miss += r.missed
+                    bsz.append(r.batch_size)
+        if i < n:
+            nxt = t0 + int(arrive[i] * 1e9) - time.monotonic_ns()
+            if nxt > 200_000:
+                time.sleep(min(nxt, 1_000_000) * 1e-9 * 0.5)
+    t_total = (time.monotonic_ns() - t0) * 1e-9
+    wh.wh_destroy(ctx)
+    lat = np.array(lat)
+    return {"requests": int(len(lat)), "rate_hz": rate_hz, "deadline_ms": deadline_ms,
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "p999_ms": round(float(np.percentile(lat, 99.9)), 3), "max_ms": round(float(lat.max()), 3),
+            "miss_rate": round(miss / max(1, len(lat)), 4), "throughput_rps": round(done_count / t_total, 1),
+            "mean_batch_requests": round(float(np.mean(bsz)), 2), "rejected": rejected,
+            "hbm_budget_mb": budget_mb, "matrices": [f"{sp.rows}x{sp.cols} rate 8" for sp in specs]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -112,6 +188,19 @@ def main():
     mat = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, stream)
     us = [workload.u_device(spec, synth.STREAM_U, k * cols) for k in range(4)]
     y = torch.empty(rows, dtype=torch.float32, device="cuda")
+    if args.probe:
+        for i in range(3):
+            wh.wh_gemv(ctx, mat, us[i], y, 0, rows, args.flags)
+        torch.cuda.synchronize()
+        a = torch.ones(1 << 30, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# probe done: 3 x wh_gemv rate {rate} {rows}x{cols}, 3 x copy of {a.numel() * 4} bytes",
+              file=sys.stderr, flush=True)
+        wh.wh_destroy(ctx)
+        return
     print("# timing", file=sys.stderr, flush=True)
     wall_ms, ev_ms = time_gemv(ctx, mat, us, y, rows, args.steps, args.warmup, args.flags)
     kern_ms = sum(ev_ms) / len(ev_ms)
@@ -203,6 +292,11 @@ def main():
         wh.wh_unload(ctx, dm)
         wh.wh_unload(ctx, m8)
         del dense, s8
+
+    if args.serving:
+        print("# serving loop", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out.setdefault("extra", {})["serving"] = bench_serving(n_measured=args.serving_requests)
 
     if args.cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)

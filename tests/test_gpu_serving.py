@@ -1,0 +1,146 @@
+"""GPU tests of the serving loop (wh_submit / wh_poll).
+
+  alone vs mix   a request's result is the same (relative L2 2e-6) whether it
+                 runs by itself or batched with a stream of other requests
+                 against several matrices, and within 1e-6 of the FP64 oracle
+  admission      a request that cannot fit the HBM budget (or k > 64) is
+                 rejected at submit with WH_ERR_BUDGET
+  deadline       a late result is still delivered and flagged missed
+  tickets        unknown tickets give WH_ERR_NOT_FOUND; a ticket retires
+                 after its result is read
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1902_08018_amd import synth, wh
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [synth.MatrixSpec(1024, 1024, 32, 8.0, seed=21), synth.MatrixSpec(2048, 1024, 32, 8.0, seed=22),
+         synth.MatrixSpec(512, 2048, 32, 8.0, seed=23)]
+
+
+def wait(ctx, tickets, timeout=30.0):
+    res = {}
+    t_end = time.monotonic() + timeout
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t in res:
+                continue
+            st, r = wh.wh_poll(ctx, t)
+            if st == wh.WH_OK:
+                res[t] = (r.status, r.t_arrive_ns, r.t_start_ns, r.t_done_ns, r.missed, r.batch_size)
+        assert time.monotonic() < t_end, "requests did not complete"
+        time.sleep(0.0002)
+    return res
+
+
+def make_request(mat, U, Y, deadline_ns=5_000_000):
+    return wh.wh_request(mat=mat, U=U.data_ptr(), u_on_device=int(U.is_cuda), k=U.shape[0], Y=Y.data_ptr(),
+                         y_on_device=int(Y.is_cuda), deadline_ns=deadline_ns, arrival_ns=0)
+
+
+@pytest.fixture(scope="module")
+def serving():
+    ctx = wh.wh_create(0, 256 << 20)
+    mats, streams, refs = [], [], []
+    for sp in SPECS:
+        M = synth.matrix(sp)
+        s = oracle.encode(M, 8)
+        d = torch.from_numpy(s).cuda()
+        streams.append(d)
+        mats.append(wh.wh_load_compressed(ctx, sp.rows, sp.cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, d))
+        refs.append(oracle.decode(s, sp.rows, sp.cols, 8).astype(np.float64))
+    yield ctx, mats, refs
+    wh.wh_destroy(ctx)
+
+
+def test_alone_and_in_the_mix(serving):
+    ctx, mats, refs = serving
+    rng = np.random.default_rng(7)
+    # the probe request: matrix 1, k = 3, host (pinned) buffers
+    Up = torch.from_numpy(synth.uniform(3 * SPECS[1].cols, seed=99).reshape(3, -1)).pin_memory()
+    Y_alone = torch.zeros((3, SPECS[1].rows), dtype=torch.float32).pin_memory()
+    t = wh.wh_submit(ctx, make_request(mats[1], Up, Y_alone))
+    wait(ctx, [t])
+    ref = Up.numpy().astype(np.float64) @ refs[1].T
+    err_alone = np.linalg.norm(Y_alone.numpy() - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err_alone.max() <= 1e-6
+    # the same request inside a burst of 60 others (host and device buffers)
+    keep, tickets, checks = [], [], []
+    for i in range(61):
+        if i == 30:
+            Y_mix = torch.zeros_like(Y_alone).pin_memory()
+            tickets.append(wh.wh_submit(ctx, make_request(mats[1], Up, Y_mix)))
+            continue
+        j = int(rng.integers(0, 3))
+        k = int(rng.integers(1, 9))
+        on_dev = bool(rng.integers(0, 2))
+        U = torch.from_numpy(synth.uniform(k * SPECS[j].cols, seed=1000 + i).reshape(k, -1))
+        Y = torch.zeros((k, SPECS[j].rows), dtype=torch.float32)
+        if on_dev:
+            U, Y = U.cuda(), Y.cuda()
+        else:
+            U, Y = U.pin_memory(), Y.pin_memory()
+        keep.append((U, Y))
+        tickets.append(wh.wh_submit(ctx, make_request(mats[j], U, Y)))
+        checks.append((j, U, Y))
+    res = wait(ctx, tickets)
+    assert all(r[0] == wh.WH_OK for r in res.values())
+    assert max(r[5] for r in res.values()) > 1, "no batching happened"
+    torch.cuda.synchronize()
+    rel = np.linalg.norm(Y_mix.numpy() - Y_alone.numpy(), axis=1) / np.linalg.norm(Y_alone.numpy(), axis=1)
+    print(f"alone vs mix: worst rel-L2 {rel.max():.3e}")
+    assert rel.max() <= 2e-6
+    for j, U, Y in checks:
+        r = U.cpu().numpy().astype(np.float64) @ refs[j].T
+        e = np.linalg.norm(Y.cpu().numpy() - r, axis=1) / np.linalg.norm(r, axis=1)
+        assert e.max() <= 1e-6
+
+
+def test_deadline_flag_and_ticket_retire(serving):
+    ctx, mats, _ = serving
+    U = torch.rand((1, SPECS[0].cols), device="cuda")
+    Y = torch.zeros((1, SPECS[0].rows), device="cuda")
+    t = wh.wh_submit(ctx, make_request(mats[0], U, Y, deadline_ns=1))
+    res = wait(ctx, [t])[t]
+    assert res[0] == wh.WH_OK and res[4] == 1           # late, but delivered
+    assert res[1] <= res[2] <= res[3]
+    assert torch.count_nonzero(Y) > 0
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_poll(ctx, t)                               # retired
+    assert ei.value.status == wh.WH_ERR_NOT_FOUND
+
+
+def test_admission_rejects_what_cannot_fit():
+    ctx = wh.wh_create(0, 1 << 20)  # 1 MiB: less than one 64-vector slot of a 1024^2 matrix
+    try:
+        M = synth.matrix(SPECS[0])
+        d = torch.from_numpy(oracle.encode(M, 8)).cuda()
+        mat = wh.wh_load_compressed(ctx, 1024, 1024, wh.WH_FMT_ZFP_FIXED_RATE, 8, d)
+        U = torch.rand((1, 1024), device="cuda")
+        Y = torch.zeros((1, 1024), device="cuda")
+        with pytest.raises(wh.WhError) as ei:
+            wh.wh_submit(ctx, make_request(mat, U, Y))
+        assert ei.value.status == wh.WH_ERR_BUDGET
+    finally:
+        wh.wh_destroy(ctx)
+
+
+def test_k_limit_and_unknown(serving):
+    ctx, mats, _ = serving
+    U = torch.rand((65, SPECS[0].cols), device="cuda")
+    Y = torch.zeros((65, SPECS[0].rows), device="cuda")
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_submit(ctx, make_request(mats[0], U, Y))
+    assert ei.value.status == wh.WH_ERR_BUDGET
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_submit(ctx, make_request(12345, U[:1], Y[:1]))
+    assert ei.value.status == wh.WH_ERR_NOT_FOUND
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_poll(ctx, 987654321)
+    assert ei.value.status == wh.WH_ERR_NOT_FOUND
