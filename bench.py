@@ -45,6 +45,17 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash() -> str:
+    """Hash of the fused kernel's source (decoder header + kernels)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1902_08018_amd", "csrc")
+    for name in ("whz_device.hpp", "whz_kernels.hip"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def time_gemv(ctx, mat, us, y, rows, steps, warmup, flags):
     """Event-timed wh_gemv launches on torch's current stream (the stream the
     library launches on).  Returns (wall ms/step, per-launch event ms list)."""
@@ -63,6 +74,73 @@ def time_gemv(ctx, mat, us, y, rows, steps, warmup, flags):
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
     return wall_ms, [a.elapsed_time(b) for a, b in ev]
+
+
+def time_call(fn, steps, warmup):
+    """Mean event-timed ms of fn() on torch's current stream (the stream the
+    library launches on when none is given)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        fn(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_precision(ctx, spec, us, y, steps):
+    """Dense storage formats of the same FP32 matrix (no compression): FP32,
+    FP16, BF16 and FP8 e4m3 with one FP32 scale per 4x4 block."""
+    import torch
+    from paper_1902_08018_amd import wh, workload
+    rows, cols = spec.rows, spec.cols
+    dense = workload.build_dense(spec)
+    res = {}
+    for name, fmt in (("f32", wh.WH_FMT_F32), ("f16", wh.WH_FMT_F16), ("bf16", wh.WH_FMT_BF16),
+                      ("fp8e4m3_bs4", wh.WH_FMT_FP8E4M3_BS4)):
+        nbytes = wh.wh_storage_bytes(rows, cols, fmt)
+        if fmt == wh.WH_FMT_F32:
+            store = dense
+        else:
+            store = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            wh.wh_quantize(ctx, dense, fmt, store)
+        m = wh.wh_load_compressed(ctx, rows, cols, fmt, 0, store)
+        ms = time_call(lambda i: wh.wh_gemv(ctx, m, us[i % len(us)], y, 0, rows), steps, 2)
+        alg = nbytes + 4 * cols + 4 * rows
+        res[name] = {"ms": round(ms, 4), "storage_gb": round(nbytes / 1e9, 3),
+                     "hbm_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "effective_gbs": round(4.0 * rows * cols / (ms * 1e-3) / 1e9, 1)}
+        wh.wh_unload(ctx, m)
+        if fmt != wh.WH_FMT_F32:
+            del store
+    del dense
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_multi_rhs(ctx, mat, spec, rate, stream_bytes, steps):
+    """k right-hand sides against the resident rate-`rate` stream (decode ->
+    LDS -> matrix cores), FP32 and BF16 vectors."""
+    import torch
+    from paper_1902_08018_amd import synth, wh
+    rows, cols = spec.rows, spec.cols
+    res = {}
+    for k in (4, 16, 64):
+        U32 = torch.from_numpy(synth.u_batch(spec, k)).cuda()
+        Y = torch.empty((k, rows), dtype=torch.float32, device="cuda")
+        for name, U in (("f32", U32), ("bf16", U32.to(torch.bfloat16))):
+            ms = time_call(lambda i: wh.wh_gemv_batched(ctx, mat, U, Y), steps, 2)
+            alg = stream_bytes + U.numel() * U.element_size() + Y.numel() * 4
+            res[f"k{k}_{name}"] = {"ms": round(ms, 4), "gflops": round(k * rows * (2 * cols - 1) / (ms * 1e-3) / 1e9, 1),
+                                   "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                   "ms_per_rhs": round(ms / k, 4)}
+    return res
 
 
 def cpu_baseline(size, rate):
@@ -99,7 +177,7 @@ def cpu_baseline(size, rate):
             "gflops": round(nrows * (2 * spec.cols - 1) / sec / 1e9, 4)}
 
 
-def bench_serving(n_measured=20000, warmup_s=1.0, rate_hz=2000.0, deadline_ms=5.0, budget_mb=96, seed=0):
+def bench_serving(n_measured=20000, warmup_s=1.0, rate_hz=2000.0, deadline_ms=5.0, budget_mb=160, seed=0):
     """Open-loop Poisson load against three resident rate-8 matrices
     (16384^2, 32768 x 16384, 65536^2); k ~ U{1..8} dose vectors in pinned
     host memory; latency measured from the scheduled arrival time."""
@@ -209,12 +287,14 @@ def main():
     eff_gbs = 4.0 * rows * cols / (wall_ms * 1e-3) / 1e9
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     flop = rows * (2 * cols - 1)
+    # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes,
+    # valid only for the kernel source they were taken on
     traffic = None
     try:
         with open(args.traffic_json) as f:
             tj = json.load(f).get(f"whz_gemv_rate{rate}_{rows}x{cols}")
-            if tj:
-                traffic = tj.get("bytes_per_launch")
+        if tj and tj.get("kernel_source_sha256_16") == kernel_source_hash():
+            traffic = tj.get("bytes_per_launch")
     except (OSError, ValueError):
         pass
     out = {
@@ -238,6 +318,7 @@ def main():
         "gflops": round(flop / (wall_ms * 1e-3) / 1e9, 2),
         "compressed_gbs": round(stream_bytes / (kern_ms * 1e-3) / 1e9, 2),
         "kernel_ms": round(kern_ms, 4),
+        "kernel_ms_p10_p50_p90": [round(float(x), 4) for x in __import__("numpy").percentile(ev_ms, [10, 50, 90])],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
     }
@@ -288,10 +369,25 @@ def main():
                                    "effective_gbs": round(4.0 * rows * cols / ((td + tg) * 1e-3) / 1e9, 2),
                                    "dense_gemv_hbm_frac": round((4.0 * rows * cols + 8 * cols) / (tg * 1e-3) / 1e9
                                                                 / HBM_PEAK_GBS, 4)}
+        # one GPU's share of an 8-way row split (the sharded layout needs no
+        # exchange: each GPU owns 8192 rows of the stream and of y)
+        print("# row shard", file=sys.stderr, flush=True)
+        shard = {}
+        for r0 in (0, rows - rows // 8):
+            ms = time_call(lambda i: wh.wh_gemv(ctx, m8, us[i % 4], y[: rows // 8], r0, r0 + rows // 8),
+                           max(5, args.steps // 2), 2)
+            shard[f"rows_{r0}_{r0 + rows // 8}"] = {"ms": round(ms, 4),
+                                                   "effective_gbs": round(4.0 * rows // 8 * cols / (ms * 1e-3) / 1e9, 1)}
+        extra["row_shard_1_of_8_rate8"] = shard
+        print("# multi-RHS", file=sys.stderr, flush=True)
+        extra["multi_rhs_rate8"] = bench_multi_rhs(ctx, m8, spec, rate, s8.numel(), max(3, args.steps // 4))
         out["extra"] = extra
         wh.wh_unload(ctx, dm)
         wh.wh_unload(ctx, m8)
         del dense, s8
+        torch.cuda.empty_cache()
+        print("# dense precision sweep", file=sys.stderr, flush=True)
+        extra["dense_precision"] = bench_precision(ctx, spec, us, y, max(5, args.steps // 2))
 
     if args.serving:
         print("# serving loop", file=sys.stderr, flush=True)

@@ -177,8 +177,9 @@ typedef struct {
 
 /* Enqueue a request; returns a ticket.  Thread-safe, never blocks on the GPU.
  * The first request for a matrix sets up its serving state: device slots of
- * 64 right-hand sides each (two if the context's HBM budget allows, one
- * otherwise) and one captured hipGraph per k-bucket and slot.  Rejected at
+ * 64 right-hand sides each (U, Y and FP64 slab partials, all charged to the
+ * context's HBM budget; two slots if the budget allows, one otherwise) and
+ * one captured hipGraph per k-bucket and slot.  Rejected at
  * once with WH_ERR_BUDGET if not even one slot of that matrix fits the
  * budget, or if k > 64.  U and Y must stay valid until wh_poll reports the
  * request done.  zfp matrices only. */

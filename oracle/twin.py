@@ -188,8 +188,9 @@ def decode_block(bits: list[int], rate: int) -> np.ndarray:
         coeffs[order[s]] = from_negabinary(nega[s])
     ints = inverse_transform(coeffs)
     out = np.empty(16, dtype=np.float32)
-    for v in range(16):
-        out[v] = np.float32(float(np.float32(ints[v])) * 2.0 ** (emax - 30))
+    with np.errstate(over="ignore"):  # arbitrary bits may overflow to +-Inf, as IEEE rounding says
+        for v in range(16):
+            out[v] = np.float32(float(np.float32(ints[v])) * 2.0 ** (emax - 30))
     return out
 
 

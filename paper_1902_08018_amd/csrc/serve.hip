@@ -7,8 +7,9 @@
 // different sizes, share one GPU:
 //
 //   submit      any thread; the request is validated, stamped and queued
-//   admission   each matrix gets a fixed number of device slots carved out of
-//               the context's HBM budget (two if the budget allows: one batch
+//   admission   each matrix gets a fixed number of device slots (U, Y and the
+//               FP64 slab partials of one batch) carved out of the context's
+//               HBM budget (two if the budget allows: one batch
 //               runs while the next is staged); a batch waits for a free slot;
 //               a request that can never fit is rejected at submit
 //   batching    continuous: whenever a slot of a matrix is free, all queued
@@ -107,7 +108,26 @@ struct Server {
 
 namespace {
 
-size_t slot_bytes(const Matrix& m) { return (size_t)kMaxRhs * ((size_t)m.desc.cols + m.desc.rows) * sizeof(float); }
+// Device memory of one batch slot: U and Y for kMaxRhs vectors, and the FP64
+// slab partials the k = 1 or multi-RHS plan needs (none when a plan has one
+// slab).  This is what a slot charges against the context's HBM budget.
+size_t slot_partials(const Matrix& m, int num_cus)
+{
+    const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, num_cus);
+    const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, num_cus);
+    size_t n = 0;
+    if (gp.nslab > 1)
+        n = std::max(n, (size_t)gp.nslab * m.desc.rows);
+    if (mp.nslab > 1)
+        n = std::max(n, (size_t)mp.nslab * kMaxRhs * m.desc.rows);
+    return n;
+}
+
+size_t slot_bytes(const Matrix& m, int num_cus)
+{
+    return (size_t)kMaxRhs * ((size_t)m.desc.cols + m.desc.rows) * sizeof(float) +
+           slot_partials(m, num_cus) * sizeof(double);
+}
 
 // Capture one graph per k-bucket for a slot: a single fused launch.
 wh_status build_slot(Server* sv, MatServe& ms, Slot& sl)
@@ -121,11 +141,7 @@ wh_status build_slot(Server* sv, MatServe& ms, Slot& sl)
         return WH_ERR_DEVICE;
     const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, sv->ctx->num_cus);
     const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, sv->ctx->num_cus);
-    size_t part_n = 0;
-    if (gp.nslab > 1)
-        part_n = std::max(part_n, (size_t)gp.nslab * m.desc.rows);
-    if (mp.nslab > 1)
-        part_n = std::max(part_n, (size_t)mp.nslab * kMaxRhs * m.desc.rows);
+    const size_t part_n = slot_partials(m, sv->ctx->num_cus);
     if (part_n && hipMalloc(&sl.part, part_n * sizeof(double)) != hipSuccess)
         return WH_ERR_NOMEM;
     if (hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess)
@@ -173,7 +189,7 @@ MatServe* serve_matrix(Server* sv, wh_mat mat, wh_status& st)
     }
     MatServe& ms = sv->mats[mat];
     ms.m = m;
-    const size_t per = slot_bytes(m);
+    const size_t per = slot_bytes(m, sv->ctx->num_cus);
     int nslots = 0;
     while (nslots < kMaxSlotsPerMatrix && sv->arena_used + per <= sv->ctx->budget) {
         sv->arena_used += per;

@@ -118,9 +118,23 @@ __device__ __forceinline__ void transpose_pairs(uint32_t (&A)[16])
     }
 }
 
+// The first stage (8-wide blocks) moves whole bytes: each output register
+// takes two bytes from each input, one byte permute per register.
+template <int I>
+__device__ __forceinline__ void transpose_bytes(uint32_t (&A)[16])
+{
+    if constexpr (I < 8) {
+        const uint32_t a = A[I], b = A[I + 8];
+        // selector bytes index (a: 0..3, b: 4..7), low output byte first
+        A[I] = __builtin_amdgcn_perm(b, a, 0x06020400u);     // a.b0 b.b0 a.b2 b.b2
+        A[I + 8] = __builtin_amdgcn_perm(b, a, 0x07030501u); // a.b1 b.b1 a.b3 b.b3
+        transpose_bytes<I + 1>(A);
+    }
+}
+
 __device__ __forceinline__ void transpose_planes(uint32_t (&A)[16])
 {
-    transpose_pairs<8, 0x00FF00FFu, 0>(A);
+    transpose_bytes<0>(A);
     transpose_pairs<4, 0x0F0F0F0Fu, 0>(A);
     transpose_pairs<2, 0x33333333u, 0>(A);
     transpose_pairs<1, 0x55555555u, 0>(A);
@@ -134,18 +148,26 @@ __device__ __forceinline__ void transpose_planes(uint32_t (&A)[16])
 // plane ends); a group bit 0 at the start ends the plane at once, and when
 // the scan reaches coefficient 15 inside a run its 1 is implied.
 //
-// Table entry for (state, nsig, 8 bits), state 0 = at a group bit, 1 =
-// inside a run:
+// Table entry for (nsig, state, 8 bits), state 0 = at a group bit, 1 =
+// inside a run; index (nsig << 9) | (state << 8) | bits:
 //   bits  0..3   stream bits consumed (0..8)
 //   bits  4..7   coefficients passed (nsig advances by this much, 0..9)
-//   bits  8..17  the ones among them (relative to nsig)
-//   bit  18      the section ended
-//   bit  19      state to continue in when it did not end
-//   bit  20      it ended by the implied 1 at coefficient 15
+//   bit   8      state to continue in when the section did not end
+//   bit  10      it ended at coefficient 15 inside a run (whose 1 is implied,
+//                not read; the entry leaves that coefficient out of its ones)
+//   bit  15      the section ended (above every index bit, so that adding it
+//                to the next index lands past the table)
+//   bits 16..31  coefficients that became significant, at their absolute
+//                positions (the table is indexed by nsig), so an entry ORs
+//                straight into the plane word in the high half
+// One more entry, kSecDone, is "ended, nothing consumed": a lane whose
+// section has ended reads it, so every step runs unpredicated.
 constexpr int kSecBits = 8;
-constexpr int kSecStates = 2;
 constexpr int kSecN = 17; // nsig 0..16
-constexpr int kSecEntries = kSecStates * kSecN * (1 << kSecBits);
+constexpr int kSecDone = kSecN * 2 * (1 << kSecBits);
+constexpr int kSecEntries = kSecDone + 1;
+constexpr uint32_t kEntState = 1u << 8, kEntImplied = 1u << 10, kEntDone = 1u << 15;
+static_assert(kSecDone <= (int)kEntDone, "the done flag must lift an index past the table");
 
 __host__ __device__ constexpr uint32_t section_entry(int state, int nsig, int bits)
 {
@@ -168,7 +190,6 @@ __host__ __device__ constexpr uint32_t section_entry(int state, int nsig, int bi
             st = 1;
         } else {
             if (nsig + adv == 15) { // coefficient 15: its 1 is implied, not read
-                ones |= 1u << adv;
                 ++adv;
                 done = 1;
                 implied = 1;
@@ -179,93 +200,122 @@ __host__ __device__ constexpr uint32_t section_entry(int state, int nsig, int bi
             const int b = (bits >> used) & 1;
             ++used;
             if (b) {
-                ones |= 1u << adv;
+                ones |= 1u << (nsig + adv);
                 st = 0;
             }
             ++adv;
         }
     }
-    return (uint32_t)used | (uint32_t)adv << 4 | ones << 8 | (uint32_t)done << 18 | (uint32_t)st << 19 |
-           (uint32_t)implied << 20;
+    return (uint32_t)used | (uint32_t)adv << 4 | (done ? 0u : (uint32_t)st << 8) | (uint32_t)done << 15 |
+           (uint32_t)implied << 10 | ones << 16;
 }
 
 struct SectionTable {
     uint32_t e[kSecEntries];
     constexpr SectionTable() : e()
     {
-        for (int st = 0; st < kSecStates; ++st)
-            for (int n = 0; n < kSecN; ++n)
+        for (int n = 0; n < kSecN; ++n)
+            for (int st = 0; st < 2; ++st)
                 for (int b = 0; b < (1 << kSecBits); ++b)
-                    e[(st * kSecN + n) * (1 << kSecBits) + b] = section_entry(st, n, b);
+                    e[(n << 9) | (st << 8) | b] = section_entry(st, n, b);
+        e[kSecDone] = kEntDone;
     }
 };
 
+// A[q] starts as plane q | plane q+16 << 16 with every odd plane
+// complemented: the transpose then yields n ^ 0xAAAAAAAA for each negabinary
+// coefficient n, the first half of the conversion to two's complement.
+__host__ __device__ constexpr uint32_t kOddPlanes(int q) { return (q & 1) ? 0xFFFFFFFFu : 0u; }
+
 // One bit plane of the embedded code (plane P, decoded in lockstep by all
 // lanes of the wave; P is a template argument so A[] is indexed at compile
-// time).  Every step is straight-line code for all lanes: a lane whose budget
-// is spent still reads (zero-padded, in-bounds) LDS but keeps its state.
+// time).  Every step is straight-line code for all lanes.  A lane whose budget
+// is spent keeps stepping over zero bits: a zero group bit ends each section
+// at once, so its plane words stay zero and its significance count is
+// unchanged.
 //
 // Bits past the end of the block read as zero.  That gives the exact result
 // everywhere except when the bit budget runs out inside a run: there the
-// zero bits walk on to coefficient 15 and set it, where the code sets the
-// coefficient the run had reached at the end of the budget.  The number of
-// zeros read past the end says which one that was, and the bit is moved.
-template <int NW, int P>
+// zero bits walk on to coefficient 15, where the code instead sets the
+// coefficient the run had reached when the budget ended.  The number of
+// zeros read past the end says which one that was.
+template <int NW, int STRIDE, int P>
 __device__ __forceinline__ void decode_plane(const uint32_t* lw, const uint32_t* tab, uint32_t& pos, uint32_t& nsig,
                                              uint32_t (&A)[16])
 {
     constexpr uint32_t kMaxBits = 32u * NW;
-    const bool act = pos < kMaxBits;
     uint32_t q = pos >> 5;
-    const uint32_t lo = funnel(lw[q + 1], lw[q], pos & 31u), hi = funnel(lw[q + 2], lw[q + 1], pos & 31u);
+    // 32 bits from pos: the verbatim bits (nsig <= 16) and the first 8
+    // section bits always fit
+    const uint32_t lo = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], pos & 31u);
     // (i) verbatim bits of the significant coefficients
-    uint32_t x = __builtin_amdgcn_ubfe(lo, 0u, nsig);
-    // (ii) group tests, 8 bits per table lookup
-    uint32_t e = tab[(nsig << kSecBits) | (funnel(hi, lo, nsig) & 0xFFu)];
-    e = act ? e : (1u << 18);
-    uint32_t off = act ? nsig + (e & 15u) : 0u;
-    x = act ? x | (((e >> 8) & 0x3FFu) << nsig) : 0u;
+    const uint32_t xv = __builtin_amdgcn_ubfe(lo, 0u, nsig);
+    // (ii) group tests, 8 bits per table lookup; the plane's new ones collect
+    // in the high half of acc (its low half gathers flag bits only)
+    uint32_t e = tab[(nsig << 9) | __builtin_amdgcn_ubfe(lo, nsig, 8u)];
+    uint32_t acc = e;
+    uint32_t at = pos + nsig + (e & 15u); // next unread bit
     nsig += (e >> 4) & 15u;
-    bool more = !(e & (1u << 18));
-    while (__any(more)) {
-        const uint32_t at = pos + off;
+    while (__any(!(e & kEntDone))) {
         q = at >> 5;
-        const uint32_t bits = funnel(lw[q + 1], lw[q], at & 31u) & 0xFFu;
-        const uint32_t e2 = tab[(((e >> 19) & 1u) * kSecN + nsig) << kSecBits | bits];
-        const uint32_t adv = more ? (e2 >> 4) & 15u : 0u;
-        x |= more ? ((e2 >> 8) & 0x3FFu) << nsig : 0u;
-        off += more ? e2 & 15u : 0u;
-        nsig += adv;
-        e = more ? e2 : e;
-        more = more && !(e2 & (1u << 18));
+        const uint32_t bits = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], at & 31u);
+        uint32_t idx = (nsig << 9) + (e & (kEntState | kEntDone)); // ended: >= kSecDone
+        idx |= bits & 0xFFu;
+        e = tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
+        acc |= e;
+        at += e & 15u;
+        nsig += (e >> 4) & 15u;
     }
-    pos += off;
-    if ((e & (1u << 20)) && pos > kMaxBits) // budget ended inside the run
-        x ^= 0x8000u | (1u << (15u - (pos - kMaxBits)));
+    // the implied 1 of coefficient 15, moved back to where the run stood when
+    // the budget ended if the run read past the end (at - kMaxBits zeros)
+    const int back = (int)kMaxBits + 21 - (int)at; // 21 - (bits read past the end)
+    const uint32_t sh = (uint32_t)(back < 6 ? 6 : (back > 21 ? 21 : back));
+    acc |= (acc & kEntImplied) << sh;
+    const uint32_t x = xv + (acc >> 16); // disjoint bit ranges
+    // a lane past the end of its block reads only zero bits: its plane word is
+    // zero and its state stays put; keep its position inside the padding
+    pos = at < kMaxBits + 32u ? at : kMaxBits + 32u;
+    // plane words arrive complemented on odd planes (see decode_block_ints)
     if constexpr (P >= 16)
-        A[P - 16] |= x << 16;
+        A[P - 16] = (x << 16) ^ kOddPlanes(P - 16);
     else
-        A[P] |= x;
+        A[P] ^= x;
 }
 
-template <int NW, int P>
+template <int NW, int STRIDE, int P>
 __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uint32_t* tab, uint32_t& pos,
                                                    uint32_t& nsig, uint32_t (&A)[16])
 {
     if constexpr (P >= 0) {
-        if (!__any(pos < 32u * NW))
+        if (!__any(pos < 32u * NW)) {
+            // planes P..0 stay zero: words 0..P-16 were never written
+            if constexpr (P >= 16) {
+#pragma unroll
+                for (int q = 0; q <= P - 16; ++q)
+                    A[q] = kOddPlanes(q);
+            }
             return;
-        decode_plane<NW, P>(lw, tab, pos, nsig, A);
-        decode_planes_from<NW, P - 1>(lw, tab, pos, nsig, A);
+        }
+        decode_plane<NW, STRIDE, P>(lw, tab, pos, nsig, A);
+        decode_planes_from<NW, STRIDE, P - 1>(lw, tab, pos, nsig, A);
     }
 }
 
-// Decode the block whose words are at lw[0..NW-1] (lw[NW..NW+4] == 0); w0 ==
-// lw[0]; tab = the section table (in LDS).  Outputs the 16 integers of the
-// block after the inverse transform (local index 4r + c) and emax.  Returns
-// false for an all-zero block (then iv[] is all 0).  Every bit pattern
-// decodes (the function is total).
+// Words a lane's staged block occupies in LDS: NW words of the block, then
+// zeros, which the decoder reads past the end of the bit budget.  Each read
+// takes words q and q + 1 of a position; a position stays below 32 bits past
+// the end plus one plane (a plane never spans more than 31 bits: nsig
+// verbatim bits and at most 1 + 2 (15 - nsig) section bits, or 16 verbatim
+// bits), so word NW + 2 is the last one read.
 template <int NW>
+constexpr int kStagedWords = NW + 3;
+
+// Decode the block staged at lw[q * STRIDE], q = 0..NW-1 (lw[q * STRIDE] == 0
+// for q = NW..NW+2); w0 == lw[0]; tab = the section table (in LDS).  Outputs
+// the 16 integers of the block after the inverse transform (local index
+// 4r + c) and emax.  Returns false for an all-zero block (then iv[] is all
+// 0).  Every bit pattern decodes (the function is total).
+template <int NW, int STRIDE>
 __device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, const uint32_t* tab, uint32_t w0, int& emax,
                                                   uint32_t (&iv)[16])
 {
@@ -273,16 +323,14 @@ __device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, const uint
     emax = (int)((w0 >> 1) & 0xFFu) - 127;
     uint32_t pos = nz ? 9u : 32u * NW; // next bit to read; decoding stops at 32*NW
     uint32_t nsig = 0u;                 // coefficients 0..nsig-1 significant
-    uint32_t A[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-        A[q] = 0u;
-    decode_planes_from<NW, 31>(lw, tab, pos, nsig, A);
+    uint32_t A[16]; // every word is written by a plane or by the early exit
+    decode_planes_from<NW, STRIDE, 31>(lw, tab, pos, nsig, A);
     transpose_planes(A);
-    // negabinary -> two's complement, undo the sequency order
+    // negabinary -> two's complement (the XOR came with the planes), undo
+    // the sequency order
 #pragma unroll
     for (int s = 0; s < 16; ++s)
-        iv[order_of(s)] = (A[s] ^ kNega) - kNega;
+        iv[order_of(s)] = A[s] - kNega;
     inv_xform(iv);
     return nz;
 }

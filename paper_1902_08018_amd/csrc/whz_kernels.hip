@@ -26,13 +26,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-template <int NW>
-struct LdsRow {
-    // NW words + 5 zero words (the decoder reads up to word NW + 3); odd for
-    // even NW, so lane-strided accesses hit distinct banks
-    static constexpr int kStride = NW + 5;
-};
-
 // The section table, built at compile time; copied to LDS by every workgroup.
 __device__ const SectionTable g_section_table{};
 
@@ -44,9 +37,12 @@ __device__ __forceinline__ void load_section_table(uint32_t* tab)
     __syncthreads();
 }
 
-// Stage one block (NW words at g) into this lane's LDS row.
-template <int NW>
-__device__ __forceinline__ void stage_block(uint32_t* row, const uint32_t* __restrict__ g, uint32_t (&w)[NW])
+// Staged blocks live word-major in LDS: word q of the block of lane l is at
+// lds[q * STRIDE + l] (STRIDE = the workgroup's lanes), so every lane-varying
+// read of a wave touches 64 distinct banks.
+// Stage one block (NW words at g) at lw = lds + lane.
+template <int NW, int STRIDE>
+__device__ __forceinline__ void stage_block(uint32_t* lw, const uint32_t* __restrict__ g, uint32_t (&w)[NW])
 {
     if constexpr (NW % 4 == 0) {
         const u32x4* g4 = reinterpret_cast<const u32x4*>(g);
@@ -65,15 +61,15 @@ __device__ __forceinline__ void stage_block(uint32_t* row, const uint32_t* __res
     }
 #pragma unroll
     for (int k = 0; k < NW; ++k)
-        row[k] = w[k];
+        lw[k * STRIDE] = w[k];
 }
 
-template <int NW>
-__device__ __forceinline__ void clear_pad(uint32_t* row)
+template <int NW, int STRIDE>
+__device__ __forceinline__ void clear_pad(uint32_t* lw)
 {
 #pragma unroll
-    for (int k = NW; k < LdsRow<NW>::kStride; ++k)
-        row[k] = 0u;
+    for (int k = NW; k < kStagedWords<NW>; ++k)
+        lw[k * STRIDE] = 0u;
 }
 
 // ------------------------------------------------------- decode kernels
@@ -81,18 +77,18 @@ template <int NW>
 __global__ void __launch_bounds__(kThreads) decode_blocks_kernel(const uint32_t* __restrict__ stream, uint64_t b0,
                                                                  uint64_t nblocks, float* __restrict__ out)
 {
-    __shared__ uint32_t lds[kThreads * LdsRow<NW>::kStride];
+    __shared__ uint32_t lds[kThreads * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
-    uint32_t* row = lds + threadIdx.x * LdsRow<NW>::kStride;
-    clear_pad<NW>(row);
+    uint32_t* row = lds + threadIdx.x;
+    clear_pad<NW, kThreads>(row);
     load_section_table<kThreads>(tab);
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < nblocks; i += stride) {
         uint32_t w[NW];
-        stage_block<NW>(row, stream + (b0 + i) * NW, w);
+        stage_block<NW, kThreads>(row, stream + (b0 + i) * NW, w);
         int emax;
         uint32_t iv[16];
-        decode_block_ints<NW>(row, tab, w[0], emax, iv);
+        decode_block_ints<NW, kThreads>(row, tab, w[0], emax, iv);
         float4* o = reinterpret_cast<float4*>(out + 16 * i);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -109,18 +105,18 @@ __global__ void __launch_bounds__(kThreads) decode_matrix_kernel(const uint32_t*
                                                                  uint64_t nblocks, uint32_t cols,
                                                                  float* __restrict__ out)
 {
-    __shared__ uint32_t lds[kThreads * LdsRow<NW>::kStride];
+    __shared__ uint32_t lds[kThreads * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
-    uint32_t* row = lds + threadIdx.x * LdsRow<NW>::kStride;
-    clear_pad<NW>(row);
+    uint32_t* row = lds + threadIdx.x;
+    clear_pad<NW, kThreads>(row);
     load_section_table<kThreads>(tab);
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < nblocks; b += stride) {
         uint32_t w[NW];
-        stage_block<NW>(row, stream + b * NW, w);
+        stage_block<NW, kThreads>(row, stream + b * NW, w);
         int emax;
         uint32_t iv[16];
-        decode_block_ints<NW>(row, tab, w[0], emax, iv);
+        decode_block_ints<NW, kThreads>(row, tab, w[0], emax, iv);
         const uint64_t bi = b / nbc, bj = b % nbc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -211,11 +207,11 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
                                                         double* __restrict__ part, uint32_t nbc, uint32_t bi_begin,
                                                         uint32_t bi_end, uint32_t slab_bc, uint32_t nslab)
 {
-    __shared__ uint32_t lds[kGemvThreads * LdsRow<NW>::kStride];
+    __shared__ uint32_t lds[kGemvThreads * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
     __shared__ double red[kGemvThreads / 64][TR * 4];
-    uint32_t* row = lds + threadIdx.x * LdsRow<NW>::kStride;
-    clear_pad<NW>(row);
+    uint32_t* row = lds + threadIdx.x;
+    clear_pad<NW, kGemvThreads>(row);
     load_section_table<kGemvThreads>(tab);
 
     const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
@@ -224,70 +220,59 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
     const uint32_t bc0 = slab * slab_bc;
     const uint32_t bc1 = bc0 + slab_bc < nbc ? bc0 + slab_bc : nbc;
 
-    Acc acc[TR][4];
-#pragma unroll
-    for (int t = 0; t < TR; ++t)
+    // one tile row at a time (rolled loop: one copy of the decoder), so only
+    // that row's four accumulators are live while blocks decode
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float4* u4 = reinterpret_cast<const float4*>(u);
+#pragma unroll 1
+    for (uint32_t t = 0; t < nr; ++t) {
+        Acc acc[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            acc[t][r].zero();
-
-    for (uint32_t bj = bc0 + threadIdx.x; bj < bc1; bj += kGemvThreads) {
-        const float4 uu = reinterpret_cast<const float4*>(u)[bj];
-        // one copy of the decoder: the tile's block-rows go round a rolled
-        // loop, and the (wave-uniform) row index picks the accumulators
-#pragma unroll 1
-        for (uint32_t t = 0; t < nr; ++t) {
+            acc[r].zero();
+        const uint32_t* srow = stream + (uint64_t)(bi0 + t) * nbc * NW;
+        for (uint32_t bj = bc0 + threadIdx.x; bj < bc1; bj += kGemvThreads) {
+            const float4 uu = u4[bj];
             uint32_t w[NW];
-            stage_block<NW>(row, stream + ((uint64_t)(bi0 + t) * nbc + bj) * NW, w);
+            stage_block<NW, kGemvThreads>(row, srow + (uint64_t)bj * NW, w);
             int emax;
             uint32_t iv[16];
-            decode_block_ints<NW>(row, tab, w[0], emax, iv);
-            float pr[4][4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    pr[r][c] = (float)(int32_t)iv[4 * r + c];
+            decode_block_ints<NW, kGemvThreads>(row, tab, w[0], emax, iv);
             const int k = emax - 30;
 #pragma unroll
-            for (int tt = 0; tt < TR; ++tt) {
-                if (tt == (int)t) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        if constexpr (Acc::kPerProduct) {
-                            // Fig. 7: each FP32 product of the decoded value
-                            // and u is added to the FP64 sum on its own
-                            acc[tt][r].add(__builtin_ldexpf(pr[r][0], k) * uu.x);
-                            acc[tt][r].add(__builtin_ldexpf(pr[r][1], k) * uu.y);
-                            acc[tt][r].add(__builtin_ldexpf(pr[r][2], k) * uu.z);
-                            acc[tt][r].add(__builtin_ldexpf(pr[r][3], k) * uu.w);
-                        } else {
-                            // FP32 row sum inside the block; the power-of-two
-                            // block scale is applied once to that sum
-                            float p = pr[r][0] * uu.x;
-                            p = __builtin_fmaf(pr[r][1], uu.y, p);
-                            p = __builtin_fmaf(pr[r][2], uu.z, p);
-                            p = __builtin_fmaf(pr[r][3], uu.w, p);
-                            acc[tt][r].add(__builtin_ldexpf(p, k));
-                        }
-                    }
+            for (int r = 0; r < 4; ++r) {
+                const float p0 = (float)(int32_t)iv[4 * r], p1 = (float)(int32_t)iv[4 * r + 1];
+                const float p2 = (float)(int32_t)iv[4 * r + 2], p3 = (float)(int32_t)iv[4 * r + 3];
+                if constexpr (Acc::kPerProduct) {
+                    // Fig. 7: each FP32 product of the decoded value and u is
+                    // added to the FP64 sum on its own
+                    acc[r].add(__builtin_ldexpf(p0, k) * uu.x);
+                    acc[r].add(__builtin_ldexpf(p1, k) * uu.y);
+                    acc[r].add(__builtin_ldexpf(p2, k) * uu.z);
+                    acc[r].add(__builtin_ldexpf(p3, k) * uu.w);
+                } else {
+                    // FP32 row sum inside the block; the power-of-two block
+                    // scale is applied once to that sum
+                    float p = p0 * uu.x;
+                    p = __builtin_fmaf(p1, uu.y, p);
+                    p = __builtin_fmaf(p2, uu.z, p);
+                    p = __builtin_fmaf(p3, uu.w, p);
+                    acc[r].add(__builtin_ldexpf(p, k));
                 }
             }
         }
-    }
-
-    // reduce across the 64 lanes of each wave, then across the 4 waves
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int t = 0; t < TR; ++t)
+        // reduce the row's sums across the 64 lanes of the wave
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
 #pragma unroll
             for (int mask = 32; mask >= 1; mask >>= 1)
-                acc[t][r].merge_from_lane(mask);
+                acc[r].merge_from_lane(mask);
             if (lane == 0)
-                red[wave][4 * t + r] = acc[t][r].value();
+                red[wave][4 * t + r] = acc[r].value();
         }
+    }
+
+    // then across the waves of the workgroup
     __syncthreads();
     if (threadIdx.x < (uint32_t)(4 * nr)) {
         const int k = threadIdx.x;
@@ -341,11 +326,11 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                                                             uint32_t bi_begin, uint32_t bi_end, uint32_t slab_bc,
                                                             uint32_t nslab)
 {
-    __shared__ uint32_t lds[kMrhsThreads * LdsRow<NW>::kStride];
+    __shared__ uint32_t lds[kMrhsThreads * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
     __shared__ float atile[kMrhsWaves][16 * kATileStride];
-    uint32_t* row = lds + threadIdx.x * LdsRow<NW>::kStride;
-    clear_pad<NW>(row);
+    uint32_t* row = lds + threadIdx.x;
+    clear_pad<NW, kMrhsThreads>(row);
     load_section_table<kMrhsThreads>(tab);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -371,16 +356,16 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
         const bool valid = bi < bi_end && bj < bc1;
         uint32_t w[NW];
         if (valid) {
-            stage_block<NW>(row, stream + ((uint64_t)bi * nbc + bj) * NW, w);
+            stage_block<NW, kMrhsThreads>(row, stream + ((uint64_t)bi * nbc + bj) * NW, w);
         } else {
 #pragma unroll
             for (int q = 0; q < NW; ++q)
-                row[q] = 0u; // decodes as a zero block
+                row[q * kMrhsThreads] = 0u; // decodes as a zero block
             w[0] = 0u;
         }
         int emax;
         uint32_t iv[16];
-        decode_block_ints<NW>(row, tab, w[0], emax, iv);
+        decode_block_ints<NW, kMrhsThreads>(row, tab, w[0], emax, iv);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll

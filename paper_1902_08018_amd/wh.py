@@ -114,8 +114,17 @@ def wh_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
     return h.value
 
 
+# Device buffers lent to the library (WH_DEVICE) stay referenced here until
+# their matrix is unloaded or the context destroyed, so that torch's caching
+# allocator cannot hand the memory to another tensor while the library still
+# reads it.
+_borrowed: dict = {}
+
+
 def wh_destroy(ctx: int) -> None:
     _check(_lib.wh_destroy(ctx), "wh_destroy")
+    for key in [k for k in _borrowed if k[0] == ctx]:
+        del _borrowed[key]
 
 
 def wh_storage_bytes(rows: int, cols: int, fmt: int, rate: int = 0) -> int:
@@ -126,7 +135,8 @@ def wh_storage_bytes(rows: int, cols: int, fmt: int, rate: int = 0) -> int:
 
 
 def wh_load_compressed(ctx: int, rows: int, cols: int, fmt: int, rate: int, data) -> int:
-    """`data`: a CUDA tensor (borrowed; keep it alive) or a host numpy/CPU
+    """`data`: a CUDA tensor (borrowed: the binding keeps a reference until
+    wh_unload / wh_destroy; do not modify it meanwhile) or a host numpy/CPU
     tensor (copied).  Returns the matrix handle."""
     d = wh_matrix_desc(rows, cols, fmt, rate)
     h = _U64()
@@ -138,11 +148,19 @@ def wh_load_compressed(ctx: int, rows: int, cols: int, fmt: int, rate: int, data
         arr = np.ascontiguousarray(arr)
         ptr, nbytes, where = arr.ctypes.data, arr.nbytes, WH_HOST
     _check(_lib.wh_load_compressed(ctx, ctypes.byref(d), ptr, nbytes, where, ctypes.byref(h)), "wh_load_compressed")
+    if where == WH_DEVICE:
+        _borrowed[(ctx, h.value)] = data
     return h.value
 
 
 def wh_unload(ctx: int, mat: int) -> None:
     _check(_lib.wh_unload(ctx, mat), "wh_unload")
+    # wh_unload frees after pending work on the library's side; a borrowed
+    # buffer may still be read by work queued on the caller's streams, so
+    # release it only once the device is idle
+    if (ctx, mat) in _borrowed:
+        torch.cuda.synchronize()
+        del _borrowed[(ctx, mat)]
 
 
 def wh_gemv(ctx: int, mat: int, u: torch.Tensor, y: torch.Tensor, row_begin: int, row_end: int,

@@ -117,7 +117,9 @@ def test_deadline_flag_and_ticket_retire(serving):
 
 
 def test_admission_rejects_what_cannot_fit():
-    ctx = wh.wh_create(0, 1 << 20)  # 1 MiB: less than one 64-vector slot of a 1024^2 matrix
+    # 1 MiB: less than one 64-vector slot of a 1024^2 matrix (512 KiB of U and
+    # Y, plus the FP64 partials of its 16-slab multi-RHS plan, 8 MiB)
+    ctx = wh.wh_create(0, 1 << 20)
     try:
         M = synth.matrix(SPECS[0])
         d = torch.from_numpy(oracle.encode(M, 8)).cuda()
