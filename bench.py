@@ -177,15 +177,23 @@ def cpu_baseline(size, rate):
             "gflops": round(nrows * (2 * spec.cols - 1) / sec / 1e9, 4)}
 
 
-def bench_serving(n_measured=20000, warmup_s=1.0, rate_hz=2000.0, deadline_ms=5.0, budget_mb=160, seed=0):
-    """Open-loop Poisson load against three resident rate-8 matrices
-    (16384^2, 32768 x 16384, 65536^2); k ~ U{1..8} dose vectors in pinned
-    host memory; latency measured from the scheduled arrival time."""
-    import math
+SERVING_SPECS = {
+    "16384x16384": (16384, 16384, 128, 32.0),
+    "32768x16384": (32768, 16384, 128, 32.0),
+    "65536x65536": (65536, 65536, 256, 32.0),
+}
+
+
+def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measured=20000, warmup_s=1.0,
+                  rate_hz=2000.0, deadline_ms=5.0, budget_mb=160, seed=0):
+    """Open-loop Poisson load against resident rate-8 matrices (target
+    uniform over `names`); k ~ U{1..8} dose vectors in pinned host memory;
+    latency measured from the scheduled arrival time."""
     import numpy as np
     import torch
     from paper_1902_08018_amd import synth, wh, workload
-    specs = [synth.MatrixSpec(16384, 16384, 128, 32.0), synth.MatrixSpec(32768, 16384, 128, 32.0), synth.LARGE]
+    specs = [synth.MatrixSpec(*SERVING_SPECS[n]) for n in names]
+    nm = len(specs)
     ctx = wh.wh_create(0, budget_mb << 20)
     streams, mats = [], []
     for sp in specs:
@@ -197,14 +205,14 @@ def bench_serving(n_measured=20000, warmup_s=1.0, rate_hz=2000.0, deadline_ms=5.
     n = n_warm + n_measured
     uu = synth.uniform(3 * n, seed=seed, stream=synth.STREAM_TRACE).astype(np.float64)
     gaps = -np.log1p(-uu[0::3]) / rate_hz
-    target = np.minimum((uu[1::3] * 3).astype(int), 2)
+    target = np.minimum((uu[1::3] * nm).astype(int), nm - 1)
     ks = 1 + np.minimum((uu[2::3] * 8).astype(int), 7)
     arrive = np.cumsum(gaps)
     # pinned host buffers, a pool per matrix reused round-robin
     pool = 256
     Ubuf = [torch.from_numpy(synth.uniform(8 * sp.cols, seed=seed + 1).reshape(8, sp.cols)).pin_memory() for sp in specs]
     Ybuf = [[torch.empty((8, sp.rows), dtype=torch.float32).pin_memory() for _ in range(pool)] for sp in specs]
-    slot = [0, 0, 0]
+    slot = [0] * nm
     outstanding = {}
     lat, miss, bsz, rejected = [], 0, [], 0
     t0 = time.monotonic_ns() + 50_000_000
@@ -393,6 +401,12 @@ def main():
         print("# serving loop", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out.setdefault("extra", {})["serving"] = bench_serving(n_measured=args.serving_requests)
+        # the same arrival process on the two smaller matrices only: one pass
+        # over the 65536^2 matrix takes longer than the deadline by itself
+        print("# serving loop, two smaller matrices", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["extra"]["serving_two_smaller"] = bench_serving(("16384x16384", "32768x16384"),
+                                                            n_measured=args.serving_requests)
 
     if args.cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -110,7 +110,10 @@ wh_status wh_storage_bytes(const wh_matrix_desc *desc, uint64_t *nbytes);
 wh_status wh_load_compressed(wh_ctx *ctx, const wh_matrix_desc *desc, const void *bytes, uint64_t nbytes,
                              int where, wh_mat *out);
 
-/* Forget a matrix (frees library-owned memory after pending work). */
+/* Forget a matrix (frees library-owned memory after pending work).  If the
+ * serving loop holds the matrix, its batches in flight finish first (and
+ * are delivered); its requests not yet started complete with
+ * WH_ERR_NOT_FOUND, and its slots return to the HBM budget. */
 wh_status wh_unload(wh_ctx *ctx, wh_mat m);
 
 /* y[i - row_begin] = sum_j M[i, j] u[j] for rows [row_begin, row_end)
@@ -176,10 +179,10 @@ typedef struct {
 } wh_result;
 
 /* Enqueue a request; returns a ticket.  Thread-safe, never blocks on the GPU.
- * The first request for a matrix sets up its serving state: device slots of
- * 64 right-hand sides each (U, Y and FP64 slab partials, all charged to the
- * context's HBM budget; two slots if the budget allows, one otherwise) and
- * one captured hipGraph per k-bucket and slot.  Rejected at
+ * The first request for a matrix sets up its serving state: one device slot
+ * of 64 right-hand sides (U, Y and FP64 slab partials, charged to the
+ * context's HBM budget) with one captured hipGraph per k-bucket; a second
+ * slot is added later if a batch has to wait and the budget has room.  Rejected at
  * once with WH_ERR_BUDGET if not even one slot of that matrix fits the
  * budget, or if k > 64.  U and Y must stay valid until wh_poll reports the
  * request done.  zfp matrices only. */

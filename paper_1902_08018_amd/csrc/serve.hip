@@ -165,7 +165,43 @@ wh_status build_slot(Server* sv, MatServe& ms, Slot& sl)
     return WH_OK;
 }
 
-// Called with sv->mu held.  Sets up serving state for a matrix on first use.
+void free_slot(Slot& sl)
+{
+    for (int b = 0; b < kNumBuckets; ++b)
+        if (sl.exec[b])
+            (void)hipGraphExecDestroy(sl.exec[b]);
+    if (sl.done_ev)
+        (void)hipEventDestroy(sl.done_ev);
+    if (sl.U)
+        (void)hipFree(sl.U);
+    if (sl.Y)
+        (void)hipFree(sl.Y);
+    if (sl.part)
+        (void)hipFree(sl.part);
+    sl = Slot{};
+}
+
+// Called with sv->mu held.  Adds a slot to a matrix if the budget has room
+// for it; the slot's bytes are charged only when it is built.
+bool add_slot(Server* sv, MatServe& ms)
+{
+    const size_t per = slot_bytes(ms.m, sv->ctx->num_cus);
+    if ((int)ms.slots.size() >= kMaxSlotsPerMatrix || sv->arena_used + per > sv->ctx->budget)
+        return false;
+    Slot sl;
+    if (build_slot(sv, ms, sl) != WH_OK) {
+        free_slot(sl);
+        return false;
+    }
+    sv->arena_used += per;
+    ms.slots.push_back(std::move(sl));
+    return true;
+}
+
+// Called with sv->mu held.  Sets up serving state for a matrix on first use:
+// one slot now; a second one later, when a batch of this matrix has to wait
+// and the budget still has room (so that every matrix in use gets its first
+// slot before any gets a second).
 MatServe* serve_matrix(Server* sv, wh_mat mat, wh_status& st)
 {
     auto it = sv->mats.find(mat);
@@ -187,27 +223,19 @@ MatServe* serve_matrix(Server* sv, wh_mat mat, wh_status& st)
         st = WH_ERR_FORMAT;
         return nullptr;
     }
-    MatServe& ms = sv->mats[mat];
-    ms.m = m;
-    const size_t per = slot_bytes(m, sv->ctx->num_cus);
-    int nslots = 0;
-    while (nslots < kMaxSlotsPerMatrix && sv->arena_used + per <= sv->ctx->budget) {
-        sv->arena_used += per;
-        ++nslots;
-    }
-    if (nslots == 0) {
+    if (slot_bytes(m, sv->ctx->num_cus) + sv->arena_used > sv->ctx->budget) {
         st = WH_ERR_BUDGET; // cannot hold even one batch of this matrix
         return nullptr;
     }
+    MatServe& ms = sv->mats[mat];
+    ms.m = m;
     if (hipStreamCreateWithFlags(&ms.stream, hipStreamNonBlocking) != hipSuccess) {
         st = WH_ERR_DEVICE;
         return nullptr;
     }
-    ms.slots.resize(nslots);
-    for (Slot& sl : ms.slots) {
-        st = build_slot(sv, ms, sl);
-        if (st != WH_OK)
-            return nullptr;
+    if (!add_slot(sv, ms)) {
+        st = WH_ERR_NOMEM;
+        return nullptr;
     }
     ms.usable = true;
     st = WH_OK;
@@ -304,16 +332,28 @@ void worker_main(Server* sv)
         if (sv->sticky == WH_OK) {
             for (auto& mv : sv->mats) {
                 MatServe& ms = mv.second;
+                bool all_busy = true;
                 for (Slot& sl : ms.slots) {
                     if (ms.pending.empty())
                         break;
                     if (sl.busy)
                         continue;
+                    all_busy = false;
                     const wh_status st = launch_batch(sv, ms, sl);
                     if (st != WH_OK) {
                         sv->ctx->failed.store(true);
                         fail_all(sv, st);
                         break;
+                    }
+                    busy_any = true;
+                }
+                // a batch is waiting on a busy matrix: add a slot if the
+                // budget allows, and use it at once
+                if (sv->sticky == WH_OK && all_busy && !ms.pending.empty() && add_slot(sv, ms)) {
+                    const wh_status st = launch_batch(sv, ms, ms.slots.back());
+                    if (st != WH_OK) {
+                        sv->ctx->failed.store(true);
+                        fail_all(sv, st);
                     }
                     busy_any = true;
                 }
@@ -358,24 +398,41 @@ void serve_shutdown(wh_ctx* ctx)
         MatServe& ms = mv.second;
         if (ms.stream)
             (void)hipStreamSynchronize(ms.stream);
-        for (Slot& sl : ms.slots) {
-            for (int b = 0; b < kNumBuckets; ++b)
-                if (sl.exec[b])
-                    (void)hipGraphExecDestroy(sl.exec[b]);
-            if (sl.done_ev)
-                (void)hipEventDestroy(sl.done_ev);
-            if (sl.U)
-                (void)hipFree(sl.U);
-            if (sl.Y)
-                (void)hipFree(sl.Y);
-            if (sl.part)
-                (void)hipFree(sl.part);
-        }
+        for (Slot& sl : ms.slots)
+            free_slot(sl);
         if (ms.stream)
             (void)hipStreamDestroy(ms.stream);
     }
     delete sv;
     ctx->server = nullptr;
+}
+
+void serve_forget(wh_ctx* ctx, wh_mat m)
+{
+    Server* sv = ctx->server;
+    if (!sv)
+        return;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->mats.find(m);
+    if (it == sv->mats.end())
+        return;
+    MatServe& ms = it->second;
+    if (ms.stream)
+        (void)hipStreamSynchronize(ms.stream); // batches in flight finish
+    for (Slot& sl : ms.slots) {
+        for (uint64_t tk : sl.batch) { // finished on the device: deliver
+            Req& r = sv->reqs[tk];
+            r.t_done = now_ns();
+            r.status = WH_OK;
+        }
+        sv->arena_used -= slot_bytes(ms.m, ctx->num_cus);
+        free_slot(sl);
+    }
+    for (uint64_t tk : ms.pending) // never started
+        sv->reqs[tk].status = WH_ERR_NOT_FOUND;
+    if (ms.stream)
+        (void)hipStreamDestroy(ms.stream);
+    sv->mats.erase(it);
 }
 
 } // namespace wh

@@ -251,6 +251,8 @@ wh_status wh_unload(wh_ctx* ctx, wh_mat m)
             mat = it->second;
             ctx->mats.erase(it);
         }
+        // the serving loop's graphs read the matrix: finish and drop them
+        serve_forget(ctx, m);
         if (mat.owned) {
             hipError_t e = hipDeviceSynchronize();
             if (e != hipSuccess)

@@ -32,6 +32,9 @@ wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, cons
                               uint32_t row_begin, uint32_t row_end, hipStream_t st);
 
 void serve_shutdown(wh_ctx* ctx);
+// Drop the serving state of matrix m (after its batches in flight finish;
+// its queued requests complete with WH_ERR_NOT_FOUND).
+void serve_forget(wh_ctx* ctx, wh_mat m);
 
 } // namespace wh
 

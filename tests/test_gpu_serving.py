@@ -146,3 +146,49 @@ def test_k_limit_and_unknown(serving):
     with pytest.raises(wh.WhError) as ei:
         wh.wh_poll(ctx, 987654321)
     assert ei.value.status == wh.WH_ERR_NOT_FOUND
+
+
+def test_unload_while_served():
+    """Unloading a served matrix finishes its batches in flight, fails its
+    queued requests with WH_ERR_NOT_FOUND, frees its slots for others, and
+    later requests for it are unknown."""
+    # 20 MiB: one slot of the 2048 x 1024 matrix (16.75 MiB: U, Y and the FP64
+    # partials of its 16-slab multi-RHS plan), but not that and a slot of the
+    # 512 x 2048 one (8.6 MiB) together
+    ctx = wh.wh_create(0, 20 << 20)
+    try:
+        M = synth.matrix(SPECS[1])
+        d = torch.from_numpy(oracle.encode(M, 8)).cuda()
+        mat = wh.wh_load_compressed(ctx, SPECS[1].rows, SPECS[1].cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, d)
+        U = torch.rand((8, SPECS[1].cols), device="cuda")
+        keep, tickets = [], []
+        for _ in range(40):
+            Y = torch.zeros((8, SPECS[1].rows), device="cuda")
+            keep.append(Y)
+            tickets.append(wh.wh_submit(ctx, make_request(mat, U, Y)))
+        wh.wh_unload(ctx, mat)
+        codes = []
+        for t in tickets:
+            try:
+                st, r = wh.wh_poll(ctx, t)
+                codes.append(st)
+            except wh.WhError as e:
+                codes.append(e.status)
+        assert all(c in (wh.WH_OK, wh.WH_ERR_NOT_FOUND) for c in codes), codes
+        assert wh.WH_PENDING not in codes
+        with pytest.raises(wh.WhError) as ei:
+            wh.wh_submit(ctx, make_request(mat, U[:1], keep[0][:1]))
+        assert ei.value.status == wh.WH_ERR_NOT_FOUND
+        # the budget it held serves the other matrix now
+        M2 = synth.matrix(SPECS[2])
+        d2 = torch.from_numpy(oracle.encode(M2, 8)).cuda()
+        mat2 = wh.wh_load_compressed(ctx, SPECS[2].rows, SPECS[2].cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, d2)
+        U2 = torch.rand((2, SPECS[2].cols), device="cuda")
+        Y2 = torch.zeros((2, SPECS[2].rows), device="cuda")
+        t2 = wh.wh_submit(ctx, make_request(mat2, U2, Y2))
+        assert wait(ctx, [t2])[t2][0] == wh.WH_OK
+        ref = U2.double().cpu().numpy() @ oracle.decode(oracle.encode(M2, 8), SPECS[2].rows, SPECS[2].cols, 8).astype(np.float64).T
+        err = np.linalg.norm(Y2.cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert err <= 1e-6
+    finally:
+        wh.wh_destroy(ctx)
