@@ -38,8 +38,9 @@ def parse():
     ap.add_argument("--serving", type=int, default=1, help="also run the Poisson serving load")
     ap.add_argument("--serving-requests", type=int, default=20000)
     ap.add_argument("--probe", type=int, default=0,
-                    help="counter-pass mode: 3 launches of the timed configuration, then 3 plain 4 GiB device "
-                         "copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE); prints no JSON")
+                    help="counter-pass mode, prints no JSON: 1 = 3 launches of the timed configuration, then 3 "
+                         "plain 4 GiB device copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE); "
+                         "2 = 3 multi-RHS launches (k = 16, FP32 U) on the same matrix")
     ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                                            "traffic.json"))
     return ap.parse_args()
@@ -274,6 +275,15 @@ def main():
     mat = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, stream)
     us = [workload.u_device(spec, synth.STREAM_U, k * cols) for k in range(4)]
     y = torch.empty(rows, dtype=torch.float32, device="cuda")
+    if args.probe == 2:
+        U = torch.from_numpy(synth.u_batch(spec, 16)).cuda()
+        Y = torch.empty((16, rows), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            wh.wh_gemv_batched(ctx, mat, U, Y)
+        torch.cuda.synchronize()
+        print(f"# probe done: 3 x wh_gemv_batched k=16 rate {rate} {rows}x{cols}", file=sys.stderr, flush=True)
+        wh.wh_destroy(ctx)
+        return
     if args.probe:
         for i in range(3):
             wh.wh_gemv(ctx, mat, us[i], y, 0, rows, args.flags)

@@ -59,30 +59,32 @@ struct AccTwoSum {
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return __half2float(__ushort_as_half(h)); }
 
-// Per-format loader: one lane-step = kElems consecutive values of a row.
+// Per-format loader: one lane-step = kElems consecutive values of a row,
+// one 16-byte load kept raw until each value is multiplied (widening all of
+// them at once would hold kElems FP32 registers per row).
 struct F32Fmt {
     static constexpr int kElems = 4;
     static constexpr int kBytes = 4;
-    __device__ __forceinline__ static void load(const void* base, uint64_t elem, float (&v)[kElems])
+    typedef f32x4 Raw;
+    __device__ __forceinline__ static Raw load(const void* base, uint64_t elem)
     {
-        const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(base) + elem / 4);
-        v[0] = x.x;
-        v[1] = x.y;
-        v[2] = x.z;
-        v[3] = x.w;
+        return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(base) + elem / 4);
     }
+    __device__ __forceinline__ static float get(const Raw& x, int k) { return x[k]; }
 };
 
 template <bool BF>
 struct Half16Fmt {
     static constexpr int kElems = 8;
     static constexpr int kBytes = 2;
-    __device__ __forceinline__ static void load(const void* base, uint64_t elem, float (&v)[kElems])
+    typedef u16x8 Raw;
+    __device__ __forceinline__ static Raw load(const void* base, uint64_t elem)
     {
-        const u16x8 x = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(base) + elem / 8);
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            v[k] = BF ? bf16_to_f32(x[k]) : f16_to_f32(x[k]);
+        return __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(base) + elem / 8);
+    }
+    __device__ __forceinline__ static float get(const Raw& x, int k)
+    {
+        return BF ? bf16_to_f32(x[k]) : f16_to_f32(x[k]);
     }
 };
 
@@ -147,20 +149,20 @@ __global__ void __launch_bounds__(kThreads) dense_rowmajor_kernel(const void* __
             uu[k + 2] = x.z;
             uu[k + 3] = x.w;
         }
-        float m[kDenseRows][E];
+        typename Fmt::Raw m[kDenseRows];
 #pragma unroll
         for (int t = 0; t < kDenseRows; ++t)
             if ((uint32_t)t < nr)
-                Fmt::load(M, (uint64_t)(r0 + t) * cols + (uint64_t)step * E, m[t]);
+                m[t] = Fmt::load(M, (uint64_t)(r0 + t) * cols + (uint64_t)step * E);
 #pragma unroll
         for (int t = 0; t < kDenseRows; ++t) {
             if ((uint32_t)t < nr) {
 #pragma unroll
                 for (int g = 0; g < E; g += 4) {
-                    float p = m[t][g] * uu[g];
-                    p = __builtin_fmaf(m[t][g + 1], uu[g + 1], p);
-                    p = __builtin_fmaf(m[t][g + 2], uu[g + 2], p);
-                    p = __builtin_fmaf(m[t][g + 3], uu[g + 3], p);
+                    float p = Fmt::get(m[t], g) * uu[g];
+                    p = __builtin_fmaf(Fmt::get(m[t], g + 1), uu[g + 1], p);
+                    p = __builtin_fmaf(Fmt::get(m[t], g + 2), uu[g + 2], p);
+                    p = __builtin_fmaf(Fmt::get(m[t], g + 3), uu[g + 3], p);
                     acc[t].add(p);
                 }
             }

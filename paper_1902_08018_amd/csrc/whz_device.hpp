@@ -244,7 +244,8 @@ __device__ __forceinline__ void decode_plane(const uint32_t* lw, const uint32_t*
                                              uint32_t (&A)[16])
 {
     constexpr uint32_t kMaxBits = 32u * NW;
-    uint32_t q = pos >> 5;
+    // word of pos (positions stay below 1024: kMaxBits + 32 + one plane)
+    uint32_t q = __builtin_amdgcn_ubfe(pos, 5u, 5u);
     // 32 bits from pos: the verbatim bits (nsig <= 16) and the first 8
     // section bits always fit
     const uint32_t lo = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], pos & 31u);
@@ -256,15 +257,17 @@ __device__ __forceinline__ void decode_plane(const uint32_t* lw, const uint32_t*
     uint32_t acc = e;
     uint32_t at = pos + nsig + (e & 15u); // next unread bit
     nsig += (e >> 4) & 15u;
-    while (__any(!(e & kEntDone))) {
-        q = at >> 5;
-        const uint32_t bits = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], at & 31u);
-        uint32_t idx = (nsig << 9) + (e & (kEntState | kEntDone)); // ended: >= kSecDone
-        idx |= bits & 0xFFu;
-        e = tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
-        acc |= e;
-        at += e & 15u;
-        nsig += (e >> 4) & 15u;
+    if (__any(!(e & kEntDone))) {
+        do {
+            q = __builtin_amdgcn_ubfe(at, 5u, 5u);
+            const uint32_t bits = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], at & 31u);
+            uint32_t idx = (nsig << 9) + (e & (kEntState | kEntDone)); // ended: >= kSecDone
+            idx |= bits & 0xFFu;
+            e = tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
+            acc |= e;
+            at += e & 15u;
+            nsig += (e >> 4) & 15u;
+        } while (__any(!(e & kEntDone)));
     }
     // the implied 1 of coefficient 15, moved back to where the run stood when
     // the budget ended if the run read past the end (at - kMaxBits zeros)
@@ -310,14 +313,15 @@ __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uin
 template <int NW>
 constexpr int kStagedWords = NW + 3;
 
-// Decode the block staged at lw[q * STRIDE], q = 0..NW-1 (lw[q * STRIDE] == 0
-// for q = NW..NW+2); w0 == lw[0]; tab = the section table (in LDS).  Outputs
-// the 16 integers of the block after the inverse transform (local index
-// 4r + c) and emax.  Returns false for an all-zero block (then iv[] is all
-// 0).  Every bit pattern decodes (the function is total).
+// Decode the coefficients of the block staged at lw[q * STRIDE], q =
+// 0..NW-1 (lw[q * STRIDE] == 0 for q = NW..NW+2); w0 == lw[0]; tab = the
+// section table (in LDS).  Outputs the 16 transform coefficients (two's
+// complement, at their block positions 4r + c, before the inverse
+// transform) and emax.  Returns false for an all-zero block (then cf[] is
+// all 0).  Every bit pattern decodes (the function is total).
 template <int NW, int STRIDE>
-__device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, const uint32_t* tab, uint32_t w0, int& emax,
-                                                  uint32_t (&iv)[16])
+__device__ __forceinline__ bool decode_block_coeffs(const uint32_t* lw, const uint32_t* tab, uint32_t w0, int& emax,
+                                                    uint32_t (&cf)[16])
 {
     const bool nz = (w0 & 1u) != 0;
     emax = (int)((w0 >> 1) & 0xFFu) - 127;
@@ -330,9 +334,58 @@ __device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, const uint
     // the sequency order
 #pragma unroll
     for (int s = 0; s < 16; ++s)
-        iv[order_of(s)] = A[s] - kNega;
+        cf[order_of(s)] = A[s] - kNega;
+    return nz;
+}
+
+// The decoded block: its coefficients through the inverse transform, as
+// integers (value = iv * 2^(emax - 30)).
+template <int NW, int STRIDE>
+__device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, const uint32_t* tab, uint32_t w0, int& emax,
+                                                  uint32_t (&iv)[16])
+{
+    const bool nz = decode_block_coeffs<NW, STRIDE>(lw, tab, w0, emax, iv);
     inv_xform(iv);
     return nz;
+}
+
+// The inverse lift without its two floor halvings is a linear map B (the
+// inverse of the forward lift's matrix (1/16) [[4,4,4,4],[5,1,-1,-5],
+// [-4,4,4,-4],[-2,6,-6,2]]):
+//   B = [[1, 3/2, -1, -1/4], [1, 1/2, 1, 5/4], [1, -1/2, 1, -5/4], [1, -3/2, -1, 1/4]]
+// and the 2-D inverse transform of a coefficient block C is B C B^T up to
+// those halvings (at most a few units of the block's last integer bit).
+// Hence a block's row sums against u are B (C (B^T u)): B^T u is a per-
+// column-block quantity, and B, being the same for every block, can be
+// applied once to a row group's accumulated sums.
+template <typename T>
+__device__ __forceinline__ void lin_inv_lift(T& x, T& y, T& z, T& w)
+{
+    y += w * T(0.5);
+    w -= y * T(0.5);
+    T t = y;
+    y += w;
+    w -= t;
+    t = z;
+    z += x;
+    x -= t;
+    t = y;
+    y += z;
+    z -= t;
+    t = w;
+    w += x;
+    x -= t;
+}
+
+// B^T u for one block column (u0..u3 its four u values).
+template <typename T>
+__device__ __forceinline__ void lin_bt_u(T u0, T u1, T u2, T u3, T (&ut)[4])
+{
+    const T s03 = u0 + u3, d03 = u0 - u3, s12 = u1 + u2, d12 = u1 - u2;
+    ut[0] = s03 + s12;
+    ut[1] = T(1.5) * d03 + T(0.5) * d12;
+    ut[2] = s12 - s03;
+    ut[3] = T(1.25) * d12 - T(0.25) * d03;
 }
 
 // --------------------------------------------------------------- encoding

@@ -237,27 +237,32 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
             stage_block<NW, kGemvThreads>(row, srow + (uint64_t)bj * NW, w);
             int emax;
             uint32_t iv[16];
-            decode_block_ints<NW, kGemvThreads>(row, tab, w[0], emax, iv);
-            const int k = emax - 30;
+            if constexpr (Acc::kPerProduct) {
+                // Fig. 7: each FP32 product of the decoded value and u is
+                // added to the FP64 sum on its own
+                decode_block_ints<NW, kGemvThreads>(row, tab, w[0], emax, iv);
+                const int k = emax - 30;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float p0 = (float)(int32_t)iv[4 * r], p1 = (float)(int32_t)iv[4 * r + 1];
-                const float p2 = (float)(int32_t)iv[4 * r + 2], p3 = (float)(int32_t)iv[4 * r + 3];
-                if constexpr (Acc::kPerProduct) {
-                    // Fig. 7: each FP32 product of the decoded value and u is
-                    // added to the FP64 sum on its own
-                    acc[r].add(__builtin_ldexpf(p0, k) * uu.x);
-                    acc[r].add(__builtin_ldexpf(p1, k) * uu.y);
-                    acc[r].add(__builtin_ldexpf(p2, k) * uu.z);
-                    acc[r].add(__builtin_ldexpf(p3, k) * uu.w);
-                } else {
-                    // FP32 row sum inside the block; the power-of-two block
-                    // scale is applied once to that sum
-                    float p = p0 * uu.x;
-                    p = __builtin_fmaf(p1, uu.y, p);
-                    p = __builtin_fmaf(p2, uu.z, p);
-                    p = __builtin_fmaf(p3, uu.w, p);
-                    acc[r].add(__builtin_ldexpf(p, k));
+                for (int r = 0; r < 4; ++r) {
+                    acc[r].add(__builtin_ldexpf((float)(int32_t)iv[4 * r], k) * uu.x);
+                    acc[r].add(__builtin_ldexpf((float)(int32_t)iv[4 * r + 1], k) * uu.y);
+                    acc[r].add(__builtin_ldexpf((float)(int32_t)iv[4 * r + 2], k) * uu.z);
+                    acc[r].add(__builtin_ldexpf((float)(int32_t)iv[4 * r + 3], k) * uu.w);
+                }
+            } else {
+                // coefficients against B^T u (FP32); B is applied once to the
+                // row group's sums below
+                decode_block_coeffs<NW, kGemvThreads>(row, tab, w[0], emax, iv);
+                float ut[4];
+                lin_bt_u<float>(uu.x, uu.y, uu.z, uu.w, ut);
+                const int k = emax - 30;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = (float)(int32_t)iv[4 * r] * ut[0];
+                    v = __builtin_fmaf((float)(int32_t)iv[4 * r + 1], ut[1], v);
+                    v = __builtin_fmaf((float)(int32_t)iv[4 * r + 2], ut[2], v);
+                    v = __builtin_fmaf((float)(int32_t)iv[4 * r + 3], ut[3], v);
+                    acc[r].add(__builtin_ldexpf(v, k));
                 }
             }
         }
@@ -274,36 +279,64 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
 
     // then across the waves of the workgroup
     __syncthreads();
-    if (threadIdx.x < (uint32_t)(4 * nr)) {
-        const int k = threadIdx.x;
-        double s = red[0][k];
+    if constexpr (Acc::kPerProduct) {
+        if (threadIdx.x < (uint32_t)(4 * nr)) {
+            const int k = threadIdx.x;
+            double s = red[0][k];
 #pragma unroll
-        for (int q = 1; q < kGemvThreads / 64; ++q)
-            s += red[q][k];
-        const uint32_t out_row = (bi0 - bi_begin) * 4 + k;
-        if (nslab == 1)
-            y[out_row] = (float)s;
-        else
-            part[(uint64_t)slab * ((bi_end - bi_begin) * 4) + out_row] = s;
+            for (int q = 1; q < kGemvThreads / 64; ++q)
+                s += red[q][k];
+            const uint32_t out_row = (bi0 - bi_begin) * 4 + k;
+            if (nslab == 1)
+                y[out_row] = (float)s;
+            else
+                part[(uint64_t)slab * ((bi_end - bi_begin) * 4) + out_row] = s;
+        }
+    } else if (threadIdx.x < nr) {
+        // one lane per block row: its four coefficient-row sums, then B
+        const int t = threadIdx.x;
+        double v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            v[r] = red[0][4 * t + r];
+#pragma unroll
+            for (int q = 1; q < kGemvThreads / 64; ++q)
+                v[r] += red[q][4 * t + r];
+        }
+        lin_inv_lift<double>(v[0], v[1], v[2], v[3]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t out_row = (bi0 + t - bi_begin) * 4 + r;
+            if (nslab == 1)
+                y[out_row] = (float)v[r];
+            else
+                part[(uint64_t)slab * ((bi_end - bi_begin) * 4) + out_row] = v[r];
+        }
     }
 }
 
 // ---------------------------------------------------- multi-RHS (MFMA path)
 // Y = M U^T for k right-hand sides (Sec. 4.4 batched).  One workgroup = 4
-// waves = 16 block-rows (64 rows); per step every wave decodes a 4 x 16
-// tile of blocks (16 rows x 64 columns, one block per lane), writes the
-// decoded values to its LDS tile, and contracts the tile against the 64 x k
-// slice of U on the matrix cores:
-//   FP32 U   v_mfma_f32_16x16x4f32: A = decoded FP32 values (exact), 16 MFMAs
-//            per 16 right-hand sides and step
-//   BF16 U   v_mfma_f32_16x16x32_bf16: A = decoded values rounded to BF16,
-//            2 MFMAs per 16 right-hand sides and step
+// waves = 16 block-rows (64 rows).  A block's rows against U are
+// B (C (B^T U)) (C its coefficients, B the inverse transform's linear part;
+// see lin_inv_lift), so the matrix cores contract coefficients, not decoded
+// values, against B^T U, and B is applied once to each block row's sums at
+// the end.  Per step (16 block columns = 64 columns):
+//   * the workgroup stages B^T U for the step's 64 columns and 16*NT
+//     right-hand sides in LDS (coalesced loads, shared by the 4 waves);
+//   * every wave decodes a 4 x 16 tile of blocks (one per lane) and writes
+//     the coefficients, scaled by the block's 2^(emax-30), to its LDS tile;
+//   * the tile (16 x 64) is contracted against the staged slice:
+//       FP32 U   v_mfma_f32_16x16x4f32, 16 MFMAs per 16 right-hand sides
+//       BF16 U   v_mfma_f32_16x16x32_bf16 (coefficients and B^T U rounded
+//                to BF16), 2 MFMAs per 16 right-hand sides
 // Operand layouts (16x16 output tile D[i][j], lane l):
 //   A[i][kk]  lane = i + 16*(kk/g), element kk % g   (g = 1 FP32, 8 BF16)
 //   B[kk][j]  lane = j + 16*(kk/g), element kk % g
 //   D[i][j]   lane = j + 16*(i/4), register i % 4
-// The FP32 MFMA accumulators cover one 64-column step; after every step they
-// are added into FP64 sums, so no FP32 chain is longer than 64 products.
+// so each lane's four accumulators are the four coefficient rows of one
+// block row.  The FP32 MFMA accumulators cover one step; after every step
+// they are added into FP64 sums.
 constexpr int kMrhsWaves = 4;
 constexpr int kMrhsThreads = 64 * kMrhsWaves;
 constexpr int kMrhsBlockRows = 4 * kMrhsWaves; // per workgroup
@@ -311,12 +344,26 @@ constexpr int kATileStride = 64 + 4;           // floats per LDS row of a wave's
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
 
+// Staged B^T U.  FP32: row (m * 16 + c) holds column 4c + m of the step for
+// the 16*NT right-hand sides; the odd row length keeps both the staging
+// writes and the MFMA operand reads on distinct banks.  BF16: row rhs holds
+// the step's 64 columns (8 consecutive columns = one 16-byte operand).
+template <int NT>
+struct MrhsUt {
+    static constexpr int kF32Stride = 16 * NT + 1;
+    static constexpr int kBf16Stride = 64 + 8;
+    static constexpr int kF32Words = 64 * kF32Stride;
+    static constexpr int kBf16Words = 16 * NT * kBf16Stride / 2;
+};
+
 __device__ __forceinline__ __bf16 to_bf16_rne(float f)
 {
     const uint32_t b = __float_as_uint(f);
     const uint16_t h = (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
     return __builtin_bit_cast(__bf16, h);
 }
+
+__device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 template <int NW, bool BF16U, int NT>
 __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __restrict__ stream,
@@ -326,9 +373,11 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                                                             uint32_t bi_begin, uint32_t bi_end, uint32_t slab_bc,
                                                             uint32_t nslab)
 {
+    using UT = MrhsUt<NT>;
     __shared__ uint32_t lds[kMrhsThreads * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
     __shared__ float atile[kMrhsWaves][16 * kATileStride];
+    __shared__ uint32_t utw[BF16U ? UT::kBf16Words : UT::kF32Words];
     uint32_t* row = lds + threadIdx.x;
     clear_pad<NW, kMrhsThreads>(row);
     load_section_table<kMrhsThreads>(tab);
@@ -338,9 +387,10 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
     const uint32_t bw = bi_begin + tile * kMrhsBlockRows + 4 * wave; // first block-row of this wave
     const uint32_t bc0 = slab * slab_bc;
     const uint32_t bc1 = bc0 + slab_bc < nbc ? bc0 + slab_bc : nbc;
-    const uint32_t cols = nbc * 4;
     const int t = lane >> 4, c = lane & 15; // this lane's block in the wave's 4 x 16 step tile
     float* at = atile[wave];
+    float* utf = reinterpret_cast<float*>(utw);
+    uint16_t* utb = reinterpret_cast<uint16_t*>(utw);
 
     mf32x4 acc[NT];
     double sum[NT][4];
@@ -351,7 +401,41 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
             sum[n][j] = 0.0;
 
     for (uint32_t cb = bc0; cb < bc1; cb += 16) {
-        // ---- decode one block per lane into the wave's A tile (16 x 64)
+        __syncthreads(); // the previous step's contraction is done with the staged slice
+        // ---- stage B^T U: item i = (right-hand side, block column), block
+        // columns fastest so that the loads of a wave are contiguous
+        for (int i = threadIdx.x; i < 16 * NT * 16; i += kMrhsThreads) {
+            const uint32_t rhs = (uint32_t)i >> 4, bcol = (uint32_t)i & 15u;
+            float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f;
+            if (rhs < k && cb + bcol < bc1) {
+                const uint64_t o = (uint64_t)rhs * ldu + 4ull * (cb + bcol);
+                if constexpr (BF16U) {
+                    const uint16_t* U = static_cast<const uint16_t*>(Uv) + o;
+                    u0 = bf16_to_float(U[0]);
+                    u1 = bf16_to_float(U[1]);
+                    u2 = bf16_to_float(U[2]);
+                    u3 = bf16_to_float(U[3]);
+                } else {
+                    const float* U = static_cast<const float*>(Uv) + o;
+                    u0 = U[0];
+                    u1 = U[1];
+                    u2 = U[2];
+                    u3 = U[3];
+                }
+            }
+            float ut[4];
+            lin_bt_u<float>(u0, u1, u2, u3, ut);
+            if constexpr (BF16U) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    utb[rhs * UT::kBf16Stride + 4 * bcol + m] = __builtin_bit_cast(uint16_t, to_bf16_rne(ut[m]));
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    utf[(m * 16 + bcol) * UT::kF32Stride + rhs] = ut[m];
+            }
+        }
+        // ---- decode one block per lane: scaled coefficients into the wave's A tile
         const uint32_t bi = bw + t, bj = cb + c;
         const bool valid = bi < bi_end && bj < bc1;
         uint32_t w[NW];
@@ -364,36 +448,29 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
             w[0] = 0u;
         }
         int emax;
-        uint32_t iv[16];
-        decode_block_ints<NW, kMrhsThreads>(row, tab, w[0], emax, iv);
+        uint32_t cf[16];
+        decode_block_coeffs<NW, kMrhsThreads>(row, tab, w[0], emax, cf);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc)
-                at[(4 * t + r) * kATileStride + 4 * c + cc] = __builtin_ldexpf((float)(int32_t)iv[4 * r + cc], emax - 30);
-        // the tile is this wave's own: its LDS writes and reads stay in program
-        // order, so no barrier is needed between decode and contraction
+                at[(4 * t + r) * kATileStride + 4 * c + cc] = __builtin_ldexpf((float)(int32_t)cf[4 * r + cc], emax - 30);
+        __syncthreads(); // staged slice complete (the A tile is the wave's own)
         // ---- contract: 16 rows x 64 columns x (16 * NT) right-hand sides
 #pragma unroll
         for (int n = 0; n < NT; ++n)
             acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
-        const uint32_t col0 = 4 * cb;
         if constexpr (!BF16U) {
-            const float* U = static_cast<const float*>(Uv);
 #pragma unroll 4
             for (int kb = 0; kb < 16; ++kb) {
-                const int kk = 4 * kb + (lane >> 4);
-                const float a = at[(lane & 15) * kATileStride + kk];
-                const uint32_t col = col0 + kk;
+                const int m = lane >> 4; // column 4 kb + m of the step
+                const float a = at[(lane & 15) * kATileStride + 4 * kb + m];
+                const float* ub = utf + (m * 16 + kb) * UT::kF32Stride + (lane & 15);
 #pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const uint32_t rhs = 16 * n + (lane & 15);
-                    const float b = (rhs < k && col < cols) ? U[(uint64_t)rhs * ldu + col] : 0.0f;
-                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[n], 0, 0, 0);
-                }
+                for (int n = 0; n < NT; ++n)
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ub[16 * n], acc[n], 0, 0, 0);
             }
         } else {
-            const uint16_t* U = static_cast<const uint16_t*>(Uv);
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 const int kk0 = 32 * ks + 8 * (lane >> 4);
@@ -403,14 +480,8 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                     a[e] = to_bf16_rne(at[(lane & 15) * kATileStride + kk0 + e]);
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
-                    const uint32_t rhs = 16 * n + (lane & 15);
-                    mbf16x8 b;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const uint32_t col = col0 + kk0 + e;
-                        const uint16_t h = (rhs < k && col < cols) ? U[(uint64_t)rhs * ldu + col] : (uint16_t)0;
-                        b[e] = __builtin_bit_cast(__bf16, h);
-                    }
+                    const mbf16x8 b =
+                        *reinterpret_cast<const mbf16x8*>(utb + (16 * n + (lane & 15)) * UT::kBf16Stride + kk0);
                     acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[n], 0, 0, 0);
                 }
             }
@@ -422,10 +493,12 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                 sum[n][j] += (double)acc[n][j];
     }
 
-    // ---- D[i][j]: lane holds rows 4*(lane/16) + j, right-hand side lane%16
+    // ---- B on each block row's four coefficient-row sums; D[i][j]: lane
+    // holds rows 4*(lane/16) + j, right-hand side lane%16
     const uint32_t nrows = (bi_end - bi_begin) * 4;
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
+        lin_inv_lift<double>(sum[n][0], sum[n][1], sum[n][2], sum[n][3]);
         const uint32_t rhs = 16 * n + (lane & 15);
         if (rhs >= k)
             continue;

@@ -7,6 +7,11 @@
 //       idle = 1: wave votes report other lanes still busy at random, so the
 //       decoder's loops take extra trips with this lane finished (as lanes
 //       of a wave do on the GPU)
+//   device_codec_host linear 0 <nblocks> <in> <out>
+//       in: nblocks * (16 int32 coefficients at positions 4r + c, then 4
+//       float32 u); out: nblocks * 8 float64: the block's four row sums
+//       against u through the exact integer inverse transform, then through
+//       the linear form B (C (B^T u)) that the fused kernels use
 //   device_codec_host encode <nw> <nblocks> <in> <out>
 //       in: nblocks * 16 float32 (v = 4r + c); out: nblocks * nw words;
 //       exit status = number of blocks with NaN/Inf (encoded as zero)
@@ -114,6 +119,37 @@ static int run(bool dec, size_t n, const std::vector<char>& in, std::vector<char
     return encode<NW>(reinterpret_cast<const float*>(in.data()), n, reinterpret_cast<uint32_t*>(out.data()));
 }
 
+static void linear(const char* in, size_t n, double* out)
+{
+    for (size_t b = 0; b < n; ++b) {
+        const char* rec = in + b * 80;
+        uint32_t cf[16];
+        float u[4];
+        std::memcpy(cf, rec, 64);
+        std::memcpy(u, rec + 64, 16);
+        uint32_t iv[16];
+        std::memcpy(iv, cf, 64);
+        wh::inv_xform(iv);
+        for (int r = 0; r < 4; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < 4; ++c)
+                s += (double)(int32_t)iv[4 * r + c] * (double)u[c];
+            out[8 * b + r] = s;
+        }
+        double ut[4]; // in FP64: the test isolates the floor halvings
+        wh::lin_bt_u<double>(u[0], u[1], u[2], u[3], ut);
+        double v[4];
+        for (int r = 0; r < 4; ++r) {
+            v[r] = 0.0;
+            for (int c = 0; c < 4; ++c)
+                v[r] += (double)(int32_t)cf[4 * r + c] * ut[c];
+        }
+        wh::lin_inv_lift<double>(v[0], v[1], v[2], v[3]);
+        for (int r = 0; r < 4; ++r)
+            out[8 * b + 4 + r] = v[r];
+    }
+}
+
 int main(int argc, char** argv)
 {
     if (argc < 6) {
@@ -121,20 +157,24 @@ int main(int argc, char** argv)
         return 255;
     }
     const bool dec = std::strcmp(argv[1], "decode") == 0;
+    const bool lin = std::strcmp(argv[1], "linear") == 0;
     const int nw = std::atoi(argv[2]);
     const size_t n = std::strtoull(argv[3], nullptr, 10);
     g_idle_lanes = argc > 6 && std::atoi(argv[6]) != 0;
     FILE* f = std::fopen(argv[4], "rb");
     if (!f)
         return 254;
-    std::vector<char> in(dec ? n * 4 * nw : n * 64);
+    std::vector<char> in(lin ? n * 80 : dec ? n * 4 * nw : n * 64);
     const size_t got = std::fread(in.data(), 1, in.size(), f);
     std::fclose(f);
     if (got != in.size())
         return 253;
     std::vector<char> out;
-    int rc;
-    switch (nw) {
+    int rc = 0;
+    if (lin) {
+        out.resize(n * 64);
+        linear(in.data(), n, reinterpret_cast<double*>(out.data()));
+    } else switch (nw) {
     case 1: rc = run<1>(dec, n, in, out); break;
     case 2: rc = run<2>(dec, n, in, out); break;
     case 3: rc = run<3>(dec, n, in, out); break;

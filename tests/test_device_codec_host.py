@@ -102,3 +102,31 @@ def test_encode_rejects_non_finite(exe, tmp_path):
     assert bad == 2
     w = np.frombuffer(got, np.uint32).reshape(4, 4)
     assert np.all(w[1] == 0) and np.all(w[3] == 0)  # encoded as zero blocks
+
+
+def test_linear_row_sums_match_integer_inverse(exe, tmp_path):
+    """The fused kernels take a block's row sums against u as B (C (B^T u)),
+    B the inverse lift without its two floor halvings.  That differs from the
+    integer inverse transform only by those halvings: a few units of the
+    block's last integer bit per value.  The coefficients are those of value
+    blocks the encoder accepts (|value| < 2^30 after block scaling), with low
+    bits dropped as a fixed rate drops bit planes."""
+    rng = np.random.default_rng(7)
+    n = 6000
+    vals = rng.integers(-(2 ** 30) + 1, 2 ** 30, size=(n, 16), dtype=np.int64)
+    smooth = rng.integers(-(2 ** 30) + 2 ** 22, 2 ** 30 - 2 ** 22, size=(n // 2, 1))
+    vals[: n // 2] = smooth + rng.integers(-(2 ** 20), 2 ** 20, size=(n // 2, 16))  # smooth blocks
+    vals[:100] = rng.integers(-3, 4, size=(100, 16))                            # tiny values
+    cf = np.stack([oracle.fwd_xform(v) for v in vals]).astype(np.int64)
+    drop = rng.integers(0, 24, size=(n, 1))
+    cf = (cf >> drop) << drop                                                   # lost low planes
+    u = rng.random((n, 4)).astype(np.float32)
+    u[:50] *= -1.0
+    rec = np.zeros(n, dtype=[("c", "<i4", 16), ("u", "<f4", 4)])
+    rec["c"] = cf.astype(np.int32)
+    rec["u"] = u
+    got, _ = run(exe, tmp_path, "linear", 0, rec, n)
+    out = np.frombuffer(got, np.float64).reshape(n, 8)
+    exact, lin = out[:, :4], out[:, 4:]
+    bound = 8.0 * np.abs(u).astype(np.float64).sum(axis=1, keepdims=True)
+    assert np.all(np.abs(exact - lin) <= bound), float(np.max(np.abs(exact - lin) / bound))
