@@ -29,7 +29,7 @@ struct GemvPlan {
 // Launch geometry of the multi-RHS kernel: tiles of 16 block-rows x slabs of
 // block-columns (multiples of 16).
 typedef GemvPlan MrhsPlan;
-constexpr uint32_t kMrhsTileBlockRows = 16;
+constexpr uint32_t kMrhsTileBlockRows = 32;
 constexpr uint32_t kMaxRhs = 64;
 
 bool whz_rate_supported(uint32_t rate);

@@ -127,7 +127,9 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
     pl.bi_end = row_end / 4;
     const uint32_t nbr = pl.bi_end - pl.bi_begin;
     pl.ntiles = (nbr + kMrhsTileBlockRows - 1) / kMrhsTileBlockRows;
-    const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 4;
+    // two 8-wave workgroups are resident per CU: one full round of them;
+    // more column slabs would only add FP64 partials (slabs x k x rows)
+    const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 2;
     const uint32_t max_slabs = (pl.nbc + 15) / 16;
     uint32_t nslab = pl.ntiles ? (uint32_t)((want + pl.ntiles - 1) / pl.ntiles) : 1;
     if (nslab < 1)

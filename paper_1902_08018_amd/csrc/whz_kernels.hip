@@ -316,38 +316,41 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
 }
 
 // ---------------------------------------------------- multi-RHS (MFMA path)
-// Y = M U^T for k right-hand sides (Sec. 4.4 batched).  One workgroup = 4
-// waves = 16 block-rows (64 rows).  A block's rows against U are
+// Y = M U^T for k right-hand sides (Sec. 4.4 batched).  One workgroup = 8
+// waves = 32 block-rows (128 rows).  A block's rows against U are
 // B (C (B^T U)) (C its coefficients, B the inverse transform's linear part;
 // see lin_inv_lift), so the matrix cores contract coefficients, not decoded
 // values, against B^T U, and B is applied once to each block row's sums at
 // the end.  Per step (16 block columns = 64 columns):
 //   * the workgroup stages B^T U for the step's 64 columns and 16*NT
-//     right-hand sides in LDS (coalesced loads, shared by the 4 waves);
-//   * every wave decodes a 4 x 16 tile of blocks (one per lane) and writes
-//     the coefficients, scaled by the block's 2^(emax-30), to its LDS tile;
-//   * the tile (16 x 64) is contracted against the staged slice:
-//       FP32 U   v_mfma_f32_16x16x4f32, 16 MFMAs per 16 right-hand sides
-//       BF16 U   v_mfma_f32_16x16x32_bf16 (coefficients and B^T U rounded
-//                to BF16), 2 MFMAs per 16 right-hand sides
+//     right-hand sides in LDS (coalesced loads, shared by the 8 waves);
+//   * every wave decodes a 4 x 16 tile of blocks (one per lane) and keeps
+//     the coefficients, scaled by the block's 2^(emax-30), in registers;
+//   * four times, the lanes of one block-column quarter write their blocks
+//     to the wave's 16 x 16 LDS tile, which is contracted at once:
+//       FP32 U   v_mfma_f32_16x16x4f32, 4 MFMAs per quarter and 16 RHS
+//       BF16 U   v_mfma_f32_16x16x16bf16_1k (coefficients and B^T U rounded
+//                to BF16), 1 MFMA per quarter and 16 RHS
+//     (a quarter-width tile keeps the LDS per workgroup low enough for four
+//     waves per SIMD).
 // Operand layouts (16x16 output tile D[i][j], lane l):
-//   A[i][kk]  lane = i + 16*(kk/g), element kk % g   (g = 1 FP32, 8 BF16)
+//   A[i][kk]  lane = i + 16*(kk/g), element kk % g   (g = 1 FP32, 4 BF16)
 //   B[kk][j]  lane = j + 16*(kk/g), element kk % g
 //   D[i][j]   lane = j + 16*(i/4), register i % 4
 // so each lane's four accumulators are the four coefficient rows of one
 // block row.  The FP32 MFMA accumulators cover one step; after every step
 // they are added into FP64 sums.
-constexpr int kMrhsWaves = 4;
+constexpr int kMrhsWaves = 8;
 constexpr int kMrhsThreads = 64 * kMrhsWaves;
-constexpr int kMrhsBlockRows = 4 * kMrhsWaves; // per workgroup
-constexpr int kATileStride = 64 + 4;           // floats per LDS row of a wave's A tile
+static_assert(4 * kMrhsWaves == (int)kMrhsTileBlockRows, "block rows per multi-RHS workgroup");
+constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's quarter tile
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
+typedef short mbf16x4 __attribute__((ext_vector_type(4)));
 
 // Staged B^T U.  FP32: row (m * 16 + c) holds column 4c + m of the step for
 // the 16*NT right-hand sides; the odd row length keeps both the staging
 // writes and the MFMA operand reads on distinct banks.  BF16: row rhs holds
-// the step's 64 columns (8 consecutive columns = one 16-byte operand).
+// the step's 64 columns (4 consecutive columns = one 8-byte operand).
 template <int NT>
 struct MrhsUt {
     static constexpr int kF32Stride = 16 * NT + 1;
@@ -356,14 +359,23 @@ struct MrhsUt {
     static constexpr int kBf16Words = 16 * NT * kBf16Stride / 2;
 };
 
-__device__ __forceinline__ __bf16 to_bf16_rne(float f)
+__device__ __forceinline__ uint16_t to_bf16_rne(float f)
 {
     const uint32_t b = __float_as_uint(f);
-    const uint16_t h = (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
-    return __builtin_bit_cast(__bf16, h);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
 }
 
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Orders the LDS accesses of the lanes of one wave: writes before it are
+// visible to reads after it in every lane of the wave, and no access moves
+// across it.
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int NW, bool BF16U, int NT>
 __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __restrict__ stream,
@@ -384,7 +396,7 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
-    const uint32_t bw = bi_begin + tile * kMrhsBlockRows + 4 * wave; // first block-row of this wave
+    const uint32_t bw = bi_begin + tile * kMrhsTileBlockRows + 4 * wave; // first block-row of this wave
     const uint32_t bc0 = slab * slab_bc;
     const uint32_t bc1 = bc0 + slab_bc < nbc ? bc0 + slab_bc : nbc;
     const int t = lane >> 4, c = lane & 15; // this lane's block in the wave's 4 x 16 step tile
@@ -428,14 +440,14 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
             if constexpr (BF16U) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
-                    utb[rhs * UT::kBf16Stride + 4 * bcol + m] = __builtin_bit_cast(uint16_t, to_bf16_rne(ut[m]));
+                    utb[rhs * UT::kBf16Stride + 4 * bcol + m] = to_bf16_rne(ut[m]);
             } else {
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
                     utf[(m * 16 + bcol) * UT::kF32Stride + rhs] = ut[m];
             }
         }
-        // ---- decode one block per lane: scaled coefficients into the wave's A tile
+        // ---- decode one block per lane: scaled coefficients (registers)
         const uint32_t bi = bw + t, bj = cb + c;
         const bool valid = bi < bi_end && bj < bc1;
         uint32_t w[NW];
@@ -450,39 +462,51 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
         int emax;
         uint32_t cf[16];
         decode_block_coeffs<NW, kMrhsThreads>(row, tab, w[0], emax, cf);
+        float sc[16];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int cc = 0; cc < 4; ++cc)
-                at[(4 * t + r) * kATileStride + 4 * c + cc] = __builtin_ldexpf((float)(int32_t)cf[4 * r + cc], emax - 30);
-        __syncthreads(); // staged slice complete (the A tile is the wave's own)
-        // ---- contract: 16 rows x 64 columns x (16 * NT) right-hand sides
+        for (int v = 0; v < 16; ++v)
+            sc[v] = __builtin_ldexpf((float)(int32_t)cf[v], emax - 30);
+        __syncthreads(); // staged slice complete
 #pragma unroll
         for (int n = 0; n < NT; ++n)
             acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
-        if constexpr (!BF16U) {
-#pragma unroll 4
-            for (int kb = 0; kb < 16; ++kb) {
-                const int m = lane >> 4; // column 4 kb + m of the step
-                const float a = at[(lane & 15) * kATileStride + 4 * kb + m];
-                const float* ub = utf + (m * 16 + kb) * UT::kF32Stride + (lane & 15);
+        // ---- four quarters of 4 block columns: write, then contract
 #pragma unroll
-                for (int n = 0; n < NT; ++n)
-                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ub[16 * n], acc[n], 0, 0, 0);
+        for (int q = 0; q < 4; ++q) {
+            // the tile is the wave's own: lanes read what other lanes of the
+            // wave wrote, so each hand-over is a wave-scope release/acquire
+            // (no workgroup barrier is needed)
+            wave_sync_lds();
+            if ((c >> 2) == q) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    *reinterpret_cast<f32x4*>(at + (4 * t + r) * kATileStride + 4 * (c & 3)) =
+                        f32x4{sc[4 * r], sc[4 * r + 1], sc[4 * r + 2], sc[4 * r + 3]};
             }
-        } else {
+            wave_sync_lds();
+            if constexpr (!BF16U) {
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int kk0 = 32 * ks + 8 * (lane >> 4);
-                mbf16x8 a;
+                for (int kq = 0; kq < 4; ++kq) {
+                    const int m = lane >> 4;     // column 4 kb + m of the step, kb = 4 q + kq
+                    const float a = at[(lane & 15) * kATileStride + 4 * kq + m];
+                    const float* ub = utf + (m * 16 + 4 * q + kq) * UT::kF32Stride + (lane & 15);
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    a[e] = to_bf16_rne(at[(lane & 15) * kATileStride + kk0 + e]);
+                    for (int n = 0; n < NT; ++n)
+                        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ub[16 * n], acc[n], 0, 0, 0);
+                }
+            } else {
+                // K = 16: lane holds A[i][4(lane/16) .. +3], one block column
+                const f32x4 av = *reinterpret_cast<const f32x4*>(at + (lane & 15) * kATileStride + 4 * (lane >> 4));
+                mbf16x4 a;
+                a[0] = (short)to_bf16_rne(av.x);
+                a[1] = (short)to_bf16_rne(av.y);
+                a[2] = (short)to_bf16_rne(av.z);
+                a[3] = (short)to_bf16_rne(av.w);
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
-                    const mbf16x8 b =
-                        *reinterpret_cast<const mbf16x8*>(utb + (16 * n + (lane & 15)) * UT::kBf16Stride + kk0);
-                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[n], 0, 0, 0);
+                    const mbf16x4 b = *reinterpret_cast<const mbf16x4*>(
+                        utb + (16 * n + (lane & 15)) * UT::kBf16Stride + 16 * q + 4 * (lane >> 4));
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[n], 0, 0, 0);
                 }
             }
         }

@@ -44,7 +44,7 @@ def test_mrhs_fp32(gpu_ctx, small_mrhs, k):
     wh.wh_unload(gpu_ctx, mat)
 
 
-@pytest.mark.parametrize("k", [4, 16, 64])
+@pytest.mark.parametrize("k", [4, 16, 20, 33, 64])  # every compiled width (16, 32, 48, 64 RHS)
 def test_mrhs_bf16(gpu_ctx, small_mrhs, k):
     s, Mhat = small_mrhs
     U = synth.u_batch(synth.SMALL, k)
