@@ -119,17 +119,27 @@ wh_status wh_unload(wh_ctx *ctx, wh_mat m);
 /* y[i - row_begin] = sum_j M[i, j] u[j] for rows [row_begin, row_end)
  * (Eq. 2 / Eq. 5 over the slit rows of a resident field matrix, Fig. 2).
  * d_u: cols FP32; d_y: (row_end - row_begin) FP32.  Both bounds multiples
- * of 4, row_begin <= row_end <= rows.  Compressed formats are decoded on
- * the fly inside the kernel; products are FP32; the row sums are FP32
- * within a 4x4 block and FP64 or compensated FP32 across blocks; y is
- * rounded once to FP32 (Fig. 7). */
+ * of 4, row_begin <= row_end <= rows.  d_u 16-byte aligned.
+ *
+ * Compressed formats are decoded inside the kernel, never written out.  A
+ * block's contribution is taken in coefficient space: its coefficients,
+ * scaled by the block exponent, times B^T u (B = the inverse transform's
+ * linear part), in FP32; B is applied to each row group's sums.  This equals
+ * the product with the decoded matrix up to the transform's floor halvings
+ * (a few units of each block's last bit: ~1e-8 relative) for streams an
+ * encoder produced.  Row sums are FP64 (default) or compensated FP32 across
+ * blocks; y is rounded once to FP32 (Fig. 7).  WH_PAPER_MP instead
+ * multiplies every bit-exact decoded value by u in FP32 and adds each
+ * product to an FP64 sum.  Dense formats multiply the stored values. */
 wh_status wh_gemv(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t row_begin, uint32_t row_end,
                   uint32_t flags, void *stream);
 
 /* Y = M U for k right-hand sides (Sec. 4.4, batched).  d_U: k vectors of
  * cols values, vector r at d_U + r*ldu (ldu >= cols), dtype 0 = FP32,
  * 1 = BF16.  d_Y: k vectors of rows FP32 at d_Y + r*ldy (ldy >= rows).
- * 1 <= k <= 64.  zfp format only. */
+ * 1 <= k <= 64.  zfp format only; WH_PAPER_MP only with k = 1.  The matrix
+ * cores contract the scaled coefficients against B^T U (as wh_gemv, FP32;
+ * with BF16 U both operands are rounded to BF16), FP64 across columns. */
 #define WH_U_F32 0
 #define WH_U_BF16 1
 wh_status wh_gemv_batched(wh_ctx *ctx, wh_mat m, const void *d_U, int u_dtype, uint32_t k, uint32_t ldu,
