@@ -75,8 +75,9 @@ def _check(st: int) -> None:
 
 
 def stream_nbytes(rows: int, cols: int, rate: int) -> int:
-    """Fixed rate: exactly 16*rate bits per 4x4 block."""
-    return (rows // 4) * (cols // 4) * 2 * rate
+    """Fixed rate: exactly 16*rate bits per 4x4 block; a dimension that is
+    not a multiple of 4 ends in a partial (edge-padded) block."""
+    return ((rows + 3) // 4) * ((cols + 3) // 4) * 2 * rate
 
 
 def encode(M: np.ndarray, rate: int) -> np.ndarray:
@@ -105,15 +106,13 @@ def decode_blocks(stream: np.ndarray, rate: int, b0: int, nblocks: int) -> np.nd
 
 def gemv_fp64(stream: np.ndarray, rows: int, cols: int, rate: int, u: np.ndarray,
               row_begin: int = 0, row_end: int | None = None, nthreads: int = 1) -> np.ndarray:
-    """FP64 y over the oracle-decoded matrix for rows [row_begin, row_end).
-
-    `stream` may hold only the block-rows of that range if `row_begin`
-    addresses it relative to the array (see `gemv_fp64_rows`)."""
+    """FP64 y over the oracle-decoded matrix for rows [row_begin, row_end)
+    (any range inside the matrix); `stream` is the whole matrix's code."""
     row_end = rows if row_end is None else row_end
     stream = np.ascontiguousarray(stream, dtype=np.uint8)
     u = np.ascontiguousarray(u, dtype=np.float32)
     assert u.size == cols
-    y = np.empty(row_end - row_begin, dtype=np.float64)
+    y = np.empty(max(row_end - row_begin, 0), dtype=np.float64)
     _check(lib().orc_gemv_fp64(_ptr(stream), rows, cols, rate, _ptr(u), row_begin, row_end, _ptr(y), nthreads))
     return y
 
@@ -123,7 +122,7 @@ def gemv_paper_mp(stream: np.ndarray, rows: int, cols: int, rate: int, u: np.nda
     row_end = rows if row_end is None else row_end
     stream = np.ascontiguousarray(stream, dtype=np.uint8)
     u = np.ascontiguousarray(u, dtype=np.float32)
-    y = np.empty(row_end - row_begin, dtype=np.float32)
+    y = np.empty(max(row_end - row_begin, 0), dtype=np.float32)
     _check(lib().orc_gemv_paper_mp(_ptr(stream), rows, cols, rate, _ptr(u), row_begin, row_end, _ptr(y), nthreads))
     return y
 

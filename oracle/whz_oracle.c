@@ -362,28 +362,36 @@ static int check_shape(uint32_t rows, uint32_t cols, uint32_t rate)
 {
     if (rate < 1 || rate > 64)
         return ORC_ERR_INVALID;
-    if (rows % 4 || cols % 4)
+    if (rows == 0 || cols == 0)
         return ORC_ERR_SHAPE;
     return ORC_OK;
 }
 
-/* M: rows x cols FP32 row-major.  stream: (rows/4)*(cols/4)*2*rate bytes,
- * zeroed by this call.  Block (bi, bj) is block number bi*(cols/4) + bj. */
+/* Blocks along a dimension of n values: the last one may be partial. */
+static uint32_t nblk(uint32_t n) { return (n + 3) / 4; }
+
+/* Index n-1 for positions past the end: a partial block is completed by
+ * repeating the matrix's last row / column (edge padding). */
+static uint32_t clamp_index(uint32_t i, uint32_t n) { return i < n ? i : n - 1; }
+
+/* M: rows x cols FP32 row-major.  stream: nblk(rows)*nblk(cols)*2*rate
+ * bytes, zeroed by this call.  Block (bi, bj) is block number
+ * bi*nblk(cols) + bj; a partial block holds the edge-padded values. */
 int orc_encode(const float *M, uint32_t rows, uint32_t cols, uint32_t rate, uint8_t *stream)
 {
     int st = check_shape(rows, cols, rate);
     if (st)
         return st;
     unsigned maxbits = 16u * rate;
-    uint64_t nbytes = (uint64_t)(rows / 4) * (cols / 4) * (maxbits / 8);
+    uint64_t nbytes = (uint64_t)nblk(rows) * nblk(cols) * (maxbits / 8);
     memset(stream, 0, nbytes);
     bitw w = {stream, 0};
-    for (uint32_t bi = 0; bi < rows / 4; bi++) {
-        for (uint32_t bj = 0; bj < cols / 4; bj++) {
+    for (uint32_t bi = 0; bi < nblk(rows); bi++) {
+        for (uint32_t bj = 0; bj < nblk(cols); bj++) {
             float f[16];
             for (int r = 0; r < 4; r++)
                 for (int c = 0; c < 4; c++)
-                    f[4 * r + c] = M[(uint64_t)(4 * bi + r) * cols + 4 * bj + c];
+                    f[4 * r + c] = M[(uint64_t)clamp_index(4 * bi + r, rows) * cols + clamp_index(4 * bj + c, cols)];
             st = encode_block(&w, f, maxbits);
             if (st)
                 return st;
@@ -405,7 +413,8 @@ int orc_decode_blocks(const uint8_t *stream, uint32_t rate, uint64_t b0, uint64_
     return ORC_OK;
 }
 
-/* Decode a whole matrix into Mhat (rows x cols row-major). */
+/* Decode a whole matrix into Mhat (rows x cols row-major); the padding of
+ * partial blocks is dropped. */
 int orc_decode(const uint8_t *stream, uint32_t rows, uint32_t cols, uint32_t rate, float *Mhat)
 {
     int st = check_shape(rows, cols, rate);
@@ -413,13 +422,14 @@ int orc_decode(const uint8_t *stream, uint32_t rows, uint32_t cols, uint32_t rat
         return st;
     unsigned maxbits = 16u * rate;
     bitr r = {stream, 0};
-    for (uint32_t bi = 0; bi < rows / 4; bi++) {
-        for (uint32_t bj = 0; bj < cols / 4; bj++) {
+    for (uint32_t bi = 0; bi < nblk(rows); bi++) {
+        for (uint32_t bj = 0; bj < nblk(cols); bj++) {
             float f[16];
             decode_block(&r, f, maxbits);
-            for (int rr = 0; rr < 4; rr++)
-                for (int c = 0; c < 4; c++)
-                    Mhat[(uint64_t)(4 * bi + rr) * cols + 4 * bj + c] = f[4 * rr + c];
+            for (uint32_t rr = 0; rr < 4; rr++)
+                for (uint32_t c = 0; c < 4; c++)
+                    if (4 * bi + rr < rows && 4 * bj + c < cols)
+                        Mhat[(uint64_t)(4 * bi + rr) * cols + 4 * bj + c] = f[4 * rr + c];
         }
     }
     return ORC_OK;
@@ -432,7 +442,7 @@ enum { ORC_MODE_FP64 = 0, ORC_MODE_PAPER_MP = 1 };
 
 typedef struct {
     const uint8_t *stream;
-    uint32_t cols, rate;
+    uint32_t rows, cols, rate;
     const float *u;
     uint32_t bi_begin, bi_end; /* block-rows handled by this worker */
     uint32_t row0;             /* first output row of the call */
@@ -444,22 +454,25 @@ typedef struct {
 static void *gemv_worker(void *arg)
 {
     gemv_job *job = (gemv_job *)arg;
-    uint32_t cols = job->cols;
+    uint32_t cols = job->cols, padded = 4 * nblk(cols);
     unsigned maxbits = 16u * job->rate;
-    float *rowbuf = (float *)malloc(sizeof(float) * 4 * (size_t)cols);
+    float *rowbuf = (float *)malloc(sizeof(float) * 4 * (size_t)padded);
     if (!rowbuf)
         return (void *)1;
     for (uint32_t bi = job->bi_begin; bi < job->bi_end; bi++) {
-        bitr r = {job->stream, (uint64_t)bi * (cols / 4) * maxbits};
-        for (uint32_t bj = 0; bj < cols / 4; bj++) {
+        bitr r = {job->stream, (uint64_t)bi * nblk(cols) * maxbits};
+        for (uint32_t bj = 0; bj < nblk(cols); bj++) {
             float f[16];
             decode_block(&r, f, maxbits);
             for (int rr = 0; rr < 4; rr++)
                 for (int c = 0; c < 4; c++)
-                    rowbuf[(size_t)rr * cols + 4 * bj + c] = f[4 * rr + c];
+                    rowbuf[(size_t)rr * padded + 4 * bj + c] = f[4 * rr + c];
         }
-        for (int rr = 0; rr < 4; rr++) {
-            const float *m = rowbuf + (size_t)rr * cols;
+        for (uint32_t rr = 0; rr < 4 && 4 * bi + rr < job->rows; rr++) {
+            if (4 * bi + rr < job->row0) /* before the range, in its first block row */
+                continue;
+            /* the sum runs over the matrix's own columns only */
+            const float *m = rowbuf + (size_t)rr * padded;
             uint32_t row = 4 * bi + rr - job->row0;
             if (job->mode == ORC_MODE_FP64) {
                 double sum = 0.0;
@@ -486,9 +499,10 @@ static int run_gemv(const uint8_t *stream, uint32_t rows, uint32_t cols, uint32_
     int st = check_shape(rows, cols, rate);
     if (st)
         return st;
-    if (row_begin % 4 || row_end % 4 || row_begin > row_end || row_end > rows)
+    /* any range of rows: its first and last block rows are decoded whole */
+    if (row_begin > row_end || row_end > rows)
         return ORC_ERR_SHAPE;
-    uint32_t nbr = (row_end - row_begin) / 4;
+    uint32_t nbr = row_begin < row_end ? nblk(row_end) - row_begin / 4 : 0;
     if (nthreads < 1)
         nthreads = 1;
     if ((uint32_t)nthreads > nbr)
@@ -504,6 +518,7 @@ static int run_gemv(const uint8_t *stream, uint32_t rows, uint32_t cols, uint32_
     for (int t = 0; t < nthreads; t++) {
         gemv_job *j = &jobs[t];
         j->stream = stream;
+        j->rows = row_end;
         j->cols = cols;
         j->rate = rate;
         j->u = u;

@@ -23,6 +23,9 @@ operand, wrong bit order) fails at least one of them:
                         the paper's printed numbers
   Sec. 4.4 claim        FP32 accumulation of a 256000-term row loses most
                         of its bits; the FP64 and Fig. 7 reductions do not
+  edge padding          a partial block codes the matrix padded by its last
+                        row / column (numpy's "edge" pad); decoding drops
+                        the padding; the GEMV sums the real columns only
 """
 import math
 import os
@@ -321,8 +324,8 @@ def test_nonfinite_rejected():
 
 
 def test_shape_rejected():
-    with pytest.raises(oracle.OracleError):
-        oracle.encode(np.ones((6, 4), dtype=np.float32), 8)
+    with pytest.raises(oracle.OracleError):  # an empty matrix has no blocks to code
+        oracle.encode(np.ones((0, 4), dtype=np.float32), 8)
 
 
 # ----------------------------------------------- the paper's printed numbers
@@ -386,3 +389,41 @@ def test_compression_error_decreases_with_rate():
     assert all(a > b for a, b in zip(errs, errs[1:]))
     nr8 = metrics.nrmse(M, oracle.decode(oracle.encode(M, 8), 256, 4096, 8))
     assert nr8 < 1e-3
+
+
+# ---------------------------------------------------- partial blocks (edge padding)
+@pytest.mark.parametrize("rows,cols", [(1, 1), (3, 5), (7, 13), (38, 22), (9, 38)])
+@pytest.mark.parametrize("rate", [4, 8, 16])
+def test_partial_blocks_are_edge_padded(rows, cols, rate):
+    """A matrix whose sides are not multiples of 4 is coded as the matrix
+    padded by repeating its last row and column (numpy's "edge" padding);
+    decoding drops the padding, and the GEMV sums over the real columns."""
+    rng = np.random.default_rng(rows * 1000 + cols)
+    M = (rng.standard_normal((rows, cols)) * np.exp2(rng.integers(-3, 4, size=(rows, 1)))).astype(np.float32)
+    P = np.pad(M, ((0, -rows % 4), (0, -cols % 4)), mode="edge")
+    s = oracle.encode(M, rate)
+    assert s.size == oracle.stream_nbytes(rows, cols, rate) == P.size // 16 * 2 * rate
+    assert np.array_equal(s, oracle.encode(P, rate))
+    D = oracle.decode(s, rows, cols, rate)
+    Dp = oracle.decode(s, P.shape[0], P.shape[1], rate)
+    assert np.array_equal(D.view(np.uint32), Dp[:rows, :cols].view(np.uint32))
+    u = rng.random(cols).astype(np.float32)
+    y = oracle.gemv_fp64(s, rows, cols, rate, u)
+    ref = np.array([math.fsum(float(a) * float(b) for a, b in zip(row, u)) for row in D])
+    np.testing.assert_allclose(y, ref, rtol=1e-13, atol=1e-300)
+    for rb, re in [(0, rows), (rows // 2, rows), (0, (rows + 1) // 2), (rows // 3, rows - rows // 3)]:
+        # any range of rows: the same values as the whole product's slice
+        yr = oracle.gemv_fp64(s, rows, cols, rate, u, row_begin=rb, row_end=re)
+        assert np.array_equal(yr, y[rb:re])
+        ym = oracle.gemv_paper_mp(s, rows, cols, rate, u, row_begin=rb, row_end=re)
+        assert np.array_equal(ym, oracle.gemv_paper_mp(s, rows, cols, rate, u)[rb:re])
+
+
+def test_row_range_bounds():
+    M = np.ones((9, 8), np.float32)
+    s = oracle.encode(M, 8)
+    u = np.ones(8, np.float32)
+    assert oracle.gemv_fp64(s, 9, 8, 8, u, row_begin=5, row_end=5).size == 0
+    for rb, re in [(3, 2), (0, 10), (10, 10)]:
+        with pytest.raises(oracle.OracleError):
+            oracle.gemv_fp64(s, 9, 8, 8, u, row_begin=rb, row_end=re)
