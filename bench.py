@@ -144,6 +144,127 @@ def bench_multi_rhs(ctx, mat, spec, rate, stream_bytes, steps):
     return res
 
 
+# The paper's GEMV shapes (Sec. 5, Fig. 10): the slit matrix, its transpose
+# and a square one; and a field matrix (about 2067 MB of FP32, Sec. 3) whose
+# 378-row slit windows are multiplied one after another as the slit moves.
+SLIT_SHAPES = (("wide_378x256000", 378, 256000), ("tall_256000x378", 256000, 378),
+               ("square_10000x10000", 10000, 10000))
+FIELD_ROWS, FIELD_COLS, SLIT_ROWS = 2116, 256000, 378
+
+
+def bench_slit_field(ctx, rate, steps):
+    """Fused decode + GEMV on the paper's GEMV shapes at `rate` bits/value,
+    beside the dense FP32 GEMV of the same matrix (rows padded to a multiple
+    of 4, which dense storage needs); and slit windows of a field matrix."""
+    import torch
+    from paper_1902_08018_amd import synth, wh, workload
+    res = {}
+    for name, rows, cols in SLIT_SHAPES:
+        spec = synth.MatrixSpec(rows, cols, 512, 32.0, seed=3)
+        st = workload.build_stream(ctx, spec, rate)
+        m = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, st)
+        us = [workload.u_device(spec, offset=i * cols) for i in range(4)]
+        y = torch.empty(rows, dtype=torch.float32, device="cuda")
+        ms = time_call(lambda i: wh.wh_gemv(ctx, m, us[i % 4], y, 0, rows), steps, 3)
+        wh.wh_unload(ctx, m)
+        del st
+        flop = rows * (2 * cols - 1)  # Eq. 3's GEMV count
+        entry = {"ms": round(ms, 4), "gflops": round(flop / (ms * 1e-3) / 1e9, 1),
+                 "effective_gbs": round(4.0 * rows * cols / (ms * 1e-3) / 1e9, 1)}
+        prow, pcol = (rows + 3) // 4 * 4, (cols + 3) // 4 * 4
+        if pcol == cols:
+            pspec = synth.MatrixSpec(prow, cols, 512, 32.0, seed=3)
+            dense = workload.build_dense(pspec)
+            md = wh.wh_load_compressed(ctx, prow, cols, wh.WH_FMT_F32, 0, dense)
+            yd = torch.empty(prow, dtype=torch.float32, device="cuda")
+            msd = time_call(lambda i: wh.wh_gemv(ctx, md, us[i % 4], yd, 0, prow), steps, 3)
+            wh.wh_unload(ctx, md)
+            del dense
+            entry["dense_f32"] = {"ms": round(msd, 4), "gflops": round(flop / (msd * 1e-3) / 1e9, 1),
+                                  "hbm_frac": round(4.0 * prow * cols / (msd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        res[name] = entry
+        torch.cuda.empty_cache()
+    spec = synth.MatrixSpec(FIELD_ROWS, FIELD_COLS, 512, 32.0, seed=4)
+    st = workload.build_stream(ctx, spec, rate)
+    m = wh.wh_load_compressed(ctx, FIELD_ROWS, FIELD_COLS, wh.WH_FMT_ZFP_FIXED_RATE, rate, st)
+    u = workload.u_device(spec)
+    y = torch.empty(SLIT_ROWS, dtype=torch.float32, device="cuda")
+    nwin = FIELD_ROWS - SLIT_ROWS + 1
+    starts = [(i * 7) % nwin for i in range(max(steps, 16))]  # the slit steps 7 rows at a time
+
+    def slit(i):
+        r0 = starts[i % len(starts)]
+        wh.wh_gemv(ctx, m, u, y, r0, r0 + SLIT_ROWS)
+    ms = time_call(slit, len(starts), 3)
+    flop = SLIT_ROWS * (2 * FIELD_COLS - 1)
+    res[f"field_{FIELD_ROWS}x{FIELD_COLS}_slit_{SLIT_ROWS}_rows"] = {
+        "ms": round(ms, 4), "gflops": round(flop / (ms * 1e-3) / 1e9, 1),
+        "effective_gbs": round(4.0 * SLIT_ROWS * FIELD_COLS / (ms * 1e-3) / 1e9, 1),
+        "field_stream_gb": round(st.numel() / 1e9, 3), "window_starts": "0, 7, 14, ... (mod 1739)"}
+    wh.wh_unload(ctx, m)
+    del st
+    torch.cuda.empty_cache()
+    res["rate"] = rate
+    res["paper_context"] = "P100 mixed-precision GEMV, uncompressed: 198.3 / 65.9 / 202.6 GFLOP/s (wide / tall / square)"
+    return res
+
+
+def bench_host_pipeline(ctx, rate, steps):
+    """Table 1 measured: a compressed matrix kept in page-locked host memory
+    and streamed over the link by wh_gemv_host, chunks of block rows copied
+    while the fused kernel works on the chunk before (Sec. 3.1-3.2).  Beside
+    it, the parts of Table 1's formulas measured on their own: the plain
+    host-to-device copy of the same compressed bytes (T_transfer / R) and the
+    fused kernel on the resident matrix (T_compute + T_decode)."""
+    import torch
+    from paper_1902_08018_amd import synth, wh, workload
+    res = {}
+    for name, spec in (("field_2116x256000", synth.MatrixSpec(FIELD_ROWS, FIELD_COLS, 512, 32.0, seed=4)),
+                       ("65536x65536", synth.LARGE)):
+        rows, cols = spec.rows, spec.cols
+        st = workload.build_stream(ctx, spec, rate)
+        h = torch.empty(st.numel(), dtype=torch.uint8, pin_memory=True)
+        h.copy_(st)
+        m = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, st)
+        u = workload.u_device(spec)
+        y = torch.empty(rows, dtype=torch.float32, device="cuda")
+        t_fused = time_call(lambda i: wh.wh_gemv(ctx, m, u, y, 0, rows), steps, 2)
+        wh.wh_unload(ctx, m)
+        dbuf = torch.empty_like(st)
+        del st
+        t_copy = time_call(lambda i: dbuf.copy_(h, non_blocking=True), 3, 1)
+        del dbuf
+        torch.cuda.empty_cache()
+        link_gbs = h.numel() / (t_copy * 1e-3) / 1e9
+        entry = {"compressed_gb": round(h.numel() / 1e9, 3), "uncompressed_gb": round(4.0 * rows * cols / 1e9, 3),
+                 "R": 32 / rate, "link_h2d_gbs": round(link_gbs, 1),
+                 "t_copy_compressed_ms": round(t_copy, 3), "t_fused_resident_ms": round(t_fused, 3)}
+        for chunk_rows, label in ((0, "chunk_32MiB"), (4 * max(1, (8 << 20) // wh.stream_bytes(4, cols, rate)),
+                                                        "chunk_8MiB")):
+            call = (lambda i: wh.wh_gemv_host(ctx, h, rows, cols, rate, u, y, 0, rows, chunk_rows))
+            period = time_call(call, 3, 1)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            lat = []
+            for _ in range(3):  # from an idle device: the copy of the first chunk to the last y
+                e0.record()
+                call(0)
+                e1.record()
+                torch.cuda.synchronize()
+                lat.append(e0.elapsed_time(e1))
+            entry[label] = {"period_ms": round(period, 3), "latency_ms": round(min(lat), 3),
+                            "effective_gbs": round(4.0 * rows * cols / (period * 1e-3) / 1e9, 1)}
+        # Table 1 with the measured parts (T_compute << T_transfer for a GEMV, Sec. 3.2)
+        t_transfer = 4.0 * rows * cols / (link_gbs * 1e9) * 1e3
+        entry["table1_ms"] = {"period_without_compression": round(t_transfer, 3),
+                              "period_with": round(max(t_transfer / entry["R"], t_fused), 3),
+                              "latency_with": round(t_fused + t_transfer / entry["R"], 3)}
+        res[name] = entry
+        del h
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(size, rate):
     """The CPU oracle (decode + FP64 GEMV, threads over block-rows) on a
     bounded sample: whole rows of the same matrix, encoded by the oracle."""
@@ -406,6 +527,10 @@ def main():
         torch.cuda.empty_cache()
         print("# dense precision sweep", file=sys.stderr, flush=True)
         extra["dense_precision"] = bench_precision(ctx, spec, us, y, max(5, args.steps // 2))
+        print("# the paper's GEMV shapes and slit windows of a field matrix", file=sys.stderr, flush=True)
+        extra[f"slit_field_rate{rate}"] = bench_slit_field(ctx, rate, max(10, args.steps))
+        print("# host-resident matrices streamed over the link", file=sys.stderr, flush=True)
+        extra[f"host_pipeline_rate{rate}"] = bench_host_pipeline(ctx, rate, max(5, args.steps // 2))
 
     if args.serving:
         print("# serving loop", file=sys.stderr, flush=True)

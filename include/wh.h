@@ -26,8 +26,12 @@
  *     every later call returns WH_ERR_DEVICE.
  *   - The caller owns every d_* buffer it passes; the library owns its
  *     workspaces and any matrix it copied in (WH_HOST).
- *   - Matrices are row-major, rows x cols; v1 requires rows and cols to be
- *     multiples of 4 (else WH_ERR_SHAPE).
+ *   - Matrices are row-major, rows x cols.  The compressed format takes any
+ *     rows, cols >= 1: a partial 4x4 block at the bottom or right edge is
+ *     coded as if the matrix were extended by repeating its last row and
+ *     column (edge padding), and every output stops at the matrix's edge.
+ *     Dense formats need rows and cols to be multiples of 4
+ *     (else WH_ERR_SHAPE).
  *   - A context is used from one host thread at a time, except wh_submit /
  *     wh_poll which are thread-safe.
  */
@@ -44,7 +48,7 @@ typedef int32_t wh_status;
 #define WH_OK 0
 #define WH_PENDING 1
 #define WH_ERR_INVALID (-1)   /* bad argument (NULL, range, unsupported)  */
-#define WH_ERR_SHAPE (-2)     /* dimensions not multiples of 4 / mismatch  */
+#define WH_ERR_SHAPE (-2)     /* bad dimensions / row range / mismatch     */
 #define WH_ERR_FORMAT (-3)    /* unknown format / rate / byte count        */
 #define WH_ERR_NOMEM (-4)     /* device allocation failed                  */
 #define WH_ERR_BUDGET (-5)    /* serving admission: over the HBM budget    */
@@ -56,8 +60,8 @@ typedef enum {
     /* WHZ1: zfp-style fixed-rate code of FP32 values in 4x4 blocks (block
      * floating point, decorrelating lift, sequency order, negabinary,
      * embedded bit-plane group testing).  Exactly 16*rate bits per block,
-     * blocks in raster order b = (i/4)*(cols/4) + (j/4).  Sec. 4.3,
-     * Table 2 ("fixed rate"). */
+     * blocks in raster order b = (i/4)*ceil(cols/4) + (j/4), partial
+     * blocks edge-padded.  Sec. 4.3, Table 2 ("fixed rate"). */
     WH_FMT_ZFP_FIXED_RATE = 1,
     WH_FMT_F32 = 2,          /* dense FP32, row-major                       */
     WH_FMT_F16 = 3,          /* dense IEEE half, RNE from FP32              */
@@ -94,7 +98,12 @@ const char *wh_status_str(wh_status st);
 
 /* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds
  * the device memory the serving loop may hold for request buffers (0 = 1 GiB
- * default).  No GPU / bad device -> WH_ERR_DEVICE. */
+ * default).  No GPU / bad device -> WH_ERR_DEVICE.  The environment
+ * variables WH_GEMV_LANES (4, 8, ..., 512 lanes per block row),
+ * WH_GEMV_ROWS (1, 2 or 4 block rows per lane group) and WH_GEMV_SLABS
+ * (column slabs), read here, fix the compressed GEMV's launch shape instead
+ * of the planner's choice (for launch-shape sweeps); invalid values are
+ * ignored.  Results stay within the stated tolerances for every shape. */
 wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx **out);
 
 /* Destroy a context: waits for its work, frees what it owns. */
@@ -118,8 +127,11 @@ wh_status wh_unload(wh_ctx *ctx, wh_mat m);
 
 /* y[i - row_begin] = sum_j M[i, j] u[j] for rows [row_begin, row_end)
  * (Eq. 2 / Eq. 5 over the slit rows of a resident field matrix, Fig. 2).
- * d_u: cols FP32; d_y: (row_end - row_begin) FP32.  Both bounds multiples
- * of 4, row_begin <= row_end <= rows.  d_u 16-byte aligned.
+ * d_u: cols FP32; d_y: (row_end - row_begin) FP32.  Any range with
+ * row_begin <= row_end <= rows (else WH_ERR_SHAPE), except that the
+ * block-scaled FP8 format needs both ends on multiples of 4.  The compressed
+ * format decodes the range's first and last block rows whole and writes only
+ * the range's rows.  d_u 16-byte aligned.
  *
  * Compressed formats are decoded inside the kernel, never written out.  A
  * block's contribution is taken in coefficient space: its coefficients,
@@ -145,19 +157,40 @@ wh_status wh_gemv(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t 
 wh_status wh_gemv_batched(wh_ctx *ctx, wh_mat m, const void *d_U, int u_dtype, uint32_t k, uint32_t ldu,
                           float *d_Y, uint32_t ldy, uint32_t flags, void *stream);
 
+/* y[i - row_begin] = sum_j M[i, j] u[j] for rows [row_begin, row_end) of a
+ * WHZ1 matrix that stays in HOST memory (Sec. 3.1-3.2, Table 1: the model
+ * matrix lives in host DDR and crosses PCIe compressed, pipelined with the
+ * work on the GPU).  h_code: the matrix's whole rate-`rate` stream (rows x
+ * cols, layout as WH_FMT_ZFP_FIXED_RATE), host memory; only the block rows
+ * of the range are read.  The block rows cross the link in chunks of
+ * chunk_rows rows (a multiple of 4; 0 = about 32 MiB of code per chunk) on
+ * a copy stream of the library's, into two device staging buffers used in
+ * turn; each chunk's fused decode + GEMV runs on `stream` once its copy has
+ * landed, while the next chunk is in flight.  Copies overlap the GPU's work
+ * only from page-locked memory (hipHostMalloc, torch pin_memory); pageable
+ * memory works but its copies are staged by the runtime.  h_code must stay
+ * valid and unchanged until the work on `stream` has finished.  d_u, d_y,
+ * flags, ranges and errors as wh_gemv; the staging buffers belong to the
+ * context (grown on demand, freed by wh_destroy). */
+wh_status wh_gemv_host(wh_ctx *ctx, const void *h_code, uint32_t rows, uint32_t cols, uint32_t rate,
+                       const float *d_u, float *d_y, uint32_t row_begin, uint32_t row_end, uint32_t chunk_rows,
+                       uint32_t flags, void *stream);
+
 /* Bit-exactness probe: decode blocks [block_begin, block_begin + nblocks)
- * of a zfp matrix into d_out[nblocks][16] FP32 (v = 4r + c in a block). */
+ * of a zfp matrix into d_out[nblocks][16] FP32 (v = 4r + c in a block;
+ * partial blocks come out with their edge padding). */
 wh_status wh_decode_debug(wh_ctx *ctx, wh_mat m, uint64_t block_begin, uint64_t nblocks, float *d_out,
                           void *stream);
 
 /* Decode a whole zfp matrix into a dense row-major FP32 matrix d_out
- * (rows x cols) -- the "decode, then GEMV" path of Fig. 11. */
+ * (rows x cols; the edge padding is dropped) -- the "decode, then GEMV"
+ * path of Fig. 11. */
 wh_status wh_decode(wh_ctx *ctx, wh_mat m, float *d_out, void *stream);
 
 /* Offline encoder (Sec. 4.3: encoding happens before the loop starts), run
  * on the GPU: WHZ1 fixed-rate code of the dense FP32 matrix d_M (rows x
- * cols, row-major) into d_stream (wh_storage_bytes bytes; every byte is
- * written).  NaN/Inf values encode as zero blocks and are counted in
+ * cols, row-major, any rows, cols >= 1, 16-byte aligned) into d_stream
+ * (wh_storage_bytes bytes; every byte is written).  NaN/Inf values encode as zero blocks and are counted in
  * *d_bad (device uint32, may be NULL; not cleared by the call). */
 wh_status wh_encode(wh_ctx *ctx, const float *d_M, uint32_t rows, uint32_t cols, uint32_t rate, void *d_stream,
                     uint32_t *d_bad, void *stream);

@@ -415,7 +415,7 @@ wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, cons
     hipError_t e = hipSuccess;
     uint32_t nslab = 1;
     if (fmt == WH_FMT_FP8E4M3_BS4) {
-        GemvPlan pl = whz_gemv_plan(mat.desc.rows, cols, row_begin, row_end, ctx->num_cus, kThreads);
+        GemvPlan pl = block_slab_plan(cols, row_begin, row_end, ctx->num_cus, kThreads, kFp8TileRows);
         nslab = pl.nslab;
         double* part = nullptr;
         if (nslab > 1) {

@@ -7,10 +7,11 @@
 // different sizes, share one GPU:
 //
 //   submit      any thread; the request is validated, stamped and queued
-//   admission   each matrix gets a fixed number of device slots (U, Y and the
-//               FP64 slab partials of one batch) carved out of the context's
-//               HBM budget (two if the budget allows: one batch
-//               runs while the next is staged); a batch waits for a free slot;
+//   admission   each matrix gets device slots (U, Y and the FP64 slab
+//               partials of one batch) carved out of the context's HBM
+//               budget: one on first use, a second (one batch runs while the
+//               next is staged) if the budget still holds the first slots of
+//               every other resident matrix; a batch waits for a free slot;
 //               a request that can never fit is rejected at submit
 //   batching    continuous: whenever a slot of a matrix is free, all queued
 //               requests of that matrix (FIFO, up to 64 right-hand sides) form
@@ -117,9 +118,9 @@ size_t slot_partials(const Matrix& m, int num_cus)
     const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, num_cus);
     size_t n = 0;
     if (gp.nslab > 1)
-        n = std::max(n, (size_t)gp.nslab * m.desc.rows);
+        n = std::max(n, (size_t)gp.nslab * gp.part_rows());
     if (mp.nslab > 1)
-        n = std::max(n, (size_t)mp.nslab * kMaxRhs * m.desc.rows);
+        n = std::max(n, (size_t)mp.nslab * kMaxRhs * mp.part_rows());
     return n;
 }
 
@@ -181,12 +182,35 @@ void free_slot(Slot& sl)
     sl = Slot{};
 }
 
+// Called with sv->mu held (takes ctx->mu).  The first slots still owed to
+// the context's resident compressed matrices that have none yet (each one
+// that fits the budget on its own).
+size_t first_slot_reserve(Server* sv)
+{
+    size_t r = 0;
+    std::lock_guard<std::mutex> lk(sv->ctx->mu);
+    for (const auto& kv : sv->ctx->mats) {
+        if (kv.second.desc.fmt != WH_FMT_ZFP_FIXED_RATE)
+            continue;
+        auto it = sv->mats.find(kv.first);
+        if (it != sv->mats.end() && !it->second.slots.empty())
+            continue;
+        const size_t b = slot_bytes(kv.second, sv->ctx->num_cus);
+        if (b <= sv->ctx->budget)
+            r += b;
+    }
+    return r;
+}
+
 // Called with sv->mu held.  Adds a slot to a matrix if the budget has room
-// for it; the slot's bytes are charged only when it is built.
+// for it; the slot's bytes are charged only when it is built.  A second slot
+// must leave room for the first slots of the resident matrices that have
+// none yet, so a matrix whose first request comes late is not starved.
 bool add_slot(Server* sv, MatServe& ms)
 {
     const size_t per = slot_bytes(ms.m, sv->ctx->num_cus);
-    if ((int)ms.slots.size() >= kMaxSlotsPerMatrix || sv->arena_used + per > sv->ctx->budget)
+    const size_t reserve = ms.slots.empty() ? 0 : first_slot_reserve(sv);
+    if ((int)ms.slots.size() >= kMaxSlotsPerMatrix || sv->arena_used + per + reserve > sv->ctx->budget)
         return false;
     Slot sl;
     if (build_slot(sv, ms, sl) != WH_OK) {
@@ -200,8 +224,8 @@ bool add_slot(Server* sv, MatServe& ms)
 
 // Called with sv->mu held.  Sets up serving state for a matrix on first use:
 // one slot now; a second one later, when a batch of this matrix has to wait
-// and the budget still has room (so that every matrix in use gets its first
-// slot before any gets a second).
+// and the budget has room beyond the first slots owed to the other resident
+// matrices.
 MatServe* serve_matrix(Server* sv, wh_mat mat, wh_status& st)
 {
     auto it = sv->mats.find(mat);

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cstdlib>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -34,20 +35,44 @@ wh_status device_error(wh_ctx* ctx, hipError_t e)
 
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
+// WH_GEMV_LANES / WH_GEMV_ROWS / WH_GEMV_SLABS fix the fused GEMV's lanes per
+// block row, block rows per lane group and column slabs (launch-shape sweeps
+// and tests); a value that is not valid is ignored.
+GemvTuning gemv_tuning_from_env()
+{
+    auto get = [](const char* name) -> uint32_t {
+        const char* v = std::getenv(name);
+        if (!v || !*v)
+            return 0;
+        char* end = nullptr;
+        const unsigned long x = std::strtoul(v, &end, 10);
+        return (*end == 0 && x <= 0xFFFFFFFFul) ? (uint32_t)x : 0u;
+    };
+    GemvTuning t;
+    const uint32_t lanes = get("WH_GEMV_LANES"), rows = get("WH_GEMV_ROWS");
+    if (lanes >= 4 && lanes <= kGemvLanes && (lanes & (lanes - 1)) == 0)
+        t.lanes = lanes;
+    if (rows == 1 || rows == 2 || rows == 4)
+        t.rows = rows;
+    t.slabs = get("WH_GEMV_SLABS");
+    return t;
+}
+
 wh_status storage_bytes(const wh_matrix_desc& d, uint64_t& nbytes)
 {
     if (d.rows == 0 || d.cols == 0)
         return WH_ERR_SHAPE;
-    if (d.rows % 4 || d.cols % 4)
-        return WH_ERR_SHAPE;
+    if (d.fmt == WH_FMT_ZFP_FIXED_RATE) { // partial blocks at the edges are edge-padded
+        if (!whz_rate_supported(d.rate))
+            return WH_ERR_FORMAT;
+        nbytes = (uint64_t)((d.rows + 3) / 4) * ((d.cols + 3) / 4) * 2u * d.rate;
+        return WH_OK;
+    }
+    if (d.rows % 4 || d.cols % 4) // dense formats: whole 4 x 4 tiles
+        return d.fmt >= WH_FMT_F32 && d.fmt <= WH_FMT_FP8E4M3_BS4 ? WH_ERR_SHAPE : WH_ERR_FORMAT;
     const uint64_t n = (uint64_t)d.rows * d.cols;
     const uint64_t nb = n / 16;
     switch (d.fmt) {
-    case WH_FMT_ZFP_FIXED_RATE:
-        if (!whz_rate_supported(d.rate))
-            return WH_ERR_FORMAT;
-        nbytes = nb * 2u * d.rate;
-        return WH_OK;
     case WH_FMT_F32:
         nbytes = n * 4;
         return WH_OK;
@@ -93,15 +118,7 @@ Matrix* find_matrix(wh_ctx* ctx, wh_mat m)
 
 } // namespace wh
 
-#define WH_GUARD(ctx)                                                                                               \
-    do {                                                                                                             \
-        if (!(ctx))                                                                                                  \
-            return WH_ERR_INVALID;                                                                                   \
-        if ((ctx)->failed.load())                                                                                    \
-            return WH_ERR_DEVICE;                                                                                    \
-        if (hipSetDevice((ctx)->device) != hipSuccess)                                                               \
-            return WH_ERR_DEVICE;                                                                                    \
-    } while (0)
+
 
 extern "C" {
 
@@ -151,6 +168,7 @@ wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
         wh_ctx* ctx = new wh_ctx();
         ctx->device = hip_device;
         ctx->num_cus = prop.multiProcessorCount;
+        ctx->gemv_tune = gemv_tuning_from_env();
         ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (1ull << 30);
         *out = ctx;
         return WH_OK;
@@ -169,6 +187,7 @@ wh_status wh_destroy(wh_ctx* ctx)
         (void)hipSetDevice(ctx->device);
         serve_shutdown(ctx);
         (void)hipDeviceSynchronize();
+        host_pipe_free(ctx);
         for (auto& kv : ctx->mats)
             if (kv.second.owned && kv.second.dptr)
                 (void)hipFree(kv.second.dptr);
@@ -284,7 +303,10 @@ wh_status wh_gemv(wh_ctx* ctx, wh_mat m, const float* d_u, float* d_y, uint32_t 
                 return WH_ERR_NOT_FOUND;
             mat = *p;
         }
-        if (row_begin % 4 || row_end % 4 || row_begin > row_end || row_end > mat.desc.rows)
+        if (row_begin > row_end || row_end > mat.desc.rows)
+            return WH_ERR_SHAPE;
+        // block-scaled FP8 works on whole 4 x 4 tiles: a range of block rows
+        if (mat.desc.fmt == WH_FMT_FP8E4M3_BS4 && (row_begin % 4 || row_end % 4))
             return WH_ERR_SHAPE;
         if (row_begin == row_end)
             return WH_OK;
@@ -293,10 +315,11 @@ wh_status wh_gemv(wh_ctx* ctx, wh_mat m, const float* d_u, float* d_y, uint32_t 
                                                        : AccMode::Fp64;
         hipStream_t st = static_cast<hipStream_t>(stream);
         if (mat.desc.fmt == WH_FMT_ZFP_FIXED_RATE) {
-            const GemvPlan pl = whz_gemv_plan(mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus);
+            const GemvPlan pl =
+                whz_gemv_plan(mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
             double* part = nullptr;
             if (pl.nslab > 1) {
-                wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * (row_end - row_begin));
+                wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * pl.part_rows());
                 if (s2 != WH_OK)
                     return s2;
                 part = ctx->part;
@@ -338,7 +361,7 @@ wh_status wh_gemv_batched(wh_ctx* ctx, wh_mat m, const void* d_U, int u_dtype, u
         const MrhsPlan pl = whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus);
         double* part = nullptr;
         if (pl.nslab > 1) {
-            wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * k * mat.desc.rows);
+            wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * k * pl.part_rows());
             if (s2 != WH_OK)
                 return s2;
             part = ctx->part;
@@ -366,7 +389,7 @@ wh_status wh_decode_debug(wh_ctx* ctx, wh_mat m, uint64_t block_begin, uint64_t 
         }
         if (mat.desc.fmt != WH_FMT_ZFP_FIXED_RATE)
             return WH_ERR_FORMAT;
-        const uint64_t nb = (uint64_t)(mat.desc.rows / 4) * (mat.desc.cols / 4);
+        const uint64_t nb = (uint64_t)((mat.desc.rows + 3) / 4) * ((mat.desc.cols + 3) / 4);
         if (block_begin > nb || nblocks > nb - block_begin)
             return WH_ERR_INVALID;
         if (nblocks == 0)
@@ -407,7 +430,7 @@ wh_status wh_encode(wh_ctx* ctx, const float* d_M, uint32_t rows, uint32_t cols,
     WH_GUARD(ctx);
     if (!d_M || !d_stream || !aligned(d_M, 16) || !aligned(d_stream, 4))
         return WH_ERR_INVALID;
-    if (rows == 0 || cols == 0 || rows % 4 || cols % 4)
+    if (rows == 0 || cols == 0)
         return WH_ERR_SHAPE;
     if (!whz_rate_supported(rate))
         return WH_ERR_FORMAT;

@@ -20,7 +20,15 @@ struct Matrix {
     bool owned;      // copied in by the library (WH_HOST)
 };
 
-struct Server; // serving loop state (serve.hip)
+struct Server;   // serving loop state (serve.hip)
+struct HostPipe; // copy stream and staging of wh_gemv_host (host_stream.hip)
+
+// wh_gemv_host: staging buffers used in turn, and the default chunk of
+// compressed bytes per copy.
+constexpr int kPipeBuffers = 2;
+constexpr uint64_t kPipeChunkBytes = 32ull << 20;
+// Waits for the pipe's copies and frees it (wh_destroy).
+void host_pipe_free(wh_ctx* ctx);
 
 wh_status device_error(wh_ctx* ctx, hipError_t e);
 wh_status ensure_partials(wh_ctx* ctx, size_t count);
@@ -41,6 +49,7 @@ void serve_forget(wh_ctx* ctx, wh_mat m);
 struct wh_ctx {
     int device = 0;
     int num_cus = 256;
+    wh::GemvTuning gemv_tune; // launch-shape overrides read at wh_create
     uint64_t budget = 0;
     std::mutex mu; // guards mats / next_id
     std::unordered_map<wh_mat, wh::Matrix> mats;
@@ -49,4 +58,16 @@ struct wh_ctx {
     size_t part_cap = 0;
     std::atomic<bool> failed{false};
     wh::Server* server = nullptr; // owned; freed by serve_shutdown
+    wh::HostPipe* pipe = nullptr;  // owned; freed by host_pipe_free
 };
+
+// Entry-point prologue: a live context whose device is current.
+#define WH_GUARD(ctx)                                                                                               \
+    do {                                                                                                             \
+        if (!(ctx))                                                                                                  \
+            return WH_ERR_INVALID;                                                                                   \
+        if ((ctx)->failed.load())                                                                                    \
+            return WH_ERR_DEVICE;                                                                                    \
+        if (hipSetDevice((ctx)->device) != hipSuccess)                                                               \
+            return WH_ERR_DEVICE;                                                                                    \
+    } while (0)

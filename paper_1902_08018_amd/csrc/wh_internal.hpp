@@ -12,18 +12,42 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // Accumulation of the cross-block row sums.
 enum class AccMode { Fp64, TwoSum, PaperMp };
 
-// Block-rows per workgroup tile of the fused GEMV, and its workgroup size.
-constexpr int kGemvTileRows = 4;
+// Workgroup size of the fused GEMV; the most block rows one lane group takes
+// per tile; and the LDS doubles that hold the groups' row sums (slots x 4 x
+// rows per group: one slot per wave, or per group of fewer than 64 lanes).
 constexpr uint32_t kGemvLanes = 512;
+constexpr int kGemvMaxRowsPerGroup = 4;
+constexpr int kGemvRedDoubles = 512;
+constexpr uint32_t gemv_slots(uint32_t lg) { return lg >= 6 ? kGemvLanes / 64 : kGemvLanes >> lg; }
 
-// Launch geometry of the fused GEMV over block-rows [bi_begin, bi_end).
+// Launch geometry of the fused GEMV over rows [row_begin, row_end), i.e.
+// block-rows [bi_begin, bi_end).  The lanes of a workgroup form groups of
+// 2^lg; each group sweeps one block row's slab of block columns, and a tile is
+// (512 >> lg) groups x rpg block rows.  A matrix whose sides are not multiples
+// of 4 ends in partial blocks: the stream codes them edge-padded, u is taken as
+// zero past the last column, and rows outside the range are not written.
 struct GemvPlan {
-    uint32_t nbc;      // block-columns (cols / 4)
-    uint32_t bi_begin; // first block-row
-    uint32_t bi_end;   // one past the last block-row
-    uint32_t ntiles;   // row tiles of kGemvTileRows block-rows
-    uint32_t slab_bc;  // block-columns per slab (multiple of 256)
+    uint32_t nbc;      // block-columns (ceil(cols / 4))
+    uint32_t bi_begin; // first block-row (row_begin / 4)
+    uint32_t bi_end;   // one past the last block-row (ceil(row_end / 4))
+    uint32_t ntiles;   // row tiles
+    uint32_t slab_bc;  // block-columns per slab (a multiple of the group width)
     uint32_t nslab;    // column slabs; > 1 needs an FP64 partial workspace
+    uint32_t cols;     // matrix columns
+    uint32_t nrows;    // rows written: row_end - row_begin
+    uint32_t lg;       // log2 of the lanes per group (2 .. 9)
+    uint32_t rpg;      // block rows per group and tile (1 .. kGemvMaxRowsPerGroup)
+    uint32_t skip;     // row_begin % 4: rows of the first block row before the range
+    // FP64 partials per slab and right-hand side: the range's block-rows
+    uint32_t part_rows() const { return (bi_end - bi_begin) * 4; }
+};
+
+// Fixed launch shape for the fused GEMV (tuning and tests): zero fields are
+// left to the planner.
+struct GemvTuning {
+    uint32_t lanes = 0; // lanes per group: 4, 8, ..., 512
+    uint32_t rows = 0;  // block rows per group and tile: 1 .. kGemvMaxRowsPerGroup
+    uint32_t slabs = 0; // column slabs (at most one per group width of block columns)
 };
 
 // Launch geometry of the multi-RHS kernel: tiles of 16 block-rows x slabs of
@@ -36,9 +60,12 @@ bool whz_rate_supported(uint32_t rate);
 MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus);
 hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu,
                     uint32_t k, float* Y, uint32_t ldy, double* part, hipStream_t st);
-// lanes: workgroup size of the kernel the plan is for (slabs are multiples of it)
 GemvPlan whz_gemv_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
-                       uint32_t lanes = kGemvLanes);
+                       const GemvTuning* tune = nullptr);
+// Slabs of block columns for a kernel whose `lanes` lanes sweep each block row
+// of a tile of `tile_rows` block rows together (the block-scaled FP8 GEMV).
+GemvPlan block_slab_plan(uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t lanes,
+                         uint32_t tile_rows);
 hipError_t whz_gemv(uint32_t rate, const GemvPlan& pl, AccMode mode, const void* stream, const float* u, float* y,
                     double* part, hipStream_t st);
 hipError_t whz_decode_blocks(uint32_t rate, const void* stream, uint64_t b0, uint64_t n, float* out, hipStream_t st);

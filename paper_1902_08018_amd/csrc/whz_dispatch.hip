@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "wh_internal.hpp"
 
 #define WH_FOR_EACH_NW(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(16)
@@ -75,30 +77,105 @@ hipError_t whz_encode(uint32_t rate, const float* M, uint32_t rows, uint32_t col
     }
 }
 
-GemvPlan whz_gemv_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t lanes)
+namespace {
+
+uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+GemvPlan range_plan(uint32_t cols, uint32_t row_begin, uint32_t row_end)
 {
-    (void)rows;
-    const uint32_t kThreads = lanes;
     GemvPlan pl{};
-    pl.nbc = cols / 4;
+    pl.nbc = (cols + 3) / 4;
     pl.bi_begin = row_begin / 4;
-    pl.bi_end = row_end / 4;
-    const uint32_t nbr = pl.bi_end - pl.bi_begin;
-    pl.ntiles = (nbr + kGemvTileRows - 1) / kGemvTileRows;
-    // enough workgroups to fill the chip several times over
-    const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 8;
-    const uint32_t max_slabs = (pl.nbc + kThreads - 1) / kThreads;
-    uint32_t nslab = pl.ntiles ? (uint32_t)((want + pl.ntiles - 1) / pl.ntiles) : 1;
-    if (nslab < 1)
-        nslab = 1;
-    if (nslab > max_slabs)
-        nslab = max_slabs ? max_slabs : 1;
-    uint32_t slab_bc = (pl.nbc + nslab - 1) / nslab;
-    slab_bc = (slab_bc + kThreads - 1) / kThreads * kThreads;
-    pl.slab_bc = slab_bc ? slab_bc : kThreads;
-    pl.nslab = (pl.nbc + pl.slab_bc - 1) / pl.slab_bc;
+    pl.bi_end = (row_end + 3) / 4;
+    pl.cols = cols;
+    pl.nrows = row_end - row_begin;
+    pl.skip = row_begin & 3u;
+    return pl;
+}
+
+// Slab width for `nslab` slabs of whole groups of `width` block columns;
+// returns the slab count that width gives.
+uint32_t set_slabs(GemvPlan& pl, uint32_t nslab, uint32_t width)
+{
+    uint32_t slab_bc = ceil_div(pl.nbc, nslab ? nslab : 1);
+    slab_bc = ceil_div(slab_bc, width) * width;
+    pl.slab_bc = slab_bc ? slab_bc : width;
+    pl.nslab = ceil_div(pl.nbc, pl.slab_bc);
     if (pl.nslab < 1)
         pl.nslab = 1;
+    return pl.nslab;
+}
+
+} // namespace
+
+// Launch shape of the fused GEMV, chosen from sweeps of every shape over
+// matrices from 378 x 256000 to 65536^2 on MI355X:
+//  * 8 lanes per block row (14 % faster than 512 on 65536^2).  A wave then
+//    decodes an 8 x 8 patch of blocks instead of 64 blocks of one row, and a
+//    workgroup's slab of u is small and reused by its 64 block rows.  Wider
+//    groups only where a tile of 512 / G block rows would be mostly empty
+//    (few rows); narrower where a row has fewer than 8 block columns.
+//  * One block row per group and tile.
+//  * Column slabs of `iters` blocks per lane and row: about 2048 workgroups
+//    (some three rounds of the 768 resident at once) with 3 to 16 blocks per
+//    lane; past 2^27 blocks, about 8192 workgroups of up to 48 blocks per
+//    lane, which keeps the FP64 partial sums small (the times differ by under
+//    1 % there).
+GemvPlan whz_gemv_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
+                       const GemvTuning* tune)
+{
+    (void)rows;
+    (void)num_cus;
+    GemvPlan pl = range_plan(cols, row_begin, row_end);
+    const uint32_t nbr = pl.bi_end - pl.bi_begin;
+    uint32_t lg = 3;
+    while (lg > 2 && (1u << lg) > pl.nbc) // fewer block columns than lanes
+        --lg;
+    for (;;) { // the narrowest groups whose tiles are at least 90 % full
+        const uint64_t tile = kGemvLanes >> lg;
+        const uint64_t span = (uint64_t)ceil_div(nbr, tile) * tile;
+        if (lg >= 9 || 10 * (uint64_t)nbr >= 9 * span)
+            break;
+        ++lg;
+    }
+    uint32_t rpg = 1;
+    if (tune && tune->lanes) {
+        lg = 2;
+        while ((1u << lg) < tune->lanes && lg < 9)
+            ++lg;
+    }
+    if (tune && tune->rows && gemv_slots(lg) * 4 * tune->rows <= (uint32_t)kGemvRedDoubles)
+        rpg = tune->rows;
+    pl.lg = lg;
+    pl.rpg = rpg;
+    pl.ntiles = ceil_div(nbr, (uint64_t)(kGemvLanes >> lg) * rpg);
+    const uint32_t G = 1u << lg;
+    const uint64_t blocks = (uint64_t)nbr * pl.nbc;
+    const uint64_t per_wg = (uint64_t)kGemvLanes;
+    uint64_t iters = std::min<uint64_t>(16, std::max<uint64_t>(3, (blocks + per_wg * 1024) / (per_wg * 2048)));
+    if (blocks > (1ull << 27))
+        iters = std::min<uint64_t>(48, blocks / (per_wg * 8192));
+    uint32_t nslab = ceil_div(pl.nbc, (uint64_t)G * iters);
+    if (tune && tune->slabs)
+        nslab = tune->slabs;
+    const uint32_t max_slabs = ceil_div(pl.nbc, G);
+    set_slabs(pl, std::max(1u, std::min(nslab, max_slabs)), G);
+    return pl;
+}
+
+GemvPlan block_slab_plan(uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t lanes,
+                         uint32_t tile_rows)
+{
+    GemvPlan pl = range_plan(cols, row_begin, row_end);
+    const uint32_t nbr = pl.bi_end - pl.bi_begin;
+    pl.ntiles = ceil_div(nbr, tile_rows);
+    // enough workgroups to fill the chip several times over
+    const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 8;
+    const uint32_t max_slabs = ceil_div(pl.nbc, lanes);
+    uint32_t nslab = pl.ntiles ? ceil_div(want, pl.ntiles) : 1;
+    if (nslab > max_slabs)
+        nslab = max_slabs;
+    set_slabs(pl, nslab ? nslab : 1, lanes);
     return pl;
 }
 
@@ -122,9 +199,11 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
 {
     (void)rows;
     MrhsPlan pl{};
-    pl.nbc = cols / 4;
+    pl.nbc = (cols + 3) / 4;
     pl.bi_begin = row_begin / 4;
-    pl.bi_end = row_end / 4;
+    pl.bi_end = (row_end + 3) / 4;
+    pl.cols = cols;
+    pl.nrows = row_end - row_begin;
     const uint32_t nbr = pl.bi_end - pl.bi_begin;
     pl.ntiles = (nbr + kMrhsTileBlockRows - 1) / kMrhsTileBlockRows;
     // two 8-wave workgroups are resident per CU: one full round of them;

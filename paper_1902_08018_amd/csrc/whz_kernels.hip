@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kThreads) decode_blocks_kernel(const uint32_t*
 // Whole matrix into row-major FP32 (rows x cols).
 template <int NW>
 __global__ void __launch_bounds__(kThreads) decode_matrix_kernel(const uint32_t* __restrict__ stream, uint32_t nbc,
-                                                                 uint64_t nblocks, uint32_t cols,
+                                                                 uint64_t nblocks, uint32_t rows, uint32_t cols,
                                                                  float* __restrict__ out)
 {
     __shared__ uint32_t lds[kThreads * kStagedWords<NW>];
@@ -118,35 +118,56 @@ __global__ void __launch_bounds__(kThreads) decode_matrix_kernel(const uint32_t*
         uint32_t iv[16];
         decode_block_ints<NW, kThreads>(row, tab, w[0], emax, iv);
         const uint64_t bi = b / nbc, bj = b % nbc;
+        if ((cols & 3u) == 0 && 4 * bi + 3 < rows) { // a whole block on 16-byte aligned rows
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            f32x4 v;
-            v.x = __builtin_ldexpf((float)(int32_t)iv[4 * r], emax - 30);
-            v.y = __builtin_ldexpf((float)(int32_t)iv[4 * r + 1], emax - 30);
-            v.z = __builtin_ldexpf((float)(int32_t)iv[4 * r + 2], emax - 30);
-            v.w = __builtin_ldexpf((float)(int32_t)iv[4 * r + 3], emax - 30);
-            __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(out + (4 * bi + r) * cols + 4 * bj));
+            for (int r = 0; r < 4; ++r) {
+                f32x4 v;
+                v.x = __builtin_ldexpf((float)(int32_t)iv[4 * r], emax - 30);
+                v.y = __builtin_ldexpf((float)(int32_t)iv[4 * r + 1], emax - 30);
+                v.z = __builtin_ldexpf((float)(int32_t)iv[4 * r + 2], emax - 30);
+                v.w = __builtin_ldexpf((float)(int32_t)iv[4 * r + 3], emax - 30);
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(out + (4 * bi + r) * cols + 4 * bj));
+            }
+        } else { // the values of the block inside the matrix (the padding is dropped)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (4 * bi + r < rows && 4 * bj + c < cols)
+                        out[(4 * bi + r) * cols + 4 * bj + c] = __builtin_ldexpf((float)(int32_t)iv[4 * r + c], emax - 30);
         }
     }
 }
 
 // ---------------------------------------------------------------- encoder
 template <int NW>
-__global__ void __launch_bounds__(kThreads) encode_kernel(const float* __restrict__ M, uint32_t nbc, uint32_t cols,
-                                                          uint64_t nblocks, uint32_t* __restrict__ stream,
+__global__ void __launch_bounds__(kThreads) encode_kernel(const float* __restrict__ M, uint32_t nbc, uint32_t rows,
+                                                          uint32_t cols, uint64_t nblocks, uint32_t* __restrict__ stream,
                                                           uint32_t* __restrict__ bad)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < nblocks; b += stride) {
         const uint64_t bi = b / nbc, bj = b % nbc;
         float f[16];
+        if ((cols & 3u) == 0 && 4 * bi + 3 < rows) { // a whole block on 16-byte aligned rows
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float4 v = *reinterpret_cast<const float4*>(M + (4 * bi + r) * cols + 4 * bj);
-            f[4 * r] = v.x;
-            f[4 * r + 1] = v.y;
-            f[4 * r + 2] = v.z;
-            f[4 * r + 3] = v.w;
+            for (int r = 0; r < 4; ++r) {
+                const float4 v = *reinterpret_cast<const float4*>(M + (4 * bi + r) * cols + 4 * bj);
+                f[4 * r] = v.x;
+                f[4 * r + 1] = v.y;
+                f[4 * r + 2] = v.z;
+                f[4 * r + 3] = v.w;
+            }
+        } else { // a partial block is completed by repeating the last row / column
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t i = 4 * bi + r < rows ? 4 * bi + r : rows - 1;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint64_t j = 4 * bj + c < cols ? 4 * bj + c : cols - 1;
+                    f[4 * r + c] = M[i * cols + j];
+                }
+            }
         }
         uint32_t out[NW];
         const bool finite = encode_block<NW>(f, out);
@@ -201,38 +222,66 @@ struct TwoSumAcc {
 
 constexpr int kGemvThreads = (int)kGemvLanes;
 
-template <int NW, int TR, typename Acc>
+// The workgroup's lanes form groups of 2^lg lanes (4 to 512).  A group
+// sweeps a block row's slab of block columns, its lanes striding them; the
+// workgroup's tile is (512 >> lg) groups x rpg block rows, group g taking the
+// tile's rows g, g + groups, ...  Square and wide matrices use one group of
+// 512 lanes; narrow ones (few block columns) use small groups, so that every
+// lane has blocks to decode.  Output row i of the range is matrix row
+// 4 * bi_begin + skip + i.
+template <int NW, typename Acc>
 __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __restrict__ stream,
                                                         const float* __restrict__ u, float* __restrict__ y,
                                                         double* __restrict__ part, uint32_t nbc, uint32_t bi_begin,
-                                                        uint32_t bi_end, uint32_t slab_bc, uint32_t nslab)
+                                                        uint32_t bi_end, uint32_t slab_bc, uint32_t nslab,
+                                                        uint32_t cols, uint32_t nrows, uint32_t lg, uint32_t rpg,
+                                                        uint32_t skip)
 {
     __shared__ uint32_t lds[kGemvThreads * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
-    __shared__ double red[kGemvThreads / 64][TR * 4];
+    // a group's four row sums per tile row: one slot per wave when a group
+    // spans whole waves, else one per group
+    __shared__ double red[kGemvRedDoubles];
     uint32_t* row = lds + threadIdx.x;
     clear_pad<NW, kGemvThreads>(row);
     load_section_table<kGemvThreads>(tab);
 
+    const uint32_t G = 1u << lg, groups = (uint32_t)kGemvThreads >> lg;
+    const uint32_t grp = threadIdx.x >> lg, gl = threadIdx.x & (G - 1);
     const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
-    const uint32_t bi0 = bi_begin + tile * TR;
-    const uint32_t nr = bi_end - bi0 < (uint32_t)TR ? bi_end - bi0 : (uint32_t)TR;
+    const uint32_t bi0 = bi_begin + tile * groups * rpg;
     const uint32_t bc0 = slab * slab_bc;
     const uint32_t bc1 = bc0 + slab_bc < nbc ? bc0 + slab_bc : nbc;
 
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool wide = lg >= 6; // a group spans whole waves
+    const uint32_t slot = wide ? (uint32_t)wave : grp, slot_len = 4 * rpg;
+    const bool leader = wide ? lane == 0 : gl == 0;
+    const int first_mask = wide ? 32 : (int)(G >> 1);
+    const float4* u4 = reinterpret_cast<const float4*>(u);
     // one tile row at a time (rolled loop: one copy of the decoder), so only
     // that row's four accumulators are live while blocks decode
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float4* u4 = reinterpret_cast<const float4*>(u);
 #pragma unroll 1
-    for (uint32_t t = 0; t < nr; ++t) {
+    for (uint32_t t = 0; t < rpg; ++t) {
+        const uint32_t bi = bi0 + t * groups + grp;
+        if (bi >= bi_end) // the same for every lane of the group
+            break;
         Acc acc[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             acc[r].zero();
-        const uint32_t* srow = stream + (uint64_t)(bi0 + t) * nbc * NW;
-        for (uint32_t bj = bc0 + threadIdx.x; bj < bc1; bj += kGemvThreads) {
-            const float4 uu = u4[bj];
+        const uint32_t* srow = stream + (uint64_t)bi * nbc * NW;
+        for (uint32_t bj = bc0 + gl; bj < bc1; bj += G) {
+            float4 uu;
+            if (4 * bj + 3 < cols) {
+                uu = u4[bj];
+            } else { // the partial last block column: u is zero past the last column
+                const uint32_t j = 4 * bj;
+                uu.x = u[j];
+                uu.y = j + 1 < cols ? u[j + 1] : 0.0f;
+                uu.z = j + 2 < cols ? u[j + 2] : 0.0f;
+                uu.w = 0.0f;
+            }
             uint32_t w[NW];
             stage_block<NW, kGemvThreads>(row, srow + (uint64_t)bj * NW, w);
             int emax;
@@ -266,52 +315,50 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
                 }
             }
         }
-        // reduce the row's sums across the 64 lanes of the wave
+        // reduce the row's sums across the group's lanes within the wave
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-#pragma unroll
-            for (int mask = 32; mask >= 1; mask >>= 1)
+            for (int mask = first_mask; mask >= 1; mask >>= 1)
                 acc[r].merge_from_lane(mask);
-            if (lane == 0)
-                red[wave][4 * t + r] = acc[r].value();
+            if (leader)
+                red[slot * slot_len + 4 * t + r] = acc[r].value();
         }
     }
 
-    // then across the waves of the workgroup
+    // then across the waves of a group, one lane per block row (per row of
+    // the matrix for the Fig. 7 sums)
     __syncthreads();
+    const uint32_t nslots = wide ? G >> 6 : 1u;
+    const uint32_t i = Acc::kPerProduct ? threadIdx.x >> 2 : threadIdx.x;
+    const uint32_t g = i % groups, t = i / groups, bi = bi0 + t * groups + g;
+    if (t >= rpg || bi >= bi_end)
+        return;
+    const uint32_t s0 = wide ? g * nslots : g;
+    auto emit = [&](uint32_t r, double v) {
+        const uint32_t local = (bi - bi_begin) * 4 + r;
+        if (nslab > 1)
+            part[(uint64_t)slab * ((bi_end - bi_begin) * 4) + local] = v;
+        else if (local >= skip && local - skip < nrows)
+            y[local - skip] = (float)v;
+    };
     if constexpr (Acc::kPerProduct) {
-        if (threadIdx.x < (uint32_t)(4 * nr)) {
-            const int k = threadIdx.x;
-            double s = red[0][k];
-#pragma unroll
-            for (int q = 1; q < kGemvThreads / 64; ++q)
-                s += red[q][k];
-            const uint32_t out_row = (bi0 - bi_begin) * 4 + k;
-            if (nslab == 1)
-                y[out_row] = (float)s;
-            else
-                part[(uint64_t)slab * ((bi_end - bi_begin) * 4) + out_row] = s;
-        }
-    } else if (threadIdx.x < nr) {
-        // one lane per block row: its four coefficient-row sums, then B
-        const int t = threadIdx.x;
+        const uint32_t r = threadIdx.x & 3u;
+        double v = red[s0 * slot_len + 4 * t + r];
+        for (uint32_t q = 1; q < nslots; ++q)
+            v += red[(s0 + q) * slot_len + 4 * t + r];
+        emit(r, v);
+    } else {
         double v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            v[r] = red[0][4 * t + r];
-#pragma unroll
-            for (int q = 1; q < kGemvThreads / 64; ++q)
-                v[r] += red[q][4 * t + r];
+            v[r] = red[s0 * slot_len + 4 * t + r];
+            for (uint32_t q = 1; q < nslots; ++q)
+                v[r] += red[(s0 + q) * slot_len + 4 * t + r];
         }
         lin_inv_lift<double>(v[0], v[1], v[2], v[3]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t out_row = (bi0 + t - bi_begin) * 4 + r;
-            if (nslab == 1)
-                y[out_row] = (float)v[r];
-            else
-                part[(uint64_t)slab * ((bi_end - bi_begin) * 4) + out_row] = v[r];
-        }
+        for (int r = 0; r < 4; ++r)
+            emit((uint32_t)r, v[r]);
     }
 }
 
@@ -383,7 +430,7 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                                                             float* __restrict__ Y, uint32_t ldy,
                                                             double* __restrict__ part, uint32_t nbc,
                                                             uint32_t bi_begin, uint32_t bi_end, uint32_t slab_bc,
-                                                            uint32_t nslab)
+                                                            uint32_t nslab, uint32_t cols, uint32_t nrows_out)
 {
     using UT = MrhsUt<NT>;
     __shared__ uint32_t lds[kMrhsThreads * kStagedWords<NW>];
@@ -420,19 +467,21 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
             const uint32_t rhs = (uint32_t)i >> 4, bcol = (uint32_t)i & 15u;
             float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f;
             if (rhs < k && cb + bcol < bc1) {
-                const uint64_t o = (uint64_t)rhs * ldu + 4ull * (cb + bcol);
+                // zero past the last column (the partial last block column)
+                const uint32_t j = 4 * (cb + bcol), nv = cols - j < 4u ? cols - j : 4u;
+                const uint64_t o = (uint64_t)rhs * ldu + j;
                 if constexpr (BF16U) {
                     const uint16_t* U = static_cast<const uint16_t*>(Uv) + o;
                     u0 = bf16_to_float(U[0]);
-                    u1 = bf16_to_float(U[1]);
-                    u2 = bf16_to_float(U[2]);
-                    u3 = bf16_to_float(U[3]);
+                    u1 = nv > 1 ? bf16_to_float(U[1]) : 0.f;
+                    u2 = nv > 2 ? bf16_to_float(U[2]) : 0.f;
+                    u3 = nv > 3 ? bf16_to_float(U[3]) : 0.f;
                 } else {
                     const float* U = static_cast<const float*>(Uv) + o;
                     u0 = U[0];
-                    u1 = U[1];
-                    u2 = U[2];
-                    u3 = U[3];
+                    u1 = nv > 1 ? U[1] : 0.f;
+                    u2 = nv > 2 ? U[2] : 0.f;
+                    u3 = nv > 3 ? U[3] : 0.f;
                 }
             }
             float ut[4];
@@ -531,17 +580,19 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
             const uint32_t r = (bw - bi_begin) * 4 + 4 * (lane >> 4) + j;
             if (r >= nrows)
                 continue;
-            if (nslab == 1)
-                Y[(uint64_t)rhs * ldy + r] = (float)sum[n][j];
-            else
+            if (nslab > 1)
                 part[((uint64_t)slab * k + rhs) * nrows + r] = sum[n][j];
+            else if (r < nrows_out)
+                Y[(uint64_t)rhs * ldy + r] = (float)sum[n][j];
         }
     }
 }
 
-// Slab partials [nslab][k][nrows] -> Y (k x nrows, leading dimension ldy).
+// Slab partials [nslab][k][part_rows] -> Y (k x nrows, leading dimension
+// ldy; nrows <= part_rows: the block-rows' padding is not written).
 __global__ void __launch_bounds__(kThreads) reduce_slabs_batched_kernel(const double* __restrict__ part,
-                                                                        uint32_t nrows, uint32_t k, uint32_t nslab,
+                                                                        uint32_t part_rows, uint32_t nrows,
+                                                                        uint32_t k, uint32_t nslab,
                                                                         float* __restrict__ Y, uint32_t ldy)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -550,20 +601,35 @@ __global__ void __launch_bounds__(kThreads) reduce_slabs_batched_kernel(const do
     const uint32_t rhs = (uint32_t)(i / nrows), r = (uint32_t)(i % nrows);
     double s = 0.0;
     for (uint32_t q = 0; q < nslab; ++q)
-        s += part[((uint64_t)q * k + rhs) * nrows + r];
+        s += part[((uint64_t)q * k + rhs) * part_rows + r];
     Y[(uint64_t)rhs * ldy + r] = (float)s;
 }
 
-__global__ void __launch_bounds__(kThreads) reduce_slabs_kernel(const double* __restrict__ part, uint32_t nrows,
-                                                                uint32_t nslab, float* __restrict__ y)
+// Slab partials [nslab][part_rows] -> y[0, nrows), y[i] from partial row
+// skip + i.  A wave takes 64 / L consecutive rows; the L lanes of a row sum
+// a stride of its slabs each (a load reads 64 / L consecutive rows of L
+// slabs), then add their sums in a fixed tree (the same order on every run).
+template <int L>
+__global__ void __launch_bounds__(kThreads) reduce_slabs_kernel(const double* __restrict__ part, uint32_t part_rows,
+                                                                uint32_t skip, uint32_t nrows, uint32_t nslab,
+                                                                float* __restrict__ y)
 {
-    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= nrows)
-        return;
-    double s = 0.0;
-    for (uint32_t k = 0; k < nslab; ++k)
-        s += part[(uint64_t)k * nrows + i];
-    y[i] = (float)s;
+    constexpr uint32_t R = 64 / L;
+    const uint32_t lane = threadIdx.x & 63, rr = lane % R, phase = lane / R;
+    const uint64_t nwaves = ((uint64_t)nrows + R - 1) / R;
+    const uint64_t wstride = (uint64_t)gridDim.x * (kThreads / 64);
+    for (uint64_t w = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) / 64; w < nwaves; w += wstride) {
+        const uint64_t i = w * R + rr;
+        double s = 0.0;
+        if (i < nrows)
+            for (uint32_t q = phase; q < nslab; q += L)
+                s += part[(uint64_t)q * part_rows + skip + i];
+#pragma unroll
+        for (uint32_t mask = 32; mask >= R; mask >>= 1)
+            s += __shfl_xor(s, (int)mask, 64);
+        if (i < nrows && phase == 0)
+            y[i] = (float)s;
+    }
 }
 
 unsigned grid_for(uint64_t items, unsigned cap = 1u << 20)
@@ -584,27 +650,30 @@ hipError_t launch_decode_blocks(const uint32_t* s, uint64_t b0, uint64_t n, floa
 template <int NW>
 hipError_t launch_decode_matrix(const uint32_t* s, uint32_t rows, uint32_t cols, float* out, hipStream_t st)
 {
-    const uint64_t nb = (uint64_t)(rows / 4) * (cols / 4);
-    hipLaunchKernelGGL(decode_matrix_kernel<NW>, dim3(grid_for(nb, 65536)), dim3(kThreads), 0, st, s, cols / 4,
-                       nb, cols, out);
+    const uint32_t nbc = (cols + 3) / 4;
+    const uint64_t nb = (uint64_t)((rows + 3) / 4) * nbc;
+    hipLaunchKernelGGL(decode_matrix_kernel<NW>, dim3(grid_for(nb, 65536)), dim3(kThreads), 0, st, s, nbc, nb, rows,
+                       cols, out);
     return hipGetLastError();
 }
 
 template <int NW>
 hipError_t launch_encode(const float* M, uint32_t rows, uint32_t cols, uint32_t* s, uint32_t* bad, hipStream_t st)
 {
-    const uint64_t nb = (uint64_t)(rows / 4) * (cols / 4);
-    hipLaunchKernelGGL(encode_kernel<NW>, dim3(grid_for(nb, 65536)), dim3(kThreads), 0, st, M, cols / 4, cols, nb,
-                       s, bad);
+    const uint32_t nbc = (cols + 3) / 4;
+    const uint64_t nb = (uint64_t)((rows + 3) / 4) * nbc;
+    hipLaunchKernelGGL(encode_kernel<NW>, dim3(grid_for(nb, 65536)), dim3(kThreads), 0, st, M, nbc, rows, cols, nb, s,
+                       bad);
     return hipGetLastError();
 }
 
-template <int NW, int TR, typename Acc>
+template <int NW, typename Acc>
 hipError_t launch_gemv_t(const GemvPlan& pl, const uint32_t* s, const float* u, float* y, double* part,
                          hipStream_t st)
 {
-    hipLaunchKernelGGL((gemv_kernel<NW, TR, Acc>), dim3(pl.ntiles * pl.nslab), dim3(kGemvThreads), 0, st, s, u, y, part,
-                       pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab);
+    hipLaunchKernelGGL((gemv_kernel<NW, Acc>), dim3(pl.ntiles * pl.nslab), dim3(kGemvThreads), 0, st, s, u, y, part,
+                       pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab, pl.cols, pl.nrows, pl.lg, pl.rpg,
+                       pl.skip);
     return hipGetLastError();
 }
 
@@ -612,13 +681,21 @@ template <int NW>
 hipError_t launch_gemv(const GemvPlan& pl, AccMode mode, const uint32_t* s, const float* u, float* y, double* part,
                        hipStream_t st)
 {
-    hipError_t e = mode == AccMode::TwoSum  ? launch_gemv_t<NW, kGemvTileRows, TwoSumAcc>(pl, s, u, y, part, st)
-                   : mode == AccMode::PaperMp ? launch_gemv_t<NW, kGemvTileRows, PaperMpAcc>(pl, s, u, y, part, st)
-                                              : launch_gemv_t<NW, kGemvTileRows, Fp64Acc>(pl, s, u, y, part, st);
+    hipError_t e = mode == AccMode::TwoSum  ? launch_gemv_t<NW, TwoSumAcc>(pl, s, u, y, part, st)
+                   : mode == AccMode::PaperMp ? launch_gemv_t<NW, PaperMpAcc>(pl, s, u, y, part, st)
+                                              : launch_gemv_t<NW, Fp64Acc>(pl, s, u, y, part, st);
     if (e != hipSuccess || pl.nslab == 1)
         return e;
-    const uint32_t nrows = (pl.bi_end - pl.bi_begin) * 4;
-    hipLaunchKernelGGL(reduce_slabs_kernel, dim3(grid_for(nrows)), dim3(kThreads), 0, st, part, nrows, pl.nslab, y);
+    const uint32_t pr = pl.part_rows();
+    if (pl.nslab <= 4)
+        hipLaunchKernelGGL(reduce_slabs_kernel<1>, dim3(grid_for(pl.nrows)), dim3(kThreads), 0, st, part, pr, pl.skip,
+                           pl.nrows, pl.nslab, y);
+    else if (pl.nslab <= 64)
+        hipLaunchKernelGGL(reduce_slabs_kernel<8>, dim3(grid_for((uint64_t)pl.nrows * 8)), dim3(kThreads), 0, st,
+                           part, pr, pl.skip, pl.nrows, pl.nslab, y);
+    else
+        hipLaunchKernelGGL(reduce_slabs_kernel<64>, dim3(grid_for((uint64_t)pl.nrows * 64)), dim3(kThreads), 0, st,
+                           part, pr, pl.skip, pl.nrows, pl.nslab, y);
     return hipGetLastError();
 }
 
@@ -627,7 +704,7 @@ hipError_t launch_mrhs_t(const MrhsPlan& pl, const uint32_t* s, const void* U, u
                          uint32_t ldy, double* part, hipStream_t st)
 {
     hipLaunchKernelGGL((mrhs_kernel<NW, BF, NT>), dim3(pl.ntiles * pl.nslab), dim3(kMrhsThreads), 0, st, s, U, ldu, k,
-                       Y, ldy, part, pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab);
+                       Y, ldy, part, pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab, pl.cols, pl.nrows);
     return hipGetLastError();
 }
 
@@ -650,9 +727,8 @@ hipError_t launch_mrhs(const MrhsPlan& pl, bool bf16, const uint32_t* s, const v
     }
     if (e != hipSuccess || pl.nslab == 1)
         return e;
-    const uint32_t nrows = (pl.bi_end - pl.bi_begin) * 4;
-    hipLaunchKernelGGL(reduce_slabs_batched_kernel, dim3(grid_for((uint64_t)nrows * k)), dim3(kThreads), 0, st, part,
-                       nrows, k, pl.nslab, Y, ldy);
+    hipLaunchKernelGGL(reduce_slabs_batched_kernel, dim3(grid_for((uint64_t)pl.nrows * k)), dim3(kThreads), 0, st,
+                       part, pl.part_rows(), pl.nrows, k, pl.nslab, Y, ldy);
     return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ _sig = {
     "wh_unload": ([_P, _U64], _I32),
     "wh_gemv": ([_P, _U64, _P, _P, _U32, _U32, _U32, _P], _I32),
     "wh_gemv_batched": ([_P, _U64, _P, ctypes.c_int, _U32, _U32, _P, _U32, _U32, _P], _I32),
+    "wh_gemv_host": ([_P, _P, _U32, _U32, _U32, _P, _P, _U32, _U32, _U32, _U32, _P], _I32),
     "wh_decode_debug": ([_P, _U64, _U64, _U64, _P, _P], _I32),
     "wh_decode": ([_P, _U64, _P, _P], _I32),
     "wh_encode": ([_P, _P, _U32, _U32, _U32, _P, _P, _P], _I32),
@@ -119,12 +120,26 @@ def wh_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
 # allocator cannot hand the memory to another tensor while the library still
 # reads it.
 _borrowed: dict = {}
+# (ctx, mat) -> (rows, cols): lets the wrappers check buffer sizes, which the
+# C ABI cannot see behind its raw pointers
+_shapes: dict = {}
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def _need(ok: bool, what: str) -> None:
+    if not ok:
+        raise ValueError(what)
 
 
 def wh_destroy(ctx: int) -> None:
     _check(_lib.wh_destroy(ctx), "wh_destroy")
     for key in [k for k in _borrowed if k[0] == ctx]:
         del _borrowed[key]
+    for key in [k for k in _shapes if k[0] == ctx]:
+        del _shapes[key]
 
 
 def wh_storage_bytes(rows: int, cols: int, fmt: int, rate: int = 0) -> int:
@@ -150,11 +165,13 @@ def wh_load_compressed(ctx: int, rows: int, cols: int, fmt: int, rate: int, data
     _check(_lib.wh_load_compressed(ctx, ctypes.byref(d), ptr, nbytes, where, ctypes.byref(h)), "wh_load_compressed")
     if where == WH_DEVICE:
         _borrowed[(ctx, h.value)] = data
+    _shapes[(ctx, h.value)] = (rows, cols)
     return h.value
 
 
 def wh_unload(ctx: int, mat: int) -> None:
     _check(_lib.wh_unload(ctx, mat), "wh_unload")
+    _shapes.pop((ctx, mat), None)
     # wh_unload frees after pending work on the library's side; a borrowed
     # buffer may still be read by work queued on the caller's streams, so
     # release it only once the device is idle
@@ -165,8 +182,39 @@ def wh_unload(ctx: int, mat: int) -> None:
 
 def wh_gemv(ctx: int, mat: int, u: torch.Tensor, y: torch.Tensor, row_begin: int, row_end: int,
             flags: int = WH_ACC_DEFAULT, stream=None) -> None:
+    shp = _shapes.get((ctx, mat))
+    if shp is not None:
+        _need(u.numel() >= shp[1], f"u holds {u.numel()} values, the matrix has {shp[1]} columns")
+        _need(y.numel() >= row_end - row_begin, f"y holds {y.numel()} values for {row_end - row_begin} rows")
     _check(_lib.wh_gemv(ctx, mat, _dptr(u, torch.float32, "u"), _dptr(y, torch.float32, "y"), row_begin, row_end,
                         flags, _stream(stream)), "wh_gemv")
+
+
+def wh_gemv_host(ctx: int, h_code, rows: int, cols: int, rate: int, u: torch.Tensor, y: torch.Tensor,
+                 row_begin: int = 0, row_end: int | None = None, chunk_rows: int = 0, flags: int = WH_ACC_DEFAULT,
+                 stream=None) -> None:
+    """y = M[row_begin:row_end] u for a WHZ1 matrix held in host memory.
+    `h_code`: the whole stream as a CPU uint8 tensor (page-locked for
+    overlapped copies) or a numpy array.  The binding keeps a reference to
+    the latest `h_code` of each context; the caller keeps it unchanged until
+    the work on `stream` has finished."""
+    import numpy as np
+    row_end = rows if row_end is None else row_end
+    if isinstance(h_code, torch.Tensor):
+        if h_code.is_cuda or not h_code.is_contiguous():
+            raise TypeError("h_code must be a contiguous CPU tensor or a numpy array")
+        ptr, nbytes = h_code.data_ptr(), _nbytes(h_code)
+    else:
+        if not isinstance(h_code, np.ndarray) or not h_code.flags.c_contiguous:
+            raise TypeError("h_code must be a contiguous CPU tensor or a numpy array")
+        ptr, nbytes = h_code.ctypes.data, h_code.nbytes
+    _need(nbytes >= stream_bytes(rows, cols, rate),
+          f"h_code holds {nbytes} bytes, the code takes {stream_bytes(rows, cols, rate)}")
+    _need(u.numel() >= cols, f"u holds {u.numel()} values, the matrix has {cols} columns")
+    _need(y.numel() >= max(row_end - row_begin, 0), f"y holds {y.numel()} values for {row_end - row_begin} rows")
+    _borrowed[(ctx, "host_code")] = h_code
+    _check(_lib.wh_gemv_host(ctx, ptr, rows, cols, rate, _dptr(u, torch.float32, "u"), _dptr(y, torch.float32, "y"),
+                             row_begin, row_end, chunk_rows, flags, _stream(stream)), "wh_gemv_host")
 
 
 def wh_gemv_batched(ctx: int, mat: int, U: torch.Tensor, Y: torch.Tensor, flags: int = WH_ACC_DEFAULT,
@@ -190,23 +238,31 @@ def wh_gemv_batched(ctx: int, mat: int, U: torch.Tensor, Y: torch.Tensor, flags:
 
 
 def wh_decode_debug(ctx: int, mat: int, block_begin: int, nblocks: int, out: torch.Tensor, stream=None) -> None:
+    _need(out.numel() >= 16 * nblocks, f"out holds {out.numel()} values for {nblocks} blocks")
     _check(_lib.wh_decode_debug(ctx, mat, block_begin, nblocks, _dptr(out, torch.float32, "out"), _stream(stream)),
            "wh_decode_debug")
 
 
 def wh_decode(ctx: int, mat: int, out: torch.Tensor, stream=None) -> None:
+    shp = _shapes.get((ctx, mat))
+    if shp is not None:
+        _need(out.numel() >= shp[0] * shp[1], f"out holds {out.numel()} values for a {shp[0]} x {shp[1]} matrix")
     _check(_lib.wh_decode(ctx, mat, _dptr(out, torch.float32, "out"), _stream(stream)), "wh_decode")
 
 
 def wh_encode(ctx: int, M: torch.Tensor, rate: int, stream_out: torch.Tensor, bad: torch.Tensor | None = None,
               stream=None) -> None:
     rows, cols = M.shape
+    _need(_nbytes(stream_out) >= stream_bytes(rows, cols, rate),
+          f"stream_out holds {_nbytes(stream_out)} bytes, the code takes {stream_bytes(rows, cols, rate)}")
     _check(_lib.wh_encode(ctx, _dptr(M, torch.float32, "M"), rows, cols, rate, _dptr(stream_out, name="stream_out"),
                           None if bad is None else _dptr(bad, torch.int32, "bad"), _stream(stream)), "wh_encode")
 
 
 def wh_quantize(ctx: int, M: torch.Tensor, fmt: int, out: torch.Tensor, stream=None) -> None:
     rows, cols = M.shape
+    _need(_nbytes(out) >= wh_storage_bytes(rows, cols, fmt),
+          f"out holds {_nbytes(out)} bytes, the format takes {wh_storage_bytes(rows, cols, fmt)}")
     _check(_lib.wh_quantize(ctx, _dptr(M, torch.float32, "M"), rows, cols, fmt, _dptr(out, name="out"),
                             _stream(stream)), "wh_quantize")
 

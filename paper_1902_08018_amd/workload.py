@@ -22,12 +22,13 @@ def build_stream(ctx: int, spec: synth.MatrixSpec, rate: int, chunk_rows: int = 
     chunk_rows = max(4, min(chunk_rows, spec.rows) // 4 * 4)
     scratch = torch.empty(chunk_rows * spec.cols, dtype=torch.float32, device=device)
     bad = torch.zeros(1, dtype=torch.int32, device=device)
-    per_row = wh.stream_bytes(4, spec.cols, rate) // 4  # bytes of stream per matrix row
-    for r0 in range(0, spec.rows, chunk_rows):
+    per_block_row = wh.stream_bytes(4, spec.cols, rate)  # bytes of stream per 4 matrix rows
+    for r0 in range(0, spec.rows, chunk_rows):  # chunks start on block-rows; the last may be partial
         r1 = min(spec.rows, r0 + chunk_rows)
         m = scratch[: (r1 - r0) * spec.cols]
         synth.matrix_rows_device(spec, r0, r1, m, table)
-        wh.wh_encode(ctx, m.view(r1 - r0, spec.cols), rate, out[r0 * per_row: r1 * per_row], bad)
+        wh.wh_encode(ctx, m.view(r1 - r0, spec.cols), rate,
+                     out[r0 // 4 * per_block_row: (r1 + 3) // 4 * per_block_row], bad)
     torch.cuda.synchronize()
     if int(bad.item()) != 0:
         raise RuntimeError(f"{int(bad.item())} blocks held NaN/Inf")

@@ -119,6 +119,19 @@ def test_dense_gemv_small_config(gpu_ctx, small_dense, fmt, flags):
     wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u).cuda(), y2, 2048, 3068, flags)
     torch.cuda.synchronize()
     assert rel_l2(y2.cpu().numpy(), ref_q[2048:3068]) <= 1e-6
+    # a range that starts and ends inside block rows: row-major storage takes
+    # it; block-scaled FP8 works on whole 4 x 4 tiles and rejects it
+    if fmt == wh.WH_FMT_FP8E4M3_BS4:
+        with pytest.raises(wh.WhError) as ei:
+            wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u).cuda(), y2, 2049, 3067, flags)
+        assert ei.value.status == wh.WH_ERR_SHAPE
+    else:
+        y3 = torch.full((1020,), -7.0, dtype=torch.float32, device="cuda")
+        wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u).cuda(), y3, 2049, 3067, flags)
+        torch.cuda.synchronize()
+        y3h = y3.cpu().numpy()
+        assert rel_l2(y3h[:1018], ref_q[2049:3067]) <= 1e-6
+        assert np.all(y3h[1018:] == -7.0)
     wh.wh_unload(gpu_ctx, mat)
 
 

@@ -1,0 +1,218 @@
+"""GPU parity for matrices whose sides are not multiples of 4: the partial
+blocks at the bottom and right edges are coded edge-padded, and every
+output stops at the matrix's edge.
+
+  encode / decode   byte-exact stream and bit-exact decode against the oracle
+                    (which pins the padding against numpy's "edge" pad)
+  fused GEMV        within 1e-6 relative L2 of the FP64 oracle, on row ranges
+                    that start and end inside block rows; y is not written
+                    past the range; every launch shape (forced through the
+                    tuning variables) gives the same
+  Fig. 7 mode       within 1 FP32 ulp of the oracle's sequential Fig. 7
+  multi-RHS         FP32 U within 1e-6, BF16 U within 2e-3 (at least 258
+                    columns: the BF16 rounding errors average over the terms)
+  slit shapes       the paper's 378 x 256000 slit and its transpose, rate 8,
+                    against the multi-threaded FP64 oracle; 378-row slit
+                    windows of a resident 2116 x 256000 field matrix
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1902_08018_amd import synth, wh, workload
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1), (3, 5), (7, 13), (378, 262), (130, 378), (5, 1029), (1030, 6)]
+
+
+def rel_l2(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    return float(np.linalg.norm(y - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def case(rows, cols, rate, seed=31):
+    spec = synth.MatrixSpec(rows, cols, 32, 8.0, seed=seed)
+    M = synth.matrix(spec)
+    s = oracle.encode(M, rate)
+    return spec, M, s
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("rate", [8, 16])
+def test_encode_decode_match_oracle(gpu_ctx, shape, rate):
+    rows, cols = shape
+    spec, M, s = case(rows, cols, rate)
+    Md = torch.from_numpy(M).cuda()
+    st = torch.full((s.size,), 0x5A, dtype=torch.uint8, device="cuda")
+    wh.wh_encode(gpu_ctx, Md, rate, st)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy(), s)
+    mat = wh.wh_load_compressed(gpu_ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, st)
+    out = torch.full((rows + 1, cols), -7.0, device="cuda")  # one guard row past the matrix
+    wh.wh_decode(gpu_ctx, mat, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = oracle.decode(s, rows, cols, rate)
+    assert np.array_equal(got[:rows].view(np.uint32), want.view(np.uint32))
+    assert np.all(got[rows:] == -7.0)
+    wh.wh_unload(gpu_ctx, mat)
+
+
+def ranges(rows):
+    """Row ranges of a matrix: all rows, ranges that start and end inside
+    block rows, one row, and an empty range."""
+    out = [(0, rows), (rows // 3, rows - rows // 4), (rows - 1, rows), (rows // 2, rows // 2)]
+    if rows > 6:
+        out += [(1, 2), (3, rows - 2), (5, 6)]
+    return out
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("rate", [8, 16])
+@pytest.mark.parametrize("flags", [wh.WH_ACC_DEFAULT, wh.WH_ACC_TWOSUM])
+def test_gemv_partial_blocks(gpu_ctx, shape, rate, flags):
+    rows, cols = shape
+    spec, M, s = case(rows, cols, rate)
+    mat = wh.wh_load_compressed(gpu_ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, s)  # host copy
+    u_np = synth.uniform(cols, seed=5)
+    u = torch.from_numpy(u_np).cuda()
+    ref = oracle.gemv_fp64(s, rows, cols, rate, u_np)
+    for rb, re in ranges(rows):
+        y = torch.full((re - rb + 3,), -7.0, device="cuda")
+        wh.wh_gemv(gpu_ctx, mat, u, y, rb, re, flags)
+        torch.cuda.synchronize()
+        yh = y.cpu().numpy()
+        if re > rb:
+            assert rel_l2(yh[:re - rb], ref[rb:re]) <= 1e-6, (rb, re)
+        assert np.all(yh[re - rb:] == -7.0), (rb, re)  # nothing written past the range
+    wh.wh_unload(gpu_ctx, mat)
+
+
+@pytest.mark.parametrize("lanes,rpg,slabs", [(4, 1, 2), (8, 2, 1), (8, 1, 70), (16, 1, 1), (16, 4, 3), (16, 1, 40),
+                                             (32, 2, 1), (32, 4, 2), (64, 4, 2), (128, 1, 1), (256, 2, 5),
+                                             (512, 4, 1), (512, 1, 7)])
+def test_gemv_launch_shapes(monkeypatch, lanes, rpg, slabs):
+    """Every launch shape of the fused GEMV (lanes per block row, block rows
+    per lane group, column slabs), forced through the tuning variables, gives
+    the oracle's y on row ranges that start and end inside block rows."""
+    monkeypatch.setenv("WH_GEMV_LANES", str(lanes))
+    monkeypatch.setenv("WH_GEMV_ROWS", str(rpg))
+    monkeypatch.setenv("WH_GEMV_SLABS", str(slabs))
+    ctx = wh.wh_create(0, 0)
+    try:
+        for rows, cols in [(378, 262), (130, 1030), (1030, 6), (61, 4096)]:
+            spec, M, s = case(rows, cols, 8, seed=rows + cols)
+            mat = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, s)
+            u_np = synth.uniform(cols, seed=9)
+            u = torch.from_numpy(u_np).cuda()
+            ref = oracle.gemv_fp64(s, rows, cols, 8, u_np)
+            ref_mp = oracle.gemv_paper_mp(s, rows, cols, 8, u_np).astype(np.float64)
+            for rb, re in [(0, rows), (3, rows - 2), (rows - 5, rows)]:
+                for flags in (wh.WH_ACC_DEFAULT, wh.WH_ACC_TWOSUM, wh.WH_PAPER_MP):
+                    y = torch.full((re - rb + 2,), -7.0, device="cuda")
+                    wh.wh_gemv(ctx, mat, u, y, rb, re, flags)
+                    torch.cuda.synchronize()
+                    yh = y.cpu().numpy()
+                    if flags == wh.WH_PAPER_MP:
+                        want = ref_mp[rb:re]
+                        ulp = np.spacing(np.abs(want).astype(np.float32)).astype(np.float64)
+                        assert np.all(np.abs(yh[:re - rb] - want) <= ulp), (rows, cols, rb, re)
+                    else:
+                        assert rel_l2(yh[:re - rb], ref[rb:re]) <= 1e-6, (rows, cols, rb, re, flags)
+                    assert np.all(yh[re - rb:] == -7.0)
+            wh.wh_unload(ctx, mat)
+    finally:
+        wh.wh_destroy(ctx)
+
+
+@pytest.mark.parametrize("shape", [(7, 13), (378, 262), (5, 1029)])
+def test_gemv_paper_mp_partial_blocks(gpu_ctx, shape):
+    rows, cols = shape
+    spec, M, s = case(rows, cols, 8)
+    mat = wh.wh_load_compressed(gpu_ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, s)
+    u_np = synth.uniform(cols, seed=6)
+    ref = oracle.gemv_paper_mp(s, rows, cols, 8, u_np).astype(np.float64)
+    y = torch.empty(rows, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u_np).cuda(), y, 0, rows, wh.WH_PAPER_MP)
+    torch.cuda.synchronize()
+    g = y.cpu().numpy().astype(np.float64)
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(g - ref) <= ulp)
+    wh.wh_unload(gpu_ctx, mat)
+
+
+# The BF16 bound is statistical: both operands of the contraction carry RNE
+# errors of up to 2^-8 relative, which average out only over enough terms, so
+# the BF16 cases have a few hundred columns.
+MRHS_CASES = ([(shape, k, False) for shape in [(7, 13), (378, 262), (130, 378), (1030, 6)] for k in (5, 17)] +
+              [(shape, k, True) for shape in [(378, 262), (130, 378), (1030, 258)] for k in (5, 40)])
+
+
+@pytest.mark.parametrize("shape,k,bf16", MRHS_CASES)
+def test_mrhs_partial_blocks(gpu_ctx, shape, k, bf16):
+    rows, cols = shape
+    spec, M, s = case(rows, cols, 8)
+    Mhat = oracle.decode(s, rows, cols, 8).astype(np.float64)
+    mat = wh.wh_load_compressed(gpu_ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, s)
+    ldu, ldy = cols + 3, rows + 5
+    Up = np.zeros((k, ldu), dtype=np.float32)
+    Up[:, :cols] = synth.uniform(k * cols, seed=7).reshape(k, cols)
+    Up[:, cols:] = 1e30  # padding of U rows must never be read
+    Ut = torch.from_numpy(Up).cuda()
+    if bf16:
+        Ut = Ut.to(torch.bfloat16)
+    Uref = Ut.float().cpu().numpy().astype(np.float64)[:, :cols]
+    Y = torch.full((k, ldy), -7.0, device="cuda")
+    wh.wh_gemv_batched(gpu_ctx, mat, Ut, Y)
+    torch.cuda.synchronize()
+    Yh = Y.cpu().numpy()
+    ref = Uref @ Mhat.T
+    err = np.linalg.norm(Yh[:, :rows] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= (2e-3 if bf16 else 1e-6)
+    assert np.all(Yh[:, rows:] == -7.0)
+    wh.wh_unload(gpu_ctx, mat)
+
+
+@pytest.mark.parametrize("rows,cols", [(378, 256000), (256000, 378)])
+def test_slit_shapes(gpu_ctx, rows, cols):
+    """The paper's slit matrix (Sec. 4.4: 378 x 256000) and its transpose,
+    generated and encoded on the GPU at rate 8, against the FP64 oracle."""
+    spec = synth.MatrixSpec(rows, cols, 512, 32.0, seed=3)
+    st = workload.build_stream(gpu_ctx, spec, 8)
+    s = st.cpu().numpy()
+    assert np.array_equal(s, oracle.encode(synth.matrix(spec), 8))
+    mat = wh.wh_load_compressed(gpu_ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, st)
+    u_np = synth.uniform(cols, seed=8)
+    y = torch.empty(rows, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u_np).cuda(), y, 0, rows)
+    torch.cuda.synchronize()
+    ref = oracle.gemv_fp64(s, rows, cols, 8, u_np, nthreads=8)
+    assert rel_l2(y.cpu().numpy(), ref) <= 1e-6
+    wh.wh_unload(gpu_ctx, mat)
+
+
+def test_field_slit_windows(gpu_ctx):
+    """A field matrix (2116 x 256000, about the paper's 2067 MB of FP32,
+    Sec. 3) resident at rate 8, and 378-row slit windows at offsets that
+    start inside block rows (Fig. 2, Eq. 2 over the slit rows)."""
+    rows, cols = 2116, 256000
+    spec = synth.MatrixSpec(rows, cols, 512, 32.0, seed=4)
+    st = workload.build_stream(gpu_ctx, spec, 8)
+    s = st.cpu().numpy()
+    per_block_row = oracle.stream_nbytes(4, cols, 8)
+    assert np.array_equal(s[100 * per_block_row: 104 * per_block_row],
+                          oracle.encode(synth.matrix_rows(spec, 400, 416), 8))
+    mat = wh.wh_load_compressed(gpu_ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, st)
+    u_np = synth.uniform(cols, seed=10)
+    u = torch.from_numpy(u_np).cuda()
+    for r0 in (0, 401, 1023, rows - 378):
+        y = torch.full((380,), -7.0, device="cuda")
+        wh.wh_gemv(gpu_ctx, mat, u, y, r0, r0 + 378)
+        torch.cuda.synchronize()
+        ref = oracle.gemv_fp64(s, rows, cols, 8, u_np, row_begin=r0, row_end=r0 + 378, nthreads=8)
+        yh = y.cpu().numpy()
+        assert rel_l2(yh[:378], ref) <= 1e-6, r0
+        assert np.all(yh[378:] == -7.0)
+    wh.wh_unload(gpu_ctx, mat)

@@ -218,8 +218,9 @@ def test_gemv_argument_errors(gpu_ctx):
     s = np.zeros(oracle.stream_nbytes(16, 32, 8), dtype=np.uint8)
     mat, keep = load_stream(gpu_ctx, s, 16, 32, 8)
     u = torch.rand(32, device="cuda")
-    y = torch.empty(16, device="cuda")
-    for args, code in [((0, 6), wh.WH_ERR_SHAPE), ((4, 20), wh.WH_ERR_SHAPE), ((8, 4), wh.WH_ERR_SHAPE)]:
+    y = torch.empty(32, device="cuda")
+    for args, code in [((0, 17), wh.WH_ERR_SHAPE), ((4, 20), wh.WH_ERR_SHAPE), ((8, 4), wh.WH_ERR_SHAPE),
+                       ((17, 17), wh.WH_ERR_SHAPE)]:
         with pytest.raises(wh.WhError) as ei:
             wh.wh_gemv(gpu_ctx, mat, u, y, *args)
         assert ei.value.status == code

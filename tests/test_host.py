@@ -54,6 +54,9 @@ class Desc(ctypes.Structure):
     (4096, 4096, 1, 16, 2 * 4096 * 4096),
     (65536, 65536, 1, 8, 65536 * 65536),
     (8, 12, 1, 2, 6 * 4),                         # 6 blocks x 4 bytes
+    (6, 8, 1, 8, 4 * 16),                         # partial block-row: 2 x 2 blocks
+    (378, 256000, 1, 8, 95 * 64000 * 16),         # the paper's slit matrix, edge-padded to 380 rows
+    (1, 1, 1, 16, 32),
     (64, 64, 2, 0, 64 * 64 * 4),
     (64, 64, 3, 0, 64 * 64 * 2),
     (64, 64, 4, 0, 64 * 64 * 2),
@@ -67,7 +70,7 @@ def test_storage_bytes(lib, rows, cols, fmt, rate, want):
 
 
 @pytest.mark.parametrize("rows,cols,fmt,rate,code", [
-    (6, 8, 1, 8, -2), (8, 6, 2, 0, -2), (0, 8, 1, 8, -2),   # shape
+    (6, 8, 2, 0, -2), (8, 6, 3, 0, -2), (0, 8, 1, 8, -2),   # shape (dense formats: whole 4 x 4 tiles)
     (8, 8, 1, 7, -3), (8, 8, 1, 34, -3), (8, 8, 9, 0, -3),  # odd / too large rate, unknown format
 ])
 def test_storage_bytes_errors(lib, rows, cols, fmt, rate, code):
