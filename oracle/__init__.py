@@ -9,6 +9,7 @@ Contents:
   twin.py       pure-Python twin of the codec for tiny inputs
   metrics.py    compression-error and GEMV-error metrics (Table 2 conventions)
   quant.py      reference quantisers for the reduced-precision storage formats
+  thermal.py    the thermal step of Eq. 1 (sparse A T + diagonal B u), FP64
 """
 from __future__ import annotations
 

@@ -30,7 +30,7 @@ _HOST_LIB = os.path.join(_HERE, "libwhsynth.so")
 _DEV_SRC = os.path.join(_CSRC, "synth_dev.hip")
 _DEV_LIB = os.path.join(_HERE, "libwhsynth_dev.so")
 
-STREAM_NOISE, STREAM_U, STREAM_UBATCH, STREAM_TRACE = 0, 1, 2, 3
+STREAM_NOISE, STREAM_U, STREAM_UBATCH, STREAM_TRACE, STREAM_THERMAL = 0, 1, 2, 3, 4
 
 
 @dataclass(frozen=True)
@@ -147,6 +147,87 @@ def u_vector(spec: MatrixSpec) -> np.ndarray:
 def u_batch(spec: MatrixSpec, k: int) -> np.ndarray:
     """k dose vectors (k, cols): row r is elements [r*cols, (r+1)*cols) of stream 2."""
     return uniform(k * spec.cols, spec.seed, STREAM_UBATCH).reshape(k, spec.cols)
+
+
+# ------------------------------------------------------ thermal system
+# Stand-in for the thermal model's matrices (Sec. 2.1, Eq. 1: A sparse, B
+# diagonal, about 3.7e5 temperatures updated every millisecond), which are not
+# given: an explicit one-millisecond step of heat conduction on an nx x ny
+# mesh with a lumped (diagonal) heat capacity c_i in [1, 2) per cell and a
+# conductance per mesh edge, insulated at the border:
+#
+#     A = I - dt C^-1 K,   B = dt C^-1,
+#
+# K the weighted graph Laplacian of the mesh.  Off-diagonal entries are
+# r_ij = 0.2 * kappa_e / c_i with kappa_e in [0.5, 1) (so every diagonal entry
+# stays >= 0.2), rounded once to FP32.  C A = C - dt K is symmetric, so A is
+# not (unless all capacities are equal) and c^T A = c^T: heat is conserved.
+# Rows list their columns in ascending order (north, west, self, east,
+# south).  The source term u_k is a Gaussian dose spot that moves along the
+# mesh's middle row, 3.7 cells per step.
+
+@dataclass(frozen=True)
+class ThermalSpec:
+    nx: int
+    ny: int
+    seed: int = 0
+    dt: float = 1e-3
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+
+# about 3.7e5 temperatures, as in the paper's thermal model
+THERMAL = ThermalSpec(608, 608)
+
+
+def thermal_capacity(spec: ThermalSpec) -> np.ndarray:
+    """c_i in [1, 2), FP64 (the generator's own value, before rounding)."""
+    nh, nv = spec.ny * (spec.nx - 1), (spec.ny - 1) * spec.nx
+    return 1.0 + uniform(spec.n, spec.seed, STREAM_THERMAL, nh + nv).astype(np.float64)
+
+
+def thermal_system(spec: ThermalSpec):
+    """CSR (row_ptr uint32 [n+1], col uint32 [nnz], val float32 [nnz]) of A
+    and the diagonal of B (float32 [n])."""
+    nx, ny, n = spec.nx, spec.ny, spec.n
+    nh, nv = ny * (nx - 1), (ny - 1) * nx
+    kh = 0.5 + 0.5 * uniform(nh, spec.seed, STREAM_THERMAL, 0).astype(np.float64)   # (x,y)-(x+1,y): y*(nx-1)+x
+    kv = 0.5 + 0.5 * uniform(nv, spec.seed, STREAM_THERMAL, nh).astype(np.float64)  # (x,y)-(x,y+1): y*nx+x
+    cap = thermal_capacity(spec)
+    i = np.arange(n, dtype=np.int64)
+    x, y = i % nx, i // nx
+    has = np.stack([y > 0, x > 0, np.ones(n, bool), x < nx - 1, y < ny - 1], axis=1)
+    nbr = np.stack([i - nx, i - 1, i, i + 1, i + nx], axis=1)
+    kap = np.zeros((n, 5))
+    kap[:, 0] = np.where(has[:, 0], kv[np.clip((y - 1) * nx + x, 0, max(nv - 1, 0))] if nv else 0.0, 0.0)
+    kap[:, 1] = np.where(has[:, 1], kh[np.clip(y * (nx - 1) + x - 1, 0, max(nh - 1, 0))] if nh else 0.0, 0.0)
+    kap[:, 3] = np.where(has[:, 3], kh[np.clip(y * (nx - 1) + x, 0, max(nh - 1, 0))] if nh else 0.0, 0.0)
+    kap[:, 4] = np.where(has[:, 4], kv[np.clip(y * nx + x, 0, max(nv - 1, 0))] if nv else 0.0, 0.0)
+    r = 0.2 * kap / cap[:, None]
+    r[:, 2] = 1.0 - r.sum(axis=1)
+    counts = has.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.uint32)
+    row_ptr[1:] = np.cumsum(counts)
+    col = nbr[has].astype(np.uint32)
+    val = r[has].astype(np.float32)
+    b = (spec.dt / cap).astype(np.float32)
+    return row_ptr, col, val, b
+
+
+def thermal_source(spec: ThermalSpec, step: int, sigma: float = 12.0) -> np.ndarray:
+    """u_k (float32 [n]): a unit Gaussian spot centred at
+    (3.7 k mod nx, ny / 2)."""
+    i = np.arange(spec.n, dtype=np.int64)
+    x, y = (i % spec.nx).astype(np.float64), (i // spec.nx).astype(np.float64)
+    cx, cy = (3.7 * step) % spec.nx, spec.ny / 2.0
+    return np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2.0 * sigma * sigma)).astype(np.float32)
+
+
+def thermal_initial(spec: ThermalSpec) -> np.ndarray:
+    """T_0 (float32 [n]): 20 plus a small seeded ripple."""
+    return (20.0 + 0.01 * uniform(spec.n, spec.seed, STREAM_THERMAL, 1 << 40).astype(np.float64)).astype(np.float32)
 
 
 # ---------------------------------------------------------------- device
