@@ -121,7 +121,6 @@ def bench_precision(ctx, spec, us, y, steps):
         if fmt != wh.WH_FMT_F32:
             del store
     del dense
-    torch.cuda.empty_cache()
     return res
 
 
@@ -183,7 +182,6 @@ def bench_slit_field(ctx, rate, steps):
             entry["dense_f32"] = {"ms": round(msd, 4), "gflops": round(flop / (msd * 1e-3) / 1e9, 1),
                                   "hbm_frac": round(4.0 * prow * cols / (msd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         res[name] = entry
-        torch.cuda.empty_cache()
     spec = synth.MatrixSpec(FIELD_ROWS, FIELD_COLS, 512, 32.0, seed=4)
     st = workload.build_stream(ctx, spec, rate)
     m = wh.wh_load_compressed(ctx, FIELD_ROWS, FIELD_COLS, wh.WH_FMT_ZFP_FIXED_RATE, rate, st)
@@ -203,7 +201,6 @@ def bench_slit_field(ctx, rate, steps):
         "field_stream_gb": round(st.numel() / 1e9, 3), "window_starts": "0, 7, 14, ... (mod 1739)"}
     wh.wh_unload(ctx, m)
     del st
-    torch.cuda.empty_cache()
     res["rate"] = rate
     res["paper_context"] = "P100 mixed-precision GEMV, uncompressed: 198.3 / 65.9 / 202.6 GFLOP/s (wide / tall / square)"
     return res
@@ -231,18 +228,25 @@ def bench_host_pipeline(ctx, rate, steps):
         t_fused = time_call(lambda i: wh.wh_gemv(ctx, m, u, y, 0, rows), steps, 2)
         wh.wh_unload(ctx, m)
         dbuf = torch.empty_like(st)
-        del st
         t_copy = time_call(lambda i: dbuf.copy_(h, non_blocking=True), 3, 1)
-        del dbuf
-        torch.cuda.empty_cache()
+        # no torch.cuda.empty_cache() here: for ~150 ms after a large device
+        # allocation is freed, host-to-device copies run at about half speed
+        del dbuf, st
         link_gbs = h.numel() / (t_copy * 1e-3) / 1e9
         entry = {"compressed_gb": round(h.numel() / 1e9, 3), "uncompressed_gb": round(4.0 * rows * cols / 1e9, 3),
                  "R": 32 / rate, "link_h2d_gbs": round(link_gbs, 1),
                  "t_copy_compressed_ms": round(t_copy, 3), "t_fused_resident_ms": round(t_fused, 3)}
-        for chunk_rows, label in ((0, "chunk_32MiB"), (4 * max(1, (8 << 20) // wh.stream_bytes(4, cols, rate)),
-                                                        "chunk_8MiB")):
-            call = (lambda i: wh.wh_gemv_host(ctx, h, rows, cols, rate, u, y, 0, rows, chunk_rows))
-            period = time_call(call, 3, 1)
+        chunk8 = 4 * max(1, (8 << 20) // wh.stream_bytes(4, cols, rate))
+        # settle: after large device frees the pipeline's copies have run
+        # slowly for some calls; half a second of calls before timing
+        t_end = time.perf_counter() + 0.5
+        while time.perf_counter() < t_end:
+            wh.wh_gemv_host(ctx, h, rows, cols, rate, u, y)
+            torch.cuda.synchronize()
+        for chunk_rows, flags, label in ((0, 0, "chunk_32MiB"), (chunk8, 0, "chunk_8MiB"),
+                                         (0, wh.WH_HOST_DIRECT, "direct")):
+            call = (lambda i: wh.wh_gemv_host(ctx, h, rows, cols, rate, u, y, 0, rows, chunk_rows, flags))
+            period = time_call(call, 3, 2)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             lat = []
@@ -261,7 +265,33 @@ def bench_host_pipeline(ctx, rate, steps):
                               "latency_with": round(t_fused + t_transfer / entry["R"], 3)}
         res[name] = entry
         del h
-        torch.cuda.empty_cache()
+    return res
+
+
+def bench_thermal(ctx, steps):
+    """The thermal step of Eq. 1 on the 608 x 608 mesh (369,664 temperatures,
+    the paper's ~3.7e5), one launch per step: single steps back to back, and a
+    100-step run.  Algorithmic bytes per step: the CSR (row pointers, 8 B per
+    entry), b, u, T read once and T_next written."""
+    import numpy as np
+    import torch
+    from paper_1902_08018_amd import synth, wh
+    spec = synth.THERMAL
+    row_ptr, col, val, b = synth.thermal_system(spec)
+    dev = wh.ThermalSystem(row_ptr, col, val, b)
+    n, nnz = spec.n, dev.nnz
+    T = [torch.from_numpy(synth.thermal_initial(spec)).cuda(), torch.empty(n, device="cuda")]
+    K = 100
+    U = torch.from_numpy(np.stack([synth.thermal_source(spec, k) for k in range(K)])).cuda()
+    one = time_call(lambda i: wh.wh_thermal_step(ctx, dev, T[i % 2], U[i % K], T[(i + 1) % 2]), max(steps, 50), 5)
+    run = time_call(lambda i: wh.wh_thermal_run(ctx, dev, T[0], U, T[1]), 3, 1) / K
+    alg = 4 * (n + 1) + 8 * nnz + 16 * n
+    flop = 2 * nnz + n  # Eq. 3's thermal term: 2 nnz(A) + 2 nnz(B) - 1 per row
+    res = {"n": n, "nnz": nnz, "bytes_per_step": alg}
+    for name, ms in (("single_step", one), ("run_100_steps_per_step", run)):
+        res[name] = {"us": round(ms * 1e3, 2), "hbm_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "gflops": round(flop / (ms * 1e-3) / 1e9, 1)}
     return res
 
 
@@ -531,6 +561,8 @@ def main():
         extra[f"slit_field_rate{rate}"] = bench_slit_field(ctx, rate, max(10, args.steps))
         print("# host-resident matrices streamed over the link", file=sys.stderr, flush=True)
         extra[f"host_pipeline_rate{rate}"] = bench_host_pipeline(ctx, rate, max(5, args.steps // 2))
+        print("# thermal step", file=sys.stderr, flush=True)
+        extra["thermal_step_608x608"] = bench_thermal(ctx, args.steps)
 
     if args.serving:
         print("# serving loop", file=sys.stderr, flush=True)

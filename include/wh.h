@@ -90,6 +90,8 @@ typedef uint64_t wh_mat; /* matrix handle, never 0 */
 #define WH_ACC_FP64 1u     /* FP32 block partial sums, FP64 accumulation    */
 #define WH_ACC_TWOSUM 2u   /* FP32 block partial sums, compensated FP32
                               (TwoSum) accumulation                          */
+#define WH_HOST_DIRECT 8u  /* wh_gemv_host only: the kernel reads the
+                              page-locked stream over the link itself */
 #define WH_PAPER_MP 4u     /* Fig. 7 exactly: every FP32 product added to an
                               FP64 sum; slowest; zfp and F32 formats only    */
 
@@ -168,13 +170,41 @@ wh_status wh_gemv_batched(wh_ctx *ctx, wh_mat m, const void *d_U, int u_dtype, u
  * turn; each chunk's fused decode + GEMV runs on `stream` once its copy has
  * landed, while the next chunk is in flight.  Copies overlap the GPU's work
  * only from page-locked memory (hipHostMalloc, torch pin_memory); pageable
- * memory works but its copies are staged by the runtime.  h_code must stay
- * valid and unchanged until the work on `stream` has finished.  d_u, d_y,
- * flags, ranges and errors as wh_gemv; the staging buffers belong to the
- * context (grown on demand, freed by wh_destroy). */
+ * memory works but its copies are staged by the runtime.  With
+ * WH_HOST_DIRECT in flags there is no copy: the fused kernel reads the
+ * page-locked stream over the link itself (pageable memory ->
+ * WH_ERR_INVALID).  h_code must stay valid and unchanged until the work on
+ * `stream` has finished.  d_u, d_y, other flags, ranges and errors as
+ * wh_gemv; the staging buffers belong to the context (grown on demand, freed
+ * by wh_destroy). */
 wh_status wh_gemv_host(wh_ctx *ctx, const void *h_code, uint32_t rows, uint32_t cols, uint32_t rate,
                        const float *d_u, float *d_y, uint32_t row_begin, uint32_t row_end, uint32_t chunk_rows,
                        uint32_t flags, void *stream);
+
+/* Page-locked host memory for h_code of wh_gemv_host (hipHostMalloc): the
+ * copies of such memory overlap the GPU's work.  Needs no context.  Freed by
+ * wh_host_free (NULL is a no-op) once no queued work reads it. */
+wh_status wh_host_alloc(uint64_t bytes, void **h_ptr);
+wh_status wh_host_free(void *h_ptr);
+
+/* The thermal step (Sec. 2.1, Eq. 1): d_T_next = A d_T + B d_u, for n
+ * temperatures.  A is n x n in CSR: d_row_ptr[n + 1] (d_row_ptr[0] = 0,
+ * nondecreasing, d_row_ptr[n] = nnz), d_col[nnz] (column of each entry, < n),
+ * d_val[nnz] FP32; B is diagonal, d_b[n] FP32.  d_T, d_u, d_T_next: n FP32;
+ * d_T_next must not be d_T.  Each row is summed in FP64 and rounded once to
+ * FP32.  Entries past nnz and columns >= n are skipped (wrong values, never a
+ * stray access).  All device memory, owned by the caller. */
+wh_status wh_thermal_step(wh_ctx *ctx, uint32_t n, uint32_t nnz, const uint32_t *d_row_ptr, const uint32_t *d_col,
+                          const float *d_val, const float *d_b, const float *d_T, const float *d_u, float *d_T_next,
+                          void *stream);
+
+/* `steps` thermal steps in a row: T_{k+1} = A T_k + B u_k for k = 0 ..
+ * steps - 1, with u_k = d_U + k * ldu (ldu >= n).  d_T holds T_0 on entry
+ * and T_steps when the work on `stream` is done; d_work (n FP32, not d_T) is
+ * the other half of the ping-pong.  Arguments otherwise as wh_thermal_step. */
+wh_status wh_thermal_run(wh_ctx *ctx, uint32_t n, uint32_t nnz, const uint32_t *d_row_ptr, const uint32_t *d_col,
+                         const float *d_val, const float *d_b, float *d_T, const float *d_U, uint64_t ldu,
+                         uint32_t steps, float *d_work, void *stream);
 
 /* Bit-exactness probe: decode blocks [block_begin, block_begin + nblocks)
  * of a zfp matrix into d_out[nblocks][16] FP32 (v = 4r + c in a block;

@@ -133,7 +133,7 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
     WH_GUARD(ctx);
     if (!h_code || !d_u || !d_y || !aligned(d_u, 16) || chunk_rows % 4)
         return WH_ERR_INVALID;
-    if (flags & ~(WH_ACC_FP64 | WH_ACC_TWOSUM | WH_PAPER_MP))
+    if (flags & ~(WH_ACC_FP64 | WH_ACC_TWOSUM | WH_PAPER_MP | WH_HOST_DIRECT))
         return WH_ERR_INVALID;
     if ((flags & WH_ACC_FP64) && (flags & WH_ACC_TWOSUM))
         return WH_ERR_INVALID;
@@ -150,6 +150,23 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
                              : (flags & WH_ACC_TWOSUM) ? AccMode::TwoSum
                                                        : AccMode::Fp64;
         const uint64_t brow_bytes = (uint64_t)((cols + 3) / 4) * 2u * rate; // one block row of code
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (flags & WH_HOST_DIRECT) {
+            // the fused kernel reads the page-locked stream over the link
+            // itself: no staging, no copy engine
+            void* dev = nullptr;
+            if (hipHostGetDevicePointer(&dev, const_cast<void*>(h_code), 0) != hipSuccess || !dev) {
+                (void)hipGetLastError();
+                return WH_ERR_INVALID;
+            }
+            const GemvPlan pl = whz_gemv_plan(rows, cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
+            if (pl.nslab > 1) {
+                const wh_status s = ensure_partials(ctx, (size_t)pl.nslab * pl.part_rows());
+                if (s != WH_OK)
+                    return s;
+            }
+            return device_error(ctx, whz_gemv(rate, pl, mode, dev, d_u, d_y, pl.nslab > 1 ? ctx->part : nullptr, st));
+        }
         const uint32_t bb = row_begin / 4, be = (row_end + 3) / 4;
         uint64_t cb = chunk_rows ? chunk_rows / 4 : kPipeChunkBytes / brow_bytes;
         cb = std::max<uint64_t>(1, std::min<uint64_t>(cb, be - bb));
@@ -177,7 +194,6 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
                 return s;
         }
         HostPipe* p = ctx->pipe;
-        hipStream_t st = static_cast<hipStream_t>(stream);
         const char* src = static_cast<const char*>(h_code);
         // copies start after the work already on the caller's stream, and
         // after the GEMVs of an earlier call (on any stream) that read the
@@ -214,4 +230,26 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
     } catch (...) {
         return WH_ERR_INVALID;
     }
+}
+
+extern "C" wh_status wh_host_alloc(uint64_t bytes, void** h_ptr)
+{
+    if (!h_ptr || bytes == 0)
+        return WH_ERR_INVALID;
+    *h_ptr = nullptr;
+    void* p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, (size_t)bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return WH_ERR_NOMEM;
+    }
+    *h_ptr = p;
+    return WH_OK;
+}
+
+extern "C" wh_status wh_host_free(void* h_ptr)
+{
+    if (!h_ptr)
+        return WH_OK;
+    return hipHostFree(h_ptr) == hipSuccess ? WH_OK : WH_ERR_INVALID;
 }

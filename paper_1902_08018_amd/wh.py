@@ -28,7 +28,7 @@ WH_ERR_BUDGET, WH_ERR_DEVICE, WH_ERR_NOT_FOUND = -5, -6, -7
 
 WH_FMT_ZFP_FIXED_RATE, WH_FMT_F32, WH_FMT_F16, WH_FMT_BF16, WH_FMT_FP8E4M3_BS4 = 1, 2, 3, 4, 5
 WH_HOST, WH_DEVICE = 0, 1
-WH_ACC_DEFAULT, WH_ACC_FP64, WH_ACC_TWOSUM, WH_PAPER_MP = 0, 1, 2, 4
+WH_ACC_DEFAULT, WH_ACC_FP64, WH_ACC_TWOSUM, WH_PAPER_MP, WH_HOST_DIRECT = 0, 1, 2, 4, 8
 WH_U_F32, WH_U_BF16 = 0, 1
 
 
@@ -66,6 +66,10 @@ _sig = {
     "wh_gemv": ([_P, _U64, _P, _P, _U32, _U32, _U32, _P], _I32),
     "wh_gemv_batched": ([_P, _U64, _P, ctypes.c_int, _U32, _U32, _P, _U32, _U32, _P], _I32),
     "wh_gemv_host": ([_P, _P, _U32, _U32, _U32, _P, _P, _U32, _U32, _U32, _U32, _P], _I32),
+    "wh_host_alloc": ([_U64, ctypes.POINTER(ctypes.c_void_p)], _I32),
+    "wh_host_free": ([_P], _I32),
+    "wh_thermal_step": ([_P, _U32, _U32, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
+    "wh_thermal_run": ([_P, _U32, _U32, _P, _P, _P, _P, _P, _P, _U64, _U32, _P, _P], _I32),
     "wh_decode_debug": ([_P, _U64, _U64, _U64, _P, _P], _I32),
     "wh_decode": ([_P, _U64, _P, _P], _I32),
     "wh_encode": ([_P, _P, _U32, _U32, _U32, _P, _P, _P], _I32),
@@ -215,6 +219,70 @@ def wh_gemv_host(ctx: int, h_code, rows: int, cols: int, rate: int, u: torch.Ten
     _borrowed[(ctx, "host_code")] = h_code
     _check(_lib.wh_gemv_host(ctx, ptr, rows, cols, rate, _dptr(u, torch.float32, "u"), _dptr(y, torch.float32, "y"),
                              row_begin, row_end, chunk_rows, flags, _stream(stream)), "wh_gemv_host")
+
+
+class HostBuffer:
+    """Page-locked host memory from wh_host_alloc, viewed as a uint8 numpy
+    array (`.array`); freed by close() or when collected."""
+
+    def __init__(self, nbytes: int):
+        import numpy as np
+        p = ctypes.c_void_p()
+        _check(_lib.wh_host_alloc(nbytes, ctypes.byref(p)), "wh_host_alloc")
+        self._ptr = p.value
+        self.nbytes = nbytes
+        self.array = np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(self._ptr))
+
+    def close(self) -> None:
+        if self._ptr:
+            self.array = None
+            _check(_lib.wh_host_free(self._ptr), "wh_host_free")
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ThermalSystem:
+    """A (CSR) and the diagonal of B of Eq. 1, resident on the device."""
+
+    def __init__(self, row_ptr, col, val, b, device="cuda"):
+        import numpy as np
+        self.n = len(row_ptr) - 1
+        self.nnz = int(row_ptr[-1])
+        if len(col) != self.nnz or len(val) != self.nnz or len(b) != self.n:
+            raise ValueError("CSR arrays do not match: need row_ptr[n+1], col[nnz], val[nnz], b[n]")
+        self.row_ptr = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.uint32).view(np.int32)).to(device)
+        self.col = torch.from_numpy(np.ascontiguousarray(col, dtype=np.uint32).view(np.int32)).to(device)
+        self.val = torch.from_numpy(np.ascontiguousarray(val, dtype=np.float32)).to(device)
+        self.b = torch.from_numpy(np.ascontiguousarray(b, dtype=np.float32)).to(device)
+
+
+def wh_thermal_step(ctx: int, sysm: ThermalSystem, T: torch.Tensor, u: torch.Tensor, T_next: torch.Tensor,
+                    stream=None) -> None:
+    for name, t in (("T", T), ("u", u), ("T_next", T_next)):
+        _need(t.numel() >= sysm.n, f"{name} holds {t.numel()} values for {sysm.n} temperatures")
+    _check(_lib.wh_thermal_step(ctx, sysm.n, sysm.nnz, sysm.row_ptr.data_ptr(), sysm.col.data_ptr(),
+                                sysm.val.data_ptr(), sysm.b.data_ptr(), _dptr(T, torch.float32, "T"),
+                                _dptr(u, torch.float32, "u"), _dptr(T_next, torch.float32, "T_next"),
+                                _stream(stream)), "wh_thermal_step")
+
+
+def wh_thermal_run(ctx: int, sysm: ThermalSystem, T: torch.Tensor, U: torch.Tensor, work: torch.Tensor,
+                   stream=None) -> None:
+    """U: (steps, ldu >= n) float32, rows contiguous; T updated in place."""
+    if U.dim() != 2 or U.stride(1) != 1:
+        raise ValueError("U must be (steps, ldu) with contiguous rows")
+    _need(U.shape[1] >= sysm.n, f"rows of U hold {U.shape[1]} values for {sysm.n} temperatures")
+    for name, t in (("T", T), ("work", work)):
+        _need(t.numel() >= sysm.n, f"{name} holds {t.numel()} values for {sysm.n} temperatures")
+    _check(_lib.wh_thermal_run(ctx, sysm.n, sysm.nnz, sysm.row_ptr.data_ptr(), sysm.col.data_ptr(),
+                               sysm.val.data_ptr(), sysm.b.data_ptr(), _dptr(T, torch.float32, "T"),
+                               _dptr(U, torch.float32, "U"), U.stride(0), U.shape[0],
+                               _dptr(work, torch.float32, "work"), _stream(stream)), "wh_thermal_run")
 
 
 def wh_gemv_batched(ctx: int, mat: int, U: torch.Tensor, Y: torch.Tensor, flags: int = WH_ACC_DEFAULT,

@@ -4,7 +4,8 @@ on the chunk before (Sec. 3.1-3.2, Table 1).
 
   y against the FP64 oracle within 1e-6 relative L2 (Fig. 7 mode: within 1
   FP32 ulp), for chunk sizes from one block row up, row ranges that start
-  and end inside block rows, page-locked and pageable host memory; calls in a
+  and end inside block rows, page-locked and pageable host memory; the
+  direct mode (the kernel reads page-locked host memory itself); calls in a
   row on two streams that share the staging buffers; argument errors.
 """
 import numpy as np
@@ -46,6 +47,40 @@ def test_host_stream_matches_oracle(gpu_ctx, rows, cols, chunk_rows):
             continue
         y = torch.full((re - rb + 2,), -7.0, device="cuda")
         wh.wh_gemv_host(gpu_ctx, h, rows, cols, 8, u, y, rb, re, chunk_rows)
+        torch.cuda.synchronize()
+        yh = y.cpu().numpy()
+        assert rel_l2(yh[:re - rb], ref[rb:re]) <= 1e-6, (rb, re)
+        assert np.all(yh[re - rb:] == -7.0)
+
+
+def test_host_stream_library_pinned_buffer(gpu_ctx):
+    rows, cols = 262, 2050
+    s = case(rows, cols, seed=44)
+    hb = wh.HostBuffer(s.size)
+    try:
+        hb.array[:] = s
+        u_np = synth.uniform(cols, seed=14)
+        y = torch.empty(rows, device="cuda")
+        wh.wh_gemv_host(gpu_ctx, hb.array, rows, cols, 8, torch.from_numpy(u_np).cuda(), y, chunk_rows=32)
+        torch.cuda.synchronize()
+        assert rel_l2(y.cpu().numpy(), oracle.gemv_fp64(s, rows, cols, 8, u_np)) <= 1e-6
+    finally:
+        hb.close()
+
+
+@pytest.mark.parametrize("rows,cols", [(378, 262), (1030, 1030), (5, 7)])
+def test_host_direct_matches_oracle(gpu_ctx, rows, cols):
+    """WH_HOST_DIRECT: the fused kernel reads the page-locked stream itself."""
+    s = case(rows, cols, seed=45)
+    h = pinned(s)
+    u_np = synth.uniform(cols, seed=15)
+    u = torch.from_numpy(u_np).cuda()
+    ref = oracle.gemv_fp64(s, rows, cols, 8, u_np)
+    for rb, re in [(0, rows), (3, rows - 2), (1, 2)]:
+        if not 0 <= rb < re <= rows:
+            continue
+        y = torch.full((re - rb + 2,), -7.0, device="cuda")
+        wh.wh_gemv_host(gpu_ctx, h, rows, cols, 8, u, y, rb, re, flags=wh.WH_HOST_DIRECT)
         torch.cuda.synchronize()
         yh = y.cpu().numpy()
         assert rel_l2(yh[:re - rb], ref[rb:re]) <= 1e-6, (rb, re)
