@@ -4,8 +4,10 @@ Only the test suite, `__graft_entry__.smoke()` and the CPU-baseline leg of
 `bench.py` may import this package.  It shares no code with the GPU library.
 
 Contents:
-  whz_oracle.c  scalar C: WHZ1 encode/decode, FP64 GEMV, the paper's
-                mixed-precision GEMV (Fig. 7), dense references
+  whz_oracle.c  scalar C: WHZ1 encode/decode (fixed rate, and the
+                fixed-precision and fixed-accuracy modes with a block index),
+                FP64 GEMV, the paper's mixed-precision GEMV (Fig. 7), dense
+                references
   twin.py       pure-Python twin of the codec for tiny inputs
   metrics.py    compression-error and GEMV-error metrics (Table 2 conventions)
   quant.py      reference quantisers for the reduced-precision storage formats
@@ -50,6 +52,12 @@ def lib():
         L.orc_dense_gemv_fp64.argtypes = [P, U32, U32, P, P]
         L.orc_dense_gemv_paper_mp.argtypes = [P, U32, U32, P, P]
         L.orc_dense_gemv_fp32_naive.argtypes = [P, U32, U32, P, P]
+        L.orc_var_groups.argtypes = [U32]
+        L.orc_var_groups.restype = U32
+        L.orc_var_capacity_bytes.argtypes = [U32, U32]
+        L.orc_var_capacity_bytes.restype = U64
+        L.orc_encode_var.argtypes = [P, U32, U32, I32, I32, P, U64, P, P]
+        L.orc_decode_var.argtypes = [P, P, U32, U32, I32, I32, P]
         L.orc_encode_planes.argtypes = [P, ctypes.c_uint, P]
         L.orc_encode_planes.restype = ctypes.c_uint
         L.orc_decode_planes.argtypes = [P, ctypes.c_uint, P]
@@ -93,6 +101,43 @@ def decode(stream: np.ndarray, rows: int, cols: int, rate: int) -> np.ndarray:
     stream = np.ascontiguousarray(stream, dtype=np.uint8)
     out = np.empty((rows, cols), dtype=np.float32)
     _check(lib().orc_decode(_ptr(stream), rows, cols, rate, _ptr(out)))
+    return out
+
+
+# ------------------------------------------------- variable-rate modes
+VAR_PRECISION, VAR_ACCURACY = 0, 1
+VAR_GROUP = 32  # block columns per index entry
+
+
+def var_groups(cols: int) -> int:
+    return int(lib().orc_var_groups(cols))
+
+
+def encode_var(M: np.ndarray, mode: int, param: int):
+    """Fixed-precision (mode 0, param = planes) or fixed-accuracy (mode 1,
+    param = minexp: tolerance 2^minexp) code of M.  Returns (stream bytes,
+    index uint64 [ceil(rows/4) * var_groups(cols)], bits)."""
+    M = np.ascontiguousarray(M, dtype=np.float32)
+    rows, cols = M.shape
+    cap = int(lib().orc_var_capacity_bytes(rows, cols))
+    out = np.zeros(cap, dtype=np.uint8)
+    index = np.zeros(((rows + 3) // 4) * var_groups(cols), dtype=np.uint64)
+    nbits = ctypes.c_uint64(0)
+    _check(lib().orc_encode_var(_ptr(M), rows, cols, mode, param, _ptr(out), cap, _ptr(index), ctypes.byref(nbits)))
+    return out[: (nbits.value + 7) // 8].copy(), index, nbits.value
+
+
+def decode_var(stream: np.ndarray, index, rows: int, cols: int, mode: int, param: int) -> np.ndarray:
+    """Decode with the index (index=None: blocks read one after another).
+    `stream` may be the trimmed bytes: it is padded here for the reader."""
+    buf = np.zeros(np.asarray(stream).size + 256, dtype=np.uint8)
+    buf[: np.asarray(stream).size] = stream
+    out = np.empty((rows, cols), dtype=np.float32)
+    ip = None
+    if index is not None:
+        index = np.ascontiguousarray(index, dtype=np.uint64)
+        ip = _ptr(index)
+    _check(lib().orc_decode_var(_ptr(buf), ip, rows, cols, mode, param, _ptr(out)))
     return out
 
 

@@ -184,12 +184,13 @@ static int32_t from_negabinary(uint32_t n) { return (int32_t)((n ^ 0xAAAAAAAAu) 
 /* ------------------------------------------------------------------ */
 /* embedded bit-plane coder on 16 unsigned coefficients                */
 /* ------------------------------------------------------------------ */
-/* Writes at most `budget` bits; returns the number written. */
-static unsigned encode_planes(bitw *w, const uint32_t n16[16], unsigned budget)
+/* Writes planes 31 down to `lo`, at most `budget` bits; returns the number
+ * written. */
+static unsigned encode_planes(bitw *w, const uint32_t n16[16], unsigned budget, int lo)
 {
     unsigned left = budget;
     unsigned nsig = 0; /* coefficients 0..nsig-1 are significant */
-    for (int p = 31; p >= 0 && left > 0; p--) {
+    for (int p = 31; p >= lo && left > 0; p--) {
         uint32_t x = 0;
         for (int s = 0; s < 16; s++)
             x |= ((n16[s] >> p) & 1u) << s;
@@ -222,14 +223,15 @@ static unsigned encode_planes(bitw *w, const uint32_t n16[16], unsigned budget)
     return budget - left;
 }
 
-/* Reads at most `budget` bits into n16 (zeroed first); returns bits read. */
-static unsigned decode_planes(bitr *r, uint32_t n16[16], unsigned budget)
+/* Reads planes 31 down to `lo`, at most `budget` bits, into n16 (zeroed
+ * first; planes below lo stay zero); returns bits read. */
+static unsigned decode_planes(bitr *r, uint32_t n16[16], unsigned budget, int lo)
 {
     unsigned left = budget;
     unsigned nsig = 0;
     for (int s = 0; s < 16; s++)
         n16[s] = 0;
-    for (int p = 31; p >= 0 && left > 0; p--) {
+    for (int p = 31; p >= lo && left > 0; p--) {
         uint32_t x = 0;
         unsigned m = nsig < left ? nsig : left;
         for (unsigned k = 0; k < m; k++)
@@ -262,13 +264,13 @@ static unsigned decode_planes(bitr *r, uint32_t n16[16], unsigned budget)
 unsigned orc_encode_planes(const uint32_t *n16, unsigned budget, uint8_t *out)
 {
     bitw w = {out, 0};
-    return encode_planes(&w, n16, budget);
+    return encode_planes(&w, n16, budget, 0);
 }
 
 unsigned orc_decode_planes(const uint8_t *in, unsigned budget, uint32_t *n16)
 {
     bitr r = {in, 0};
-    return decode_planes(&r, n16, budget);
+    return decode_planes(&r, n16, budget, 0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -282,11 +284,11 @@ static int binade(float f)
     return e;
 }
 
-/* Encode f[16] (local index 4r + c) into exactly maxbits bits at w->pos.
- * Returns ORC_ERR_INVALID on NaN/Inf. */
-static int encode_block(bitw *w, const float f[16], unsigned maxbits)
+/* The block-floating-point step, the forward transform, the sequency
+ * order and negabinary: f[16] (local index 4r + c) -> n16[16] and emax.
+ * Returns 0 for an all-zero block, 1 otherwise, ORC_ERR_INVALID on NaN/Inf. */
+static int block_to_negabinary(const float f[16], int *emax_out, uint32_t n16[16])
 {
-    uint64_t start = w->pos;
     int nonzero = 0, emax = -126;
     for (int v = 0; v < 16; v++) {
         if (isnan(f[v]) || isinf(f[v]))
@@ -298,27 +300,72 @@ static int encode_block(bitw *w, const float f[16], unsigned maxbits)
             nonzero = 1;
         }
     }
-    if (!nonzero) {
+    if (!nonzero)
+        return 0;
+    if (emax < -126)
+        emax = -126;
+    /* block floating point: exact scaling, truncation toward zero */
+    int32_t iblk[16];
+    double scale = ldexp(1.0, 30 - emax);
+    for (int v = 0; v < 16; v++)
+        iblk[v] = (int32_t)trunc((double)f[v] * scale);
+    fwd_xform(iblk);
+    int order[16];
+    sequency_order(order);
+    for (int s = 0; s < 16; s++)
+        n16[s] = to_negabinary(iblk[order[s]]);
+    *emax_out = emax;
+    return 1;
+}
+
+/* n16[16] and emax -> f[16]: negabinary, sequency order and transform
+ * undone, f = ldexp(RNE_f32(i), emax - 30) (the double product is exact,
+ * the final conversion is the one IEEE rounding). */
+static void negabinary_to_block(const uint32_t n16[16], int emax, float f[16])
+{
+    int order[16];
+    sequency_order(order);
+    int32_t iblk[16];
+    for (int s = 0; s < 16; s++)
+        iblk[order[s]] = from_negabinary(n16[s]);
+    inv_xform(iblk);
+    for (int v = 0; v < 16; v++) {
+        float fi = (float)iblk[v];
+        f[v] = (float)((double)fi * ldexp(1.0, emax - 30));
+    }
+}
+
+static void put_header(bitw *w, int emax)
+{
+    unsigned E = (unsigned)(emax + 127);
+    put_bit(w, 1);
+    for (int k = 0; k < 8; k++)
+        put_bit(w, (E >> k) & 1u);
+}
+
+static int get_exponent(bitr *r)
+{
+    unsigned E = 0;
+    for (int k = 0; k < 8; k++)
+        E |= get_bit(r) << k;
+    return (int)E - 127;
+}
+
+/* Encode f[16] (local index 4r + c) into exactly maxbits bits at w->pos.
+ * Returns ORC_ERR_INVALID on NaN/Inf. */
+static int encode_block(bitw *w, const float f[16], unsigned maxbits)
+{
+    uint64_t start = w->pos;
+    int emax = 0;
+    uint32_t n16[16];
+    int st = block_to_negabinary(f, &emax, n16);
+    if (st < 0)
+        return st;
+    if (st == 0) {
         put_bit(w, 0);
     } else {
-        if (emax < -126)
-            emax = -126;
-        unsigned E = (unsigned)(emax + 127);
-        put_bit(w, 1);
-        for (int k = 0; k < 8; k++)
-            put_bit(w, (E >> k) & 1u);
-        /* block floating point: exact scaling, truncation toward zero */
-        int32_t iblk[16];
-        double scale = ldexp(1.0, 30 - emax);
-        for (int v = 0; v < 16; v++)
-            iblk[v] = (int32_t)trunc((double)f[v] * scale);
-        fwd_xform(iblk);
-        int order[16];
-        sequency_order(order);
-        uint32_t n16[16];
-        for (int s = 0; s < 16; s++)
-            n16[s] = to_negabinary(iblk[order[s]]);
-        encode_planes(w, n16, maxbits - 9);
+        put_header(w, emax);
+        encode_planes(w, n16, maxbits - 9, 0);
     }
     w->pos = start + maxbits; /* pad: unused bits stay zero */
     return ORC_OK;
@@ -333,24 +380,10 @@ static void decode_block(bitr *r, float f[16], unsigned maxbits)
         for (int v = 0; v < 16; v++)
             f[v] = 0.0f;
     } else {
-        unsigned E = 0;
-        for (int k = 0; k < 8; k++)
-            E |= get_bit(r) << k;
-        int emax = (int)E - 127;
+        int emax = get_exponent(r);
         uint32_t n16[16];
-        decode_planes(r, n16, maxbits - 9);
-        int order[16];
-        sequency_order(order);
-        int32_t iblk[16];
-        for (int s = 0; s < 16; s++)
-            iblk[order[s]] = from_negabinary(n16[s]);
-        inv_xform(iblk);
-        for (int v = 0; v < 16; v++) {
-            /* f = ldexp(RNE_f32(i), emax - 30): the double product is exact,
-             * the final conversion is the one IEEE rounding */
-            float fi = (float)iblk[v];
-            f[v] = (float)((double)fi * ldexp(1.0, emax - 30));
-        }
+        decode_planes(r, n16, maxbits - 9, 0);
+        negabinary_to_block(n16, emax, f);
     }
     r->pos = start + maxbits;
 }
@@ -426,6 +459,136 @@ int orc_decode(const uint8_t *stream, uint32_t rows, uint32_t cols, uint32_t rat
         for (uint32_t bj = 0; bj < nblk(cols); bj++) {
             float f[16];
             decode_block(&r, f, maxbits);
+            for (uint32_t rr = 0; rr < 4; rr++)
+                for (uint32_t c = 0; c < 4; c++)
+                    if (4 * bi + rr < rows && 4 * bj + c < cols)
+                        Mhat[(uint64_t)(4 * bi + rr) * cols + 4 * bj + c] = f[4 * rr + c];
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* variable-rate modes: fixed precision, fixed accuracy (Sec. 4.3)      */
+/* ------------------------------------------------------------------ */
+/* The same block code with no bit budget: a nonzero block codes bit planes
+ * 31 down to 32 - P and ends there (its length follows from its bits).
+ *   fixed precision (mode 0, param = P in 1..32): P planes in every block;
+ *   fixed accuracy (mode 1, param = minexp, tolerance 2^minexp):
+ *     P = clamp(emax - minexp + 7, 0, 32).  Dropping the planes below
+ *     32 - P changes each coefficient by less than (2/3) 2^(32-P) units of
+ *     2^(emax-30); the inverse transform's row and column gain (3.75 each)
+ *     carries that to under 0.3 tol per value, and the truncation to
+ *     integers and the lift's floor shifts add a few units of 2^(emax-30),
+ *     so |error| <= tol whenever P < 32 is not clamped (emax - minexp <= 25).
+ * Blocks follow each other with no padding, in raster order.  The index
+ * holds the bit offset of every ORC_GROUP-th block of each block row:
+ * index[bi * ngroups + a] = offset of block (bi, ORC_GROUP * a). */
+enum { ORC_VAR_PRECISION = 0, ORC_VAR_ACCURACY = 1 };
+#define ORC_GROUP 32u
+
+static int var_planes(int mode, int param, int emax)
+{
+    if (mode == ORC_VAR_PRECISION)
+        return param;
+    int p = emax - param + 7;
+    return p < 0 ? 0 : p > 32 ? 32 : p;
+}
+
+static int check_var(int mode, int param)
+{
+    if (mode == ORC_VAR_PRECISION)
+        return param >= 1 && param <= 32 ? ORC_OK : ORC_ERR_INVALID;
+    if (mode == ORC_VAR_ACCURACY)
+        return param >= -160 && param <= 160 ? ORC_OK : ORC_ERR_INVALID;
+    return ORC_ERR_INVALID;
+}
+
+static int encode_block_var(bitw *w, const float f[16], int mode, int param)
+{
+    int emax = 0;
+    uint32_t n16[16];
+    int st = block_to_negabinary(f, &emax, n16);
+    if (st < 0)
+        return st;
+    if (st == 0) {
+        put_bit(w, 0);
+        return ORC_OK;
+    }
+    put_header(w, emax);
+    encode_planes(w, n16, ~0u, 32 - var_planes(mode, param, emax));
+    return ORC_OK;
+}
+
+static void decode_block_var(bitr *r, float f[16], int mode, int param)
+{
+    if (!get_bit(r)) {
+        for (int v = 0; v < 16; v++)
+            f[v] = 0.0f;
+        return;
+    }
+    int emax = get_exponent(r);
+    uint32_t n16[16];
+    decode_planes(r, n16, ~0u, 32 - var_planes(mode, param, emax));
+    negabinary_to_block(n16, emax, f);
+}
+
+uint32_t orc_var_groups(uint32_t cols) { return (nblk(cols) + ORC_GROUP - 1) / ORC_GROUP; }
+
+/* Most bits a block can take: header, then per plane the verbatim bits of
+ * the significant coefficients, one group test and the run bits. */
+uint64_t orc_var_capacity_bytes(uint32_t rows, uint32_t cols)
+{
+    return (uint64_t)nblk(rows) * nblk(cols) * ((9 + 32 * 33 + 7) / 8) + 16;
+}
+
+/* M: rows x cols FP32 -> stream (cap bytes, zeroed here) and index
+ * (nblk(rows) * orc_var_groups(cols) entries); *nbits = bits written. */
+int orc_encode_var(const float *M, uint32_t rows, uint32_t cols, int mode, int param, uint8_t *stream, uint64_t cap,
+                   uint64_t *index, uint64_t *nbits)
+{
+    if (rows == 0 || cols == 0)
+        return ORC_ERR_SHAPE;
+    if (check_var(mode, param) || cap < orc_var_capacity_bytes(rows, cols))
+        return ORC_ERR_INVALID;
+    memset(stream, 0, cap);
+    bitw w = {stream, 0};
+    uint32_t ng = orc_var_groups(cols);
+    for (uint32_t bi = 0; bi < nblk(rows); bi++) {
+        for (uint32_t bj = 0; bj < nblk(cols); bj++) {
+            if (bj % ORC_GROUP == 0)
+                index[(uint64_t)bi * ng + bj / ORC_GROUP] = w.pos;
+            float f[16];
+            for (int r = 0; r < 4; r++)
+                for (int c = 0; c < 4; c++)
+                    f[4 * r + c] = M[(uint64_t)clamp_index(4 * bi + r, rows) * cols + clamp_index(4 * bj + c, cols)];
+            int st = encode_block_var(&w, f, mode, param);
+            if (st)
+                return st;
+        }
+    }
+    *nbits = w.pos;
+    return ORC_OK;
+}
+
+/* Decode into Mhat (rows x cols).  With an index each group of blocks
+ * starts at its recorded offset; with index == NULL the blocks are read one
+ * after another from bit 0. */
+int orc_decode_var(const uint8_t *stream, const uint64_t *index, uint32_t rows, uint32_t cols, int mode, int param,
+                   float *Mhat)
+{
+    if (rows == 0 || cols == 0)
+        return ORC_ERR_SHAPE;
+    if (check_var(mode, param))
+        return ORC_ERR_INVALID;
+    bitr r = {stream, 0};
+    uint32_t ng = orc_var_groups(cols);
+    for (uint32_t bi = 0; bi < nblk(rows); bi++) {
+        for (uint32_t bj = 0; bj < nblk(cols); bj++) {
+            if (index && bj % ORC_GROUP == 0)
+                r.pos = index[(uint64_t)bi * ng + bj / ORC_GROUP];
+            float f[16];
+            decode_block_var(&r, f, mode, param);
             for (uint32_t rr = 0; rr < 4; rr++)
                 for (uint32_t c = 0; c < 4; c++)
                     if (4 * bi + rr < rows && 4 * bj + c < cols)
