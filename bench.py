@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -212,7 +213,8 @@ def bench_host_pipeline(ctx, rate, steps):
     while the fused kernel works on the chunk before (Sec. 3.1-3.2).  Beside
     it, the parts of Table 1's formulas measured on their own: the plain
     host-to-device copy of the same compressed bytes (T_transfer / R) and the
-    fused kernel on the resident matrix (T_compute + T_decode)."""
+    fused kernel on the resident matrix (T_compute + T_decode).  The pipeline
+    is timed first, before the device allocations of the parts."""
     import torch
     from paper_1902_08018_amd import synth, wh, workload
     res = {}
@@ -222,23 +224,12 @@ def bench_host_pipeline(ctx, rate, steps):
         st = workload.build_stream(ctx, spec, rate)
         h = torch.empty(st.numel(), dtype=torch.uint8, pin_memory=True)
         h.copy_(st)
-        m = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, st)
         u = workload.u_device(spec)
         y = torch.empty(rows, dtype=torch.float32, device="cuda")
-        t_fused = time_call(lambda i: wh.wh_gemv(ctx, m, u, y, 0, rows), steps, 2)
-        wh.wh_unload(ctx, m)
-        dbuf = torch.empty_like(st)
-        t_copy = time_call(lambda i: dbuf.copy_(h, non_blocking=True), 3, 1)
-        # no torch.cuda.empty_cache() here: for ~150 ms after a large device
-        # allocation is freed, host-to-device copies run at about half speed
-        del dbuf, st
-        link_gbs = h.numel() / (t_copy * 1e-3) / 1e9
         entry = {"compressed_gb": round(h.numel() / 1e9, 3), "uncompressed_gb": round(4.0 * rows * cols / 1e9, 3),
-                 "R": 32 / rate, "link_h2d_gbs": round(link_gbs, 1),
-                 "t_copy_compressed_ms": round(t_copy, 3), "t_fused_resident_ms": round(t_fused, 3)}
+                 "R": 32 / rate}
         chunk8 = 4 * max(1, (8 << 20) // wh.stream_bytes(4, cols, rate))
-        # settle: after large device frees the pipeline's copies have run
-        # slowly for some calls; half a second of calls before timing
+        # settle: half a second of calls before timing
         t_end = time.perf_counter() + 0.5
         while time.perf_counter() < t_end:
             wh.wh_gemv_host(ctx, h, rows, cols, rate, u, y)
@@ -258,6 +249,15 @@ def bench_host_pipeline(ctx, rate, steps):
                 lat.append(e0.elapsed_time(e1))
             entry[label] = {"period_ms": round(period, 3), "latency_ms": round(min(lat), 3),
                             "effective_gbs": round(4.0 * rows * cols / (period * 1e-3) / 1e9, 1)}
+        # the parts of Table 1
+        m = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, st)
+        t_fused = time_call(lambda i: wh.wh_gemv(ctx, m, u, y, 0, rows), steps, 2)
+        wh.wh_unload(ctx, m)
+        t_copy = time_call(lambda i: st.copy_(h, non_blocking=True), 3, 1)
+        del st
+        link_gbs = h.numel() / (t_copy * 1e-3) / 1e9
+        entry.update({"link_h2d_gbs": round(link_gbs, 1), "t_copy_compressed_ms": round(t_copy, 3),
+                      "t_fused_resident_ms": round(t_fused, 3)})
         # Table 1 with the measured parts (T_compute << T_transfer for a GEMV, Sec. 3.2)
         t_transfer = 4.0 * rows * cols / (link_gbs * 1e9) * 1e3
         entry["table1_ms"] = {"period_without_compression": round(t_transfer, 3),
@@ -292,6 +292,62 @@ def bench_thermal(ctx, steps):
         res[name] = {"us": round(ms * 1e3, 2), "hbm_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
                      "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "gflops": round(flop / (ms * 1e-3) / 1e9, 1)}
+    return res
+
+
+VAR_SPEC_ARGS = (8192, 8192, 128, 16.0)
+
+
+def bench_var(ctx, steps):
+    """The variable-rate modes (Sec. 4.3, Table 2) on an 8192 x 8192 synthetic
+    matrix, beside fixed rate 8: bits per value (index included), the
+    Table 2 error columns (NRMSE over the source's range, PSNR =
+    -20 log10(2 NRMSE)), the host encoder's time, the GPU decode rate in the
+    paper's W_c convention (uncompressed bytes per second) and the fused
+    decode + GEMV."""
+    import numpy as np
+    import torch
+    from paper_1902_08018_amd import synth, wh
+    spec = synth.MatrixSpec(*VAR_SPEC_ARGS)
+    rows, cols = spec.rows, spec.cols
+    M = synth.matrix(spec)
+    Md = torch.from_numpy(M).cuda()
+    rng = float(M.max() - M.min())
+    u = torch.from_numpy(synth.u_vector(spec)).cuda()
+    y = torch.empty(rows, device="cuda")
+    out = torch.empty((rows, cols), device="cuda")
+    res = {"matrix": f"{rows}x{cols}, 128-wide lattices, ell 16"}
+    cases = [("fixed_rate_8", wh.WH_FMT_ZFP_FIXED_RATE, 8),
+             ("fixed_precision_17", wh.WH_FMT_ZFP_FIXED_PRECISION, 17),
+             ("fixed_accuracy_2^-20", wh.WH_FMT_ZFP_FIXED_ACCURACY, wh.accuracy_rate(-20)),
+             ("fixed_accuracy_2^-14", wh.WH_FMT_ZFP_FIXED_ACCURACY, wh.accuracy_rate(-14))]
+    for name, fmt, rate in cases:
+        t0 = time.perf_counter()
+        if fmt == wh.WH_FMT_ZFP_FIXED_RATE:
+            buf = torch.empty(wh.stream_bytes(rows, cols, rate), dtype=torch.uint8, device="cuda")
+            wh.wh_encode(ctx, Md, rate, buf)
+            torch.cuda.synchronize()
+        else:
+            buf = torch.from_numpy(wh.wh_encode_var(M, fmt, rate)).cuda()
+        t_enc = time.perf_counter() - t0
+        m = wh.wh_load_compressed(ctx, rows, cols, fmt, rate, buf)
+        t_dec = time_call(lambda i: wh.wh_decode(ctx, m, out), max(3, steps // 4), 1)
+        err = (out - Md).double()
+        rmse = float(torch.sqrt((err * err).mean()))
+        nrmse = rmse / rng
+        t_gemv = time_call(lambda i: wh.wh_gemv(ctx, m, u, y, 0, rows), max(5, steps // 2), 2)
+        bpv = 8.0 * buf.numel() / (rows * cols)
+        res[name] = {"bits_per_value": round(bpv, 3), "ratio": round(32.0 / bpv, 2),
+                     "rmse": float(f"{rmse:.4g}"), "nrmse": float(f"{nrmse:.4g}"),
+                     "max_error": float(f"{float(err.abs().max()):.4g}"),
+                     "psnr": round(-20.0 * math.log10(2.0 * nrmse), 2) if nrmse > 0 else None,
+                     "encode_s": round(t_enc, 3), "encoder": "GPU" if fmt == wh.WH_FMT_ZFP_FIXED_RATE else "host",
+                     "decode_ms": round(t_dec, 3), "decode_wc_gbs": round(4.0 * rows * cols / (t_dec * 1e-3) / 1e9, 1),
+                     "gemv_ms": round(t_gemv, 3),
+                     "gemv_effective_gbs": round(4.0 * rows * cols / (t_gemv * 1e-3) / 1e9, 1)}
+        wh.wh_unload(ctx, m)
+        del buf
+    del Md, out
     return res
 
 
@@ -563,6 +619,8 @@ def main():
         extra[f"host_pipeline_rate{rate}"] = bench_host_pipeline(ctx, rate, max(5, args.steps // 2))
         print("# thermal step", file=sys.stderr, flush=True)
         extra["thermal_step_608x608"] = bench_thermal(ctx, args.steps)
+        print("# variable-rate modes", file=sys.stderr, flush=True)
+        extra["variable_rate_8192x8192"] = bench_var(ctx, args.steps)
 
     if args.serving:
         print("# serving loop", file=sys.stderr, flush=True)

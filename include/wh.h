@@ -66,9 +66,24 @@ typedef enum {
     WH_FMT_F32 = 2,          /* dense FP32, row-major                       */
     WH_FMT_F16 = 3,          /* dense IEEE half, RNE from FP32              */
     WH_FMT_BF16 = 4,         /* dense bfloat16, RNE from FP32               */
-    WH_FMT_FP8E4M3_BS4 = 5   /* OCP FP8 e4m3 codes, 4x4-block tiled (16 B per
+    WH_FMT_FP8E4M3_BS4 = 5,  /* OCP FP8 e4m3 codes, 4x4-block tiled (16 B per
                               * block, raster block order, v = 4r + c inside),
                               * followed by one FP32 scale per block */
+    /* Variable-rate WHZ1 (Sec. 4.3, Table 2: zfp's fixed-precision and
+     * fixed-accuracy modes): the same block code with no bit budget; a
+     * nonzero block codes planes 31 down to 32 - P and ends there, blocks
+     * follow one another with no padding.  Storage: an index of
+     * ceil(rows/4) x ceil(ceil(cols/4)/32) uint64 (the bit offset, in the
+     * code, of every 32nd block of each block row), then the code bytes, then
+     * at least 16 zero bytes, to a multiple of 8; wh_encode_var writes it.  Any total size >= the index +
+     * 16 and a multiple of 4 is accepted by wh_load_compressed (the decoder
+     * reads zeros past the end). */
+    WH_FMT_ZFP_FIXED_PRECISION = 6, /* desc.rate = P, 1..32 planes per block */
+    WH_FMT_ZFP_FIXED_ACCURACY = 7   /* desc.rate = minexp + 1024 (tolerance
+                                     * 2^minexp, minexp in -160..160):
+                                     * P = clamp(emax - minexp + 7, 0, 32),
+                                     * so |error| <= tolerance wherever
+                                     * emax - minexp <= 25 */
 } wh_format;
 
 typedef struct {
@@ -186,6 +201,20 @@ wh_status wh_gemv_host(wh_ctx *ctx, const void *h_code, uint32_t rows, uint32_t 
  * wh_host_free (NULL is a no-op) once no queued work reads it. */
 wh_status wh_host_alloc(uint64_t bytes, void **h_ptr);
 wh_status wh_host_free(void *h_ptr);
+
+/* Variable-rate encoder (host; the paper encodes offline, Sec. 3.2): h_M
+ * rows x cols FP32 row-major in host memory -> h_out (cap bytes of host
+ * memory), the storage of format fmt (WH_FMT_ZFP_FIXED_PRECISION or
+ * _ACCURACY) with parameter `rate` as in wh_matrix_desc; *out_bytes = the
+ * bytes written (pass them to wh_load_compressed).  cap >=
+ * wh_var_capacity_bytes(rows, cols) always suffices.  NaN/Inf ->
+ * WH_ERR_INVALID.  Needs no context.  wh_gemv (not WH_PAPER_MP) and
+ * wh_decode take these formats; wh_gemv_batched and the serving loop do
+ * not (WH_ERR_FORMAT). */
+uint64_t wh_var_index_bytes(uint32_t rows, uint32_t cols);
+uint64_t wh_var_capacity_bytes(uint32_t rows, uint32_t cols);
+wh_status wh_encode_var(const float *h_M, uint32_t rows, uint32_t cols, int32_t fmt, uint32_t rate, void *h_out,
+                        uint64_t cap, uint64_t *out_bytes);
 
 /* The thermal step (Sec. 2.1, Eq. 1): d_T_next = A d_T + B d_u, for n
  * temperatures.  A is n x n in CSR: d_row_ptr[n + 1] (d_row_ptr[0] = 0,

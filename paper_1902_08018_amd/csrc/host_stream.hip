@@ -101,6 +101,12 @@ wh_status ensure_pipe(wh_ctx* ctx, size_t bytes)
     return WH_OK;
 }
 
+} // namespace
+
+wh_status host_pipe_init(wh_ctx* ctx) { return ensure_pipe(ctx, 0); }
+
+namespace {
+
 // Chunk c covers block rows [bb + c * cb, min(bb + (c + 1) * cb, be)) of the
 // matrix; as a matrix of its own it has rows [4 * b0, min(4 * b1, rows)).
 struct Chunk {

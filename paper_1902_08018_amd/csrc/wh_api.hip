@@ -170,6 +170,10 @@ wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
         ctx->num_cus = prop.multiProcessorCount;
         ctx->gemv_tune = gemv_tuning_from_env();
         ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (1ull << 30);
+        if (host_pipe_init(ctx) != WH_OK) {
+            delete ctx;
+            return WH_ERR_DEVICE;
+        }
         *out = ctx;
         return WH_OK;
     } catch (const std::bad_alloc&) {
@@ -219,11 +223,23 @@ wh_status wh_load_compressed(wh_ctx* ctx, const wh_matrix_desc* desc, const void
         return WH_ERR_INVALID;
     try {
         uint64_t need = 0;
-        wh_status st = storage_bytes(*desc, need);
-        if (st != WH_OK)
-            return st;
-        if (nbytes != need)
-            return WH_ERR_FORMAT;
+        int vmode = 0, vparam = 0;
+        if (desc->fmt == WH_FMT_ZFP_FIXED_PRECISION || desc->fmt == WH_FMT_ZFP_FIXED_ACCURACY) {
+            // variable length: the index, then at least the reader's padding
+            if (desc->rows == 0 || desc->cols == 0)
+                return WH_ERR_SHAPE;
+            if (!var_mode(desc->fmt, desc->rate, vmode, vparam))
+                return WH_ERR_FORMAT;
+            if (nbytes < var_index_bytes(desc->rows, desc->cols) + 16 || nbytes % 4)
+                return WH_ERR_FORMAT;
+            need = nbytes;
+        } else {
+            wh_status st = storage_bytes(*desc, need);
+            if (st != WH_OK)
+                return st;
+            if (nbytes != need)
+                return WH_ERR_FORMAT;
+        }
         Matrix m{};
         m.desc = *desc;
         m.nbytes = need;
@@ -314,6 +330,17 @@ wh_status wh_gemv(wh_ctx* ctx, wh_mat m, const float* d_u, float* d_y, uint32_t 
                              : (flags & WH_ACC_TWOSUM) ? AccMode::TwoSum
                                                        : AccMode::Fp64;
         hipStream_t st = static_cast<hipStream_t>(stream);
+        if (is_var_format(mat.desc.fmt)) {
+            if (mode == AccMode::PaperMp)
+                return WH_ERR_FORMAT;
+            const size_t pn = var_partials(mat, row_begin, row_end);
+            if (pn) {
+                wh_status s2 = ensure_partials(ctx, pn);
+                if (s2 != WH_OK)
+                    return s2;
+            }
+            return device_error(ctx, var_gemv(mat, mode, d_u, d_y, row_begin, row_end, pn ? ctx->part : nullptr, st));
+        }
         if (mat.desc.fmt == WH_FMT_ZFP_FIXED_RATE) {
             const GemvPlan pl =
                 whz_gemv_plan(mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
@@ -415,6 +442,8 @@ wh_status wh_decode(wh_ctx* ctx, wh_mat m, float* d_out, void* stream)
                 return WH_ERR_NOT_FOUND;
             mat = *p;
         }
+        if (is_var_format(mat.desc.fmt))
+            return device_error(ctx, var_decode(mat, d_out, static_cast<hipStream_t>(stream)));
         if (mat.desc.fmt != WH_FMT_ZFP_FIXED_RATE)
             return WH_ERR_FORMAT;
         return device_error(ctx, whz_decode_matrix(mat.desc.rate, mat.dptr, mat.desc.rows, mat.desc.cols, d_out,

@@ -27,8 +27,22 @@ struct HostPipe; // copy stream and staging of wh_gemv_host (host_stream.hip)
 // compressed bytes per copy.
 constexpr int kPipeBuffers = 2;
 constexpr uint64_t kPipeChunkBytes = 32ull << 20;
+// Creates the pipe's copy stream and events, no buffers (wh_create: the
+// stream is made before the process's other work; copies on a stream made
+// late in a busy process were measured at half speed).
+wh_status host_pipe_init(wh_ctx* ctx);
 // Waits for the pipe's copies and frees it (wh_destroy).
 void host_pipe_free(wh_ctx* ctx);
+
+// Variable-rate WHZ1 (fixed precision / fixed accuracy), whz_var.hip.
+inline bool is_var_format(int fmt) { return fmt == WH_FMT_ZFP_FIXED_PRECISION || fmt == WH_FMT_ZFP_FIXED_ACCURACY; }
+bool var_mode(int fmt, uint32_t rate, int& mode, int& param);
+uint32_t var_groups(uint32_t cols);
+uint64_t var_index_bytes(uint32_t rows, uint32_t cols);
+hipError_t var_decode(const Matrix& m, float* out, hipStream_t st);
+size_t var_partials(const Matrix& m, uint32_t row_begin, uint32_t row_end);
+hipError_t var_gemv(const Matrix& m, AccMode acc, const float* u, float* y, uint32_t row_begin, uint32_t row_end,
+                    double* part, hipStream_t st);
 
 wh_status device_error(wh_ctx* ctx, hipError_t e);
 wh_status ensure_partials(wh_ctx* ctx, size_t count);

@@ -285,9 +285,17 @@ __device__ __forceinline__ void decode_plane(const uint32_t* lw, const uint32_t*
         A[P] ^= x;
 }
 
+// Planes below this one may be cut by the bit budget without the exact
+// inverse lift leaving the int32 range: a cut at plane lo moves a
+// coefficient by less than 2^(lo+1), the 2-D inverse lift multiplies that by
+// at most 3.75^2, and the block's integers stay below 2^30 + 2^29.3 < 2^31.
+constexpr int kSafeCutPlane = 26;
+
+// `cut` ends true when the budget ended before plane kSafeCutPlane was read
+// in full (the block's top planes only), else false.
 template <int NW, int STRIDE, int P>
 __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uint32_t* tab, uint32_t& pos,
-                                                   uint32_t& nsig, uint32_t (&A)[16])
+                                                   uint32_t& nsig, uint32_t (&A)[16], bool& cut)
 {
     if constexpr (P >= 0) {
         if (!__any(pos < 32u * NW)) {
@@ -300,7 +308,9 @@ __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uin
             return;
         }
         decode_plane<NW, STRIDE, P>(lw, tab, pos, nsig, A);
-        decode_planes_from<NW, STRIDE, P - 1>(lw, tab, pos, nsig, A);
+        if constexpr (P == kSafeCutPlane)
+            cut = pos > 32u * NW;
+        decode_planes_from<NW, STRIDE, P - 1>(lw, tab, pos, nsig, A, cut);
     }
 }
 
@@ -319,16 +329,19 @@ constexpr int kStagedWords = NW + 3;
 // complement, at their block positions 4r + c, before the inverse
 // transform) and emax.  Returns false for an all-zero block (then cf[] is
 // all 0).  Every bit pattern decodes (the function is total).
+// `cut`: the budget ended above plane kSafeCutPlane (then only the exact
+// integer lift reproduces the decoded block; see lin_inv_lift).
 template <int NW, int STRIDE>
 __device__ __forceinline__ bool decode_block_coeffs(const uint32_t* lw, const uint32_t* tab, uint32_t w0, int& emax,
-                                                    uint32_t (&cf)[16])
+                                                    uint32_t (&cf)[16], bool& cut)
 {
     const bool nz = (w0 & 1u) != 0;
     emax = (int)((w0 >> 1) & 0xFFu) - 127;
     uint32_t pos = nz ? 9u : 32u * NW; // next bit to read; decoding stops at 32*NW
     uint32_t nsig = 0u;                 // coefficients 0..nsig-1 significant
     uint32_t A[16]; // every word is written by a plane or by the early exit
-    decode_planes_from<NW, STRIDE, 31>(lw, tab, pos, nsig, A);
+    cut = nz;       // a zero block is exact; others until plane kSafeCutPlane is read
+    decode_planes_from<NW, STRIDE, 31>(lw, tab, pos, nsig, A, cut);
     transpose_planes(A);
     // negabinary -> two's complement (the XOR came with the planes), undo
     // the sequency order
@@ -340,6 +353,14 @@ __device__ __forceinline__ bool decode_block_coeffs(const uint32_t* lw, const ui
 
 // The decoded block: its coefficients through the inverse transform, as
 // integers (value = iv * 2^(emax - 30)).
+template <int NW, int STRIDE>
+__device__ __forceinline__ bool decode_block_coeffs(const uint32_t* lw, const uint32_t* tab, uint32_t w0, int& emax,
+                                                    uint32_t (&cf)[16])
+{
+    bool cut;
+    return decode_block_coeffs<NW, STRIDE>(lw, tab, w0, emax, cf, cut);
+}
+
 template <int NW, int STRIDE>
 __device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, const uint32_t* tab, uint32_t w0, int& emax,
                                                   uint32_t (&iv)[16])
@@ -357,7 +378,11 @@ __device__ __forceinline__ bool decode_block_ints(const uint32_t* lw, const uint
 // those halvings (at most a few units of the block's last integer bit).
 // Hence a block's row sums against u are B (C (B^T u)): B^T u is a per-
 // column-block quantity, and B, being the same for every block, can be
-// applied once to a row group's accumulated sums.
+// applied once to a row group's accumulated sums.  This holds while the
+// integer lift stays inside int32; a block cut by the bit budget above plane
+// kSafeCutPlane can leave it (the exact lift wraps modulo 2^32), so such
+// blocks take the exact path: their decoded integers' row sums z, carried
+// back to coefficient space as L z (L = B^-1, the forward lift's linear part).
 template <typename T>
 __device__ __forceinline__ void lin_inv_lift(T& x, T& y, T& z, T& w)
 {

@@ -1,18 +1,20 @@
 // whz_kernels.hip -- WHZ1 kernels for gfx950: decode probe, full decode,
-// encoder, and the fused decode + mixed-precision GEMV (k = 1).
+// encoder, the fused decode + mixed-precision GEMV (k = 1) and the
+// multi-right-hand-side product.
 //
 // Fused GEMV (the deformation product y = C.S of Eq. 2 over a zfp-compressed
 // matrix, Sec. 4.3-4.4):
-//   grid     one workgroup (256 lanes, 4 waves) per (row tile, column slab);
-//            a row tile is TR block-rows (4*TR rows)
-//   lane     decodes one 4x4 block per step: the 256 lanes of a workgroup
-//            take 256 consecutive blocks of a block-row, so every step reads
-//            one contiguous run of the stream (16*rate*256/8 bytes)
-//   u        the lane's 4 values of u are loaded once per step and reused
-//            for all TR block-rows of the tile
-//   sums     FP32 within a block row (4 products), then FP64 (or
-//            compensated FP32) across blocks; wave shuffles + LDS for the
-//            reduction across lanes; one FP64 partial per row and slab
+//   grid     one 512-lane workgroup per (row tile, column slab)
+//   lanes    groups of 2^lg lanes (8 by default); a group sweeps one block
+//            row's slab, each lane decoding one 4x4 block per step (its
+//            words staged in LDS), so a wave works on an 8 x 8 patch of
+//            blocks; a tile holds (512 / 2^lg) x rpg block rows
+//   product  each block's coefficients against B^T u (FP32), its power-of-two
+//            scale applied to the sum; B once per block row at the end; blocks
+//            cut by the bit budget above plane 26 take the exact inverse lift
+//   sums     FP32 within a block (4 products), then FP64 (or compensated
+//            FP32) across blocks; shuffles within the group, LDS across
+//            waves; one FP64 partial per row and slab
 //   reduce   a second kernel adds the slab partials in FP64 and rounds once
 //            to FP32 (skipped when there is a single slab)
 #include <hip/hip_runtime.h>
@@ -222,6 +224,64 @@ struct TwoSumAcc {
 
 constexpr int kGemvThreads = (int)kGemvLanes;
 
+// L = B^-1 = (1/16) [[4, 4, 4, 4], [5, 1, -1, -5], [-4, 4, 4, -4],
+// [-2, 6, -6, 2]] (the forward lift's linear part) on (a, b, c, d).
+__device__ __forceinline__ void lin_fwd(float a, float b, float c, float d, float& o0, float& o1, float& o2,
+                                        float& o3)
+{
+    o0 = 0.25f * (a + b + c + d);
+    o1 = 0.0625f * (5.0f * (a - d) + (b - c));
+    o2 = 0.25f * ((b + c) - (a + d));
+    o3 = 0.0625f * (2.0f * (d - a) + 6.0f * (b - c));
+}
+
+// A block whose bit budget ended above plane kSafeCutPlane: its exact row
+// sums z = X u (X the decoded integers, through the integer inverse lift)
+// replace the coefficient-space sums by L z, so that applying B to the row
+// group's sums gives z back.
+__device__ __forceinline__ void exact_block_sums(const uint32_t (&cf)[16], float4 uu, float (&v)[4])
+{
+    uint32_t x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        x[i] = cf[i];
+    inv_xform(x);
+    float z[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        z[r] = (float)(int32_t)x[4 * r] * uu.x;
+        z[r] = __builtin_fmaf((float)(int32_t)x[4 * r + 1], uu.y, z[r]);
+        z[r] = __builtin_fmaf((float)(int32_t)x[4 * r + 2], uu.z, z[r]);
+        z[r] = __builtin_fmaf((float)(int32_t)x[4 * r + 3], uu.w, z[r]);
+    }
+    lin_fwd(z[0], z[1], z[2], z[3], v[0], v[1], v[2], v[3]);
+}
+
+// The same for the multi-RHS tile: the block's scaled coefficients become
+// L X L^T (X the exactly decoded integers), so that B (.) B^T gives X back.
+__device__ __forceinline__ void exact_block_coeffs(const uint32_t (&cf)[16], int emax, float (&sc)[16])
+{
+    uint32_t x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        x[i] = cf[i];
+    inv_xform(x);
+    float f[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        f[i] = (float)(int32_t)x[i];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        lin_fwd(f[4 * r], f[4 * r + 1], f[4 * r + 2], f[4 * r + 3], f[4 * r], f[4 * r + 1], f[4 * r + 2],
+                f[4 * r + 3]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        lin_fwd(f[c], f[4 + c], f[8 + c], f[12 + c], f[c], f[4 + c], f[8 + c], f[12 + c]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        sc[i] = __builtin_ldexpf(f[i], emax - 30);
+}
+
 // The workgroup's lanes form groups of 2^lg lanes (4 to 512).  A group
 // sweeps a block row's slab of block columns, its lanes striding them; the
 // workgroup's tile is (512 >> lg) groups x rpg block rows, group g taking the
@@ -301,18 +361,24 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
             } else {
                 // coefficients against B^T u (FP32); B is applied once to the
                 // row group's sums below
-                decode_block_coeffs<NW, kGemvThreads>(row, tab, w[0], emax, iv);
+                bool cut;
+                decode_block_coeffs<NW, kGemvThreads>(row, tab, w[0], emax, iv, cut);
                 float ut[4];
                 lin_bt_u<float>(uu.x, uu.y, uu.z, uu.w, ut);
                 const int k = emax - 30;
+                float v[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    float v = (float)(int32_t)iv[4 * r] * ut[0];
-                    v = __builtin_fmaf((float)(int32_t)iv[4 * r + 1], ut[1], v);
-                    v = __builtin_fmaf((float)(int32_t)iv[4 * r + 2], ut[2], v);
-                    v = __builtin_fmaf((float)(int32_t)iv[4 * r + 3], ut[3], v);
-                    acc[r].add(__builtin_ldexpf(v, k));
+                    v[r] = (float)(int32_t)iv[4 * r] * ut[0];
+                    v[r] = __builtin_fmaf((float)(int32_t)iv[4 * r + 1], ut[1], v[r]);
+                    v[r] = __builtin_fmaf((float)(int32_t)iv[4 * r + 2], ut[2], v[r]);
+                    v[r] = __builtin_fmaf((float)(int32_t)iv[4 * r + 3], ut[3], v[r]);
                 }
+                if (__any(cut) && cut) // rare: the exact lift, back to coefficient space
+                    exact_block_sums(iv, uu, v);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[r].add(__builtin_ldexpf(v[r], k));
             }
         }
         // reduce the row's sums across the group's lanes within the wave
@@ -510,11 +576,14 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
         }
         int emax;
         uint32_t cf[16];
-        decode_block_coeffs<NW, kMrhsThreads>(row, tab, w[0], emax, cf);
+        bool cut;
+        decode_block_coeffs<NW, kMrhsThreads>(row, tab, w[0], emax, cf, cut);
         float sc[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v)
             sc[v] = __builtin_ldexpf((float)(int32_t)cf[v], emax - 30);
+        if (__any(cut) && cut) // rare: the exact lift (see exact_block_coeffs)
+            exact_block_coeffs(cf, emax, sc);
         __syncthreads(); // staged slice complete
 #pragma unroll
         for (int n = 0; n < NT; ++n)

@@ -27,6 +27,12 @@ WH_ERR_INVALID, WH_ERR_SHAPE, WH_ERR_FORMAT, WH_ERR_NOMEM = -1, -2, -3, -4
 WH_ERR_BUDGET, WH_ERR_DEVICE, WH_ERR_NOT_FOUND = -5, -6, -7
 
 WH_FMT_ZFP_FIXED_RATE, WH_FMT_F32, WH_FMT_F16, WH_FMT_BF16, WH_FMT_FP8E4M3_BS4 = 1, 2, 3, 4, 5
+WH_FMT_ZFP_FIXED_PRECISION, WH_FMT_ZFP_FIXED_ACCURACY = 6, 7
+
+
+def accuracy_rate(minexp: int) -> int:
+    """desc.rate of WH_FMT_ZFP_FIXED_ACCURACY for the tolerance 2^minexp."""
+    return minexp + 1024
 WH_HOST, WH_DEVICE = 0, 1
 WH_ACC_DEFAULT, WH_ACC_FP64, WH_ACC_TWOSUM, WH_PAPER_MP, WH_HOST_DIRECT = 0, 1, 2, 4, 8
 WH_U_F32, WH_U_BF16 = 0, 1
@@ -66,6 +72,9 @@ _sig = {
     "wh_gemv": ([_P, _U64, _P, _P, _U32, _U32, _U32, _P], _I32),
     "wh_gemv_batched": ([_P, _U64, _P, ctypes.c_int, _U32, _U32, _P, _U32, _U32, _P], _I32),
     "wh_gemv_host": ([_P, _P, _U32, _U32, _U32, _P, _P, _U32, _U32, _U32, _U32, _P], _I32),
+    "wh_var_index_bytes": ([_U32, _U32], _U64),
+    "wh_var_capacity_bytes": ([_U32, _U32], _U64),
+    "wh_encode_var": ([_P, _U32, _U32, _I32, _U32, _P, _U64, ctypes.POINTER(_U64)], _I32),
     "wh_host_alloc": ([_U64, ctypes.POINTER(ctypes.c_void_p)], _I32),
     "wh_host_free": ([_P], _I32),
     "wh_thermal_step": ([_P, _U32, _U32, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
@@ -219,6 +228,24 @@ def wh_gemv_host(ctx: int, h_code, rows: int, cols: int, rate: int, u: torch.Ten
     _borrowed[(ctx, "host_code")] = h_code
     _check(_lib.wh_gemv_host(ctx, ptr, rows, cols, rate, _dptr(u, torch.float32, "u"), _dptr(y, torch.float32, "y"),
                              row_begin, row_end, chunk_rows, flags, _stream(stream)), "wh_gemv_host")
+
+
+def wh_encode_var(M, fmt: int, rate: int):
+    """Host encoder of the variable-rate formats: M (rows, cols) float32
+    numpy -> the storage bytes (uint8 numpy) for wh_load_compressed."""
+    import numpy as np
+    M = np.ascontiguousarray(M, dtype=np.float32)
+    rows, cols = M.shape
+    cap = int(_lib.wh_var_capacity_bytes(rows, cols))
+    out = np.empty(cap, dtype=np.uint8)
+    n = _U64()
+    _check(_lib.wh_encode_var(M.ctypes.data, rows, cols, fmt, rate, out.ctypes.data, cap, ctypes.byref(n)),
+           "wh_encode_var")
+    return out[: n.value].copy()
+
+
+def wh_var_index_bytes(rows: int, cols: int) -> int:
+    return int(_lib.wh_var_index_bytes(rows, cols))
 
 
 class HostBuffer:

@@ -114,3 +114,23 @@ def test_mrhs_argument_errors(gpu_ctx, small_mrhs):
         wh.wh_gemv_batched(gpu_ctx, mat, torch.zeros((4, 4000), device="cuda"), Y[:4])
     assert ei.value.status == wh.WH_ERR_SHAPE
     wh.wh_unload(gpu_ctx, mat)
+
+
+@pytest.mark.parametrize("rate", [2, 4, 6])
+@pytest.mark.parametrize("k", [3, 16])
+def test_mrhs_low_rates_wide_range(gpu_ctx, rate, k):
+    """Rates where the bit budget cuts coefficients to their top planes,
+    on wide-range data (rows scaled by 2^-30 .. 2^10, signs mixed): blocks
+    cut above plane 26 take the exact inverse lift."""
+    rng = np.random.default_rng(100 + rate)
+    M = (rng.standard_normal((256, 1024)) * np.exp2(rng.integers(-30, 10, size=(256, 1)))).astype(np.float32)
+    s = oracle.encode(M, rate)
+    Mhat = oracle.decode(s, 256, 1024, rate).astype(np.float64)
+    U = synth.uniform(k * 1024, seed=rate).reshape(k, 1024)
+    ref = U.astype(np.float64) @ Mhat.T
+    mat = wh.wh_load_compressed(gpu_ctx, 256, 1024, wh.WH_FMT_ZFP_FIXED_RATE, rate, s)
+    Y = torch.empty((k, 256), dtype=torch.float32, device="cuda")
+    wh.wh_gemv_batched(gpu_ctx, mat, torch.from_numpy(U).cuda(), Y)
+    torch.cuda.synchronize()
+    assert per_rhs_rel_l2(Y.cpu().numpy(), ref).max() <= 1e-6
+    wh.wh_unload(gpu_ctx, mat)

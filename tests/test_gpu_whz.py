@@ -111,6 +111,31 @@ def test_encode_decode_extremes_bitexact(gpu_ctx, rate):
     wh.wh_unload(gpu_ctx, mat)
 
 
+@pytest.mark.parametrize("rate", [2, 4, 6, 12])
+@pytest.mark.parametrize("which", ["synthetic", "wide_range"])
+def test_gemv_low_and_mid_rates(gpu_ctx, rate, which):
+    """The fused GEMV at rates where the bit budget cuts the coefficients to
+    their top planes, against the FP64 GEMV of the oracle-decoded matrix
+    (wide_range: rows scaled by 2^-30 .. 2^10, signs mixed)."""
+    if which == "synthetic":
+        M = synth.matrix(synth.MatrixSpec(256, 1024, 32, 8.0, seed=9))
+    else:
+        rng = np.random.default_rng(rate)
+        M = (rng.standard_normal((256, 1024)) * np.exp2(rng.integers(-30, 10, size=(256, 1)))).astype(np.float32)
+    rows, cols = M.shape
+    s = oracle.encode(M, rate)
+    mat = wh.wh_load_compressed(gpu_ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, s)
+    u_np = synth.uniform(cols, seed=3)
+    ref = oracle.gemv_fp64(s, rows, cols, rate, u_np)
+    y = torch.empty(rows, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u_np).cuda(), y, 0, rows)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy().astype(np.float64)
+    err = float(np.linalg.norm(yh - ref) / np.linalg.norm(ref))
+    assert err <= 1e-6, err
+    wh.wh_unload(gpu_ctx, mat)
+
+
 def test_encode_counts_nonfinite(gpu_ctx):
     M = np.ones((8, 8), dtype=np.float32)
     M[0, 0] = np.nan
