@@ -163,6 +163,15 @@ wh_status wh_unload(wh_ctx *ctx, wh_mat m);
 wh_status wh_gemv(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t row_begin, uint32_t row_end,
                   uint32_t flags, void *stream);
 
+/* The launch shape the fused compressed GEMV would use for rows
+ * [row_begin, row_end) of a rows x cols matrix on a device with num_cus
+ * CUs (diagnostics; no context, no GPU): out8 = {lanes per block row, block
+ * rows per lane group, row tiles, column slabs, block columns per slab,
+ * first block row, one past the last block row, rows of the first block row
+ * before the range}.  The workgroups launched are row tiles x column slabs. */
+wh_status wh_gemv_plan_info(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
+                            uint32_t *out8);
+
 /* Y = M U for k right-hand sides (Sec. 4.4, batched).  d_U: k vectors of
  * cols values, vector r at d_U + r*ldu (ldu >= cols), dtype 0 = FP32,
  * 1 = BF16.  d_Y: k vectors of rows FP32 at d_Y + r*ldy (ldy >= rows).

@@ -204,6 +204,19 @@ wh_status wh_destroy(wh_ctx* ctx)
     }
 }
 
+wh_status wh_gemv_plan_info(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
+                            uint32_t* out8)
+{
+    if (!out8 || rows == 0 || cols == 0 || row_begin > row_end || row_end > rows)
+        return WH_ERR_INVALID;
+    GemvTuning none;
+    const GemvPlan pl = whz_gemv_plan(rows, cols, row_begin, row_end, num_cus, &none);
+    const uint32_t v[8] = {1u << pl.lg, pl.rpg, pl.ntiles, pl.nslab, pl.slab_bc, pl.bi_begin, pl.bi_end, pl.skip};
+    for (int i = 0; i < 8; ++i)
+        out8[i] = v[i];
+    return WH_OK;
+}
+
 wh_status wh_storage_bytes(const wh_matrix_desc* desc, uint64_t* nbytes)
 {
     if (!desc || !nbytes)

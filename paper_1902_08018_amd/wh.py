@@ -72,6 +72,7 @@ _sig = {
     "wh_gemv": ([_P, _U64, _P, _P, _U32, _U32, _U32, _P], _I32),
     "wh_gemv_batched": ([_P, _U64, _P, ctypes.c_int, _U32, _U32, _P, _U32, _U32, _P], _I32),
     "wh_gemv_host": ([_P, _P, _U32, _U32, _U32, _P, _P, _U32, _U32, _U32, _U32, _P], _I32),
+    "wh_gemv_plan_info": ([_U32, _U32, _U32, _U32, ctypes.c_int, ctypes.POINTER(_U32)], _I32),
     "wh_var_index_bytes": ([_U32, _U32], _U64),
     "wh_var_capacity_bytes": ([_U32, _U32], _U64),
     "wh_encode_var": ([_P, _U32, _U32, _I32, _U32, _P, _U64, ctypes.POINTER(_U64)], _I32),
@@ -242,6 +243,15 @@ def wh_encode_var(M, fmt: int, rate: int):
     _check(_lib.wh_encode_var(M.ctypes.data, rows, cols, fmt, rate, out.ctypes.data, cap, ctypes.byref(n)),
            "wh_encode_var")
     return out[: n.value].copy()
+
+
+def wh_gemv_plan_info(rows: int, cols: int, row_begin: int = 0, row_end: int | None = None,
+                      num_cus: int = 256) -> dict:
+    row_end = rows if row_end is None else row_end
+    out = (_U32 * 8)()
+    _check(_lib.wh_gemv_plan_info(rows, cols, row_begin, row_end, num_cus, out), "wh_gemv_plan_info")
+    keys = ("lanes", "rows_per_group", "ntiles", "nslab", "slab_bc", "bi_begin", "bi_end", "skip")
+    return dict(zip(keys, [int(x) for x in out]))
 
 
 def wh_var_index_bytes(rows: int, cols: int) -> int:
