@@ -149,29 +149,37 @@ __device__ __forceinline__ void transpose_planes(uint32_t (&A)[16])
 // the scan reaches coefficient 15 inside a run its 1 is implied.
 //
 // Table entry for (nsig, state, 8 bits), state 0 = at a group bit, 1 =
-// inside a run; index (nsig << 9) | (state << 8) | bits:
-//   bits  0..3   stream bits consumed (0..8)
-//   bits  4..7   coefficients passed (nsig advances by this much, 0..9)
-//   bit   8      state to continue in when the section did not end
-//   bit  10      it ended at coefficient 15 inside a run (whose 1 is implied,
-//                not read; the entry leaves that coefficient out of its ones)
-//   bit  15      the section ended (above every index bit, so that adding it
-//                to the next index lands past the table)
-//   bits 16..31  coefficients that became significant, at their absolute
-//                positions (the table is indexed by nsig), so an entry ORs
-//                straight into the plane word in the high half
-// One more entry, kSecDone, is "ended, nothing consumed": a lane whose
-// section has ended reads it, so every step runs unpredicated.
+// inside a run; index (nsig << 9) | (state << 8) | bits.  The fields sit
+// where the decoder can take them without masking:
+//   bits  0..15  coefficients that became significant, at their absolute
+//                positions (the table is indexed by nsig), including
+//                coefficient 15's implied 1; they OR straight into the plane
+//                word's low half
+//   bits 16..19  stream bits consumed (0..8); bits 20..23 are zero, so the
+//                whole byte is the count
+//   bit  24      state to continue in when the section did not end
+//   bits 25..28  coefficients passed (nsig advances by this much, 0..9)
+//   bit  31      the section ended: the sign bit, tested without a mask
+// (e >> 16) & 0x8100 puts the state at index bit 8 and the ended flag at bit
+// 15, past every index of the table.  One more entry, kSecDone, is "ended,
+// nothing consumed": a lane whose section has ended reads it, so every step
+// runs unpredicated.
 constexpr int kSecBits = 8;
 constexpr int kSecN = 17; // nsig 0..16
 constexpr int kSecDone = kSecN * 2 * (1 << kSecBits);
 constexpr int kSecEntries = kSecDone + 1;
-constexpr uint32_t kEntState = 1u << 8, kEntImplied = 1u << 10, kEntDone = 1u << 15;
-static_assert(kSecDone <= (int)kEntDone, "the done flag must lift an index past the table");
+constexpr uint32_t kEntState = 1u << 24, kEntDone = 1u << 31;
+static_assert(kSecDone <= (int)(kEntDone >> 16), "the done flag must lift an index past the table");
+
+__host__ __device__ __forceinline__ constexpr uint32_t ent_used(uint32_t e) { return (e >> 16) & 0xFFu; }
+__host__ __device__ __forceinline__ constexpr uint32_t ent_adv(uint32_t e) { return (e >> 25) & 15u; }
+__host__ __device__ __forceinline__ constexpr bool ent_open(uint32_t e) { return (int32_t)e >= 0; }
+// the entry's part of the next index: state at bit 8, ended flag at bit 15
+__host__ __device__ __forceinline__ constexpr uint32_t ent_next(uint32_t e) { return (e >> 16) & 0x8100u; }
 
 __host__ __device__ constexpr uint32_t section_entry(int state, int nsig, int bits)
 {
-    int used = 0, adv = 0, done = 0, implied = 0, st = state;
+    int used = 0, adv = 0, done = 0, st = state;
     uint32_t ones = 0;
     for (;;) {
         if (st == 0) {
@@ -190,9 +198,9 @@ __host__ __device__ constexpr uint32_t section_entry(int state, int nsig, int bi
             st = 1;
         } else {
             if (nsig + adv == 15) { // coefficient 15: its 1 is implied, not read
+                ones |= 1u << 15;
                 ++adv;
                 done = 1;
-                implied = 1;
                 break;
             }
             if (used == kSecBits)
@@ -206,8 +214,8 @@ __host__ __device__ constexpr uint32_t section_entry(int state, int nsig, int bi
             ++adv;
         }
     }
-    return (uint32_t)used | (uint32_t)adv << 4 | (done ? 0u : (uint32_t)st << 8) | (uint32_t)done << 15 |
-           (uint32_t)implied << 10 | ones << 16;
+    return ones | (uint32_t)used << 16 | (done ? 0u : (uint32_t)st << 24) | (uint32_t)adv << 25 |
+           (done ? kEntDone : 0u);
 }
 
 struct SectionTable {
@@ -238,10 +246,13 @@ __host__ __device__ constexpr uint32_t kOddPlanes(int q) { return (q & 1) ? 0xFF
 // everywhere except when the bit budget runs out inside a run: there the
 // zero bits walk on to coefficient 15, where the code instead sets the
 // coefficient the run had reached when the budget ended.  The number of
-// zeros read past the end says which one that was.
+// zeros read past the end says which one that was.  Only planes in which
+// some lane of the wave is past its budget pay for that correction.
+//
+// Returns the wave's mask of lanes past their budget.
 template <int NW, int STRIDE, int P>
-__device__ __forceinline__ void decode_plane(const uint32_t* lw, const uint32_t* tab, uint32_t& pos, uint32_t& nsig,
-                                             uint32_t (&A)[16])
+__device__ __forceinline__ uint64_t decode_plane(const uint32_t* lw, const uint32_t* tab, uint32_t& pos,
+                                                 uint32_t& nsig, uint32_t (&A)[16])
 {
     constexpr uint32_t kMaxBits = 32u * NW;
     // word of pos (positions stay below 1024: kMaxBits + 32 + one plane)
@@ -252,37 +263,43 @@ __device__ __forceinline__ void decode_plane(const uint32_t* lw, const uint32_t*
     // (i) verbatim bits of the significant coefficients
     const uint32_t xv = __builtin_amdgcn_ubfe(lo, 0u, nsig);
     // (ii) group tests, 8 bits per table lookup; the plane's new ones collect
-    // in the high half of acc (its low half gathers flag bits only)
+    // in the low half of acc (its high half gathers other fields only)
     uint32_t e = tab[(nsig << 9) | __builtin_amdgcn_ubfe(lo, nsig, 8u)];
     uint32_t acc = e;
-    uint32_t at = pos + nsig + (e & 15u); // next unread bit
-    nsig += (e >> 4) & 15u;
-    if (__any(!(e & kEntDone))) {
+    uint32_t at = pos + nsig + ent_used(e); // next unread bit
+    nsig += ent_adv(e);
+    if (__any(ent_open(e))) {
         do {
             q = __builtin_amdgcn_ubfe(at, 5u, 5u);
             const uint32_t bits = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], at & 31u);
-            uint32_t idx = (nsig << 9) + (e & (kEntState | kEntDone)); // ended: >= kSecDone
+            uint32_t idx = (nsig << 9) + ent_next(e); // ended: >= kSecDone
             idx |= bits & 0xFFu;
             e = tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
             acc |= e;
-            at += e & 15u;
-            nsig += (e >> 4) & 15u;
-        } while (__any(!(e & kEntDone)));
+            at += ent_used(e);
+            nsig += ent_adv(e);
+        } while (__any(ent_open(e)));
     }
-    // the implied 1 of coefficient 15, moved back to where the run stood when
-    // the budget ended if the run read past the end (at - kMaxBits zeros)
-    const int back = (int)kMaxBits + 21 - (int)at; // 21 - (bits read past the end)
-    const uint32_t sh = (uint32_t)(back < 6 ? 6 : (back > 21 ? 21 : back));
-    acc |= (acc & kEntImplied) << sh;
-    const uint32_t x = xv + (acc >> 16); // disjoint bit ranges
-    // a lane past the end of its block reads only zero bits: its plane word is
-    // zero and its state stays put; keep its position inside the padding
-    pos = at < kMaxBits + 32u ? at : kMaxBits + 32u;
-    // plane words arrive complemented on odd planes (see decode_block_ints)
+    const uint64_t past = __ballot(at >= kMaxBits);
+    if (__builtin_expect(past != 0, 0)) { // a branch, not selects on every plane
+        // the implied 1 of coefficient 15 moves back to where the run stood
+        // when the budget ended (ex = zeros read past the end; ex <= 15
+        // wherever that 1 is set)
+        const uint32_t ex = __builtin_elementwise_sub_sat(at, kMaxBits);
+        const uint32_t m = acc & 0x8000u;
+        acc ^= m ^ (m >> (ex & 31u));
+        // a lane past the end reads only zero bits: its plane word is zero
+        // and its state stays put; keep its position inside the padding
+        at = __builtin_elementwise_min(at, kMaxBits + 32u);
+    }
+    pos = at;
+    const uint32_t x = (acc & 0xFFFFu) | xv; // disjoint bit ranges
+    // plane words arrive complemented on odd planes (see decode_block_coeffs)
     if constexpr (P >= 16)
         A[P - 16] = (x << 16) ^ kOddPlanes(P - 16);
     else
         A[P] ^= x;
+    return past;
 }
 
 // Planes below this one may be cut by the bit budget without the exact
@@ -292,13 +309,14 @@ __device__ __forceinline__ void decode_plane(const uint32_t* lw, const uint32_t*
 constexpr int kSafeCutPlane = 26;
 
 // `cut` ends true when the budget ended before plane kSafeCutPlane was read
-// in full (the block's top planes only), else false.
+// in full (the block's top planes only), else false.  `past`: the wave's
+// lanes already past their budget.
 template <int NW, int STRIDE, int P>
 __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uint32_t* tab, uint32_t& pos,
-                                                   uint32_t& nsig, uint32_t (&A)[16], bool& cut)
+                                                   uint32_t& nsig, uint32_t (&A)[16], bool& cut, uint64_t past)
 {
     if constexpr (P >= 0) {
-        if (!__any(pos < 32u * NW)) {
+        if (past == __builtin_amdgcn_read_exec()) {
             // planes P..0 stay zero: words 0..P-16 were never written
             if constexpr (P >= 16) {
 #pragma unroll
@@ -307,10 +325,10 @@ __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uin
             }
             return;
         }
-        decode_plane<NW, STRIDE, P>(lw, tab, pos, nsig, A);
+        past = decode_plane<NW, STRIDE, P>(lw, tab, pos, nsig, A);
         if constexpr (P == kSafeCutPlane)
             cut = pos > 32u * NW;
-        decode_planes_from<NW, STRIDE, P - 1>(lw, tab, pos, nsig, A, cut);
+        decode_planes_from<NW, STRIDE, P - 1>(lw, tab, pos, nsig, A, cut, past);
     }
 }
 
@@ -341,7 +359,7 @@ __device__ __forceinline__ bool decode_block_coeffs(const uint32_t* lw, const ui
     uint32_t nsig = 0u;                 // coefficients 0..nsig-1 significant
     uint32_t A[16]; // every word is written by a plane or by the early exit
     cut = nz;       // a zero block is exact; others until plane kSafeCutPlane is read
-    decode_planes_from<NW, STRIDE, 31>(lw, tab, pos, nsig, A, cut);
+    decode_planes_from<NW, STRIDE, 31>(lw, tab, pos, nsig, A, cut, __ballot(!nz));
     transpose_planes(A);
     // negabinary -> two's complement (the XOR came with the planes), undo
     // the sequency order

@@ -85,21 +85,20 @@ __device__ __forceinline__ void var_plane(const uint32_t* g, uint32_t lim, const
     const uint32_t xv = __builtin_amdgcn_ubfe(w, 0u, nsig);
     uint32_t e = tab[(nsig << 9) | __builtin_amdgcn_ubfe(w, nsig, 8u)];
     uint32_t acc = e;
-    uint32_t at = pos + nsig + (e & 15u);
-    nsig += (e >> 4) & 15u;
-    if (__any(!(e & kEntDone))) {
+    uint32_t at = pos + nsig + ent_used(e);
+    nsig += ent_adv(e);
+    if (__any(ent_open(e))) {
         do {
             const uint32_t bits = live ? vwindow(g, lim, at) : 0u;
-            uint32_t idx = (nsig << 9) + (e & (kEntState | kEntDone));
+            uint32_t idx = (nsig << 9) + ent_next(e);
             idx |= bits & 0xFFu;
             e = tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
             acc |= e;
-            at += e & 15u;
-            nsig += (e >> 4) & 15u;
-        } while (__any(!(e & kEntDone)));
+            at += ent_used(e);
+            nsig += ent_adv(e);
+        } while (__any(ent_open(e)));
     }
-    acc |= (acc & kEntImplied) << 21;
-    const uint32_t x = xv + (acc >> 16);
+    const uint32_t x = (acc & 0xFFFFu) | xv; // coefficient 15's implied 1 is in the table's ones
     if (live)
         pos = at;
     if constexpr (P >= 16)

@@ -59,15 +59,31 @@ static inline uint32_t __builtin_amdgcn_perm(uint32_t s0, uint32_t s1, uint32_t 
     }
     return r;
 }
+static inline uint32_t coin()
+{
+    g_lcg = g_lcg * 6364136223846793005ull + 1442695040888963407ull;
+    return (uint32_t)(g_lcg >> 63);
+}
 // wave vote of a one-lane wave; with idle lanes, "some other lane is still
 // busy" half the time when this lane's predicate is false
 static inline int __any(int p)
 {
     if (p || !g_idle_lanes)
         return p;
-    g_lcg = g_lcg * 6364136223846793005ull + 1442695040888963407ull;
-    return (int)((g_lcg >> 63) & 1u);
+    return (int)coin();
 }
+// the active lanes: this lane (bit 0) and, with idle lanes, one more (bit 1)
+static inline uint64_t __builtin_amdgcn_read_exec() { return g_idle_lanes ? 3u : 1u; }
+// ballot over the active lanes; the other lane's predicate is a coin toss
+static inline uint64_t __ballot(int p)
+{
+    uint64_t m = p ? 1u : 0u;
+    if (g_idle_lanes)
+        m |= (uint64_t)coin() << 1;
+    return m;
+}
+// v_sub_u32 with clamp: a - b, or 0 where b > a
+#define __builtin_elementwise_sub_sat(a, b) ((a) > (b) ? (a) - (b) : 0u)
 static inline uint32_t __float_as_uint(float f)
 {
     uint32_t u;
