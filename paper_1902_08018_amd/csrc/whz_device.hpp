@@ -38,6 +38,22 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh
     return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
+// The word of a staged row that holds bit position pos: pos >> 5.  On the
+// GPU the shift is opaque to the compiler, so a row address q * STRIDE +
+// base stays one shift-add; seen through, (pos >> 5) << 11 is rewritten as
+// a shift and a mask, one instruction more per window read.  The host build
+// of this header (CPU tests) takes the plain shift.
+__device__ __forceinline__ uint32_t word_of(uint32_t pos)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t q;
+    asm("v_lshrrev_b32 %0, 5, %1" : "=v"(q) : "v"(pos));
+    return q;
+#else
+    return pos >> 5;
+#endif
+}
+
 __device__ __forceinline__ uint32_t asr1(uint32_t v) { return (uint32_t)((int32_t)v >> 1); }
 
 // ---------------------------------------------------------------- lifting
@@ -256,29 +272,28 @@ __device__ __forceinline__ uint64_t decode_plane(const uint32_t* lw, const uint3
 {
     constexpr uint32_t kMaxBits = 32u * NW;
     // word of pos (positions stay below 1024: kMaxBits + 32 + one plane)
-    uint32_t q = __builtin_amdgcn_ubfe(pos, 5u, 5u);
+    uint32_t q = word_of(pos);
     // 32 bits from pos: the verbatim bits (nsig <= 16) and the first 8
     // section bits always fit
     const uint32_t lo = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], pos & 31u);
     // (i) verbatim bits of the significant coefficients
     const uint32_t xv = __builtin_amdgcn_ubfe(lo, 0u, nsig);
-    // (ii) group tests, 8 bits per table lookup; the plane's new ones collect
-    // in the low half of acc (its high half gathers other fields only)
-    uint32_t e = tab[(nsig << 9) | __builtin_amdgcn_ubfe(lo, nsig, 8u)];
-    uint32_t acc = e;
-    uint32_t at = pos + nsig + ent_used(e); // next unread bit
-    nsig += ent_adv(e);
-    if (__any(ent_open(e))) {
+    // (ii) group tests, 8 bits per table lookup.  acc's low half collects
+    // the plane's new ones; its high half is the latest entry's fields, so
+    // the loop carries no separate copy of the entry
+    uint32_t acc = tab[(nsig << 9) | __builtin_amdgcn_ubfe(lo, nsig, 8u)];
+    uint32_t at = pos + nsig + ent_used(acc); // next unread bit
+    nsig += ent_adv(acc);
+    if (__any(ent_open(acc))) {
         do {
-            q = __builtin_amdgcn_ubfe(at, 5u, 5u);
+            q = word_of(at);
             const uint32_t bits = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], at & 31u);
-            uint32_t idx = (nsig << 9) + ent_next(e); // ended: >= kSecDone
+            uint32_t idx = (nsig << 9) + ent_next(acc); // ended: >= kSecDone
             idx |= bits & 0xFFu;
-            e = tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
-            acc |= e;
-            at += ent_used(e);
-            nsig += ent_adv(e);
-        } while (__any(ent_open(e)));
+            acc = (acc & 0xFFFFu) | tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
+            at += ent_used(acc);
+            nsig += ent_adv(acc);
+        } while (__any(ent_open(acc)));
     }
     const uint64_t past = __ballot(at >= kMaxBits);
     if (__builtin_expect(past != 0, 0)) { // a branch, not selects on every plane
