@@ -11,8 +11,12 @@ resident before timing starts; 4 different u vectors rotate across steps.
 Prints one JSON line.  `value` is the effective bandwidth in the paper's
 decoder convention (uncompressed FP32 bytes of M per second, Sec. 4.3);
 `roofline` prices the kernel's algorithmic bytes (compressed stream + u + y)
-against the 8 TB/s HBM peak; `cpu_baseline` times the CPU oracle on a
-bounded sample of the same workload on this host.
+against the 8 TB/s HBM peak, with the box's measured copy ceiling beside
+it and, when a counter run on the same kernel source is on file, the VALU
+issue roofline that actually bounds the decoder; `cpu_baseline` times the CPU
+oracle on a bounded sample of the same workload on this host (all cores and
+one core); `parity_vs_oracle` checks the timed configuration's first rows
+against the oracle's FP64 GEMV.
 """
 from __future__ import annotations
 
@@ -24,6 +28,9 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue: 256 CUs x 64 lanes (4 SIMDs x 16 lanes) x 2.4 GHz, in T lane-ops/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+PARITY_ROWS = 256
 
 
 def parse():
@@ -373,9 +380,12 @@ def bench_var(ctx, steps):
     return res
 
 
-def cpu_baseline(size, rate):
+def cpu_baseline(size, rate, y_gpu=None):
     """The CPU oracle (decode + FP64 GEMV, threads over block-rows) on a
-    bounded sample: whole rows of the same matrix, encoded by the oracle."""
+    bounded sample: whole rows of the same matrix, encoded by the oracle.
+    Timed on all the process's cores (up to 16) and on one core.  With
+    y_gpu (the GPU's y for u = the spec's dose vector), also the relative L2
+    error of its first rows against the oracle's FP64 GEMV of the same rows."""
     import numpy as np
     import oracle
     from paper_1902_08018_amd import synth
@@ -385,26 +395,43 @@ def cpu_baseline(size, rate):
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))
-    nrows = 16 * cores  # 4 block-rows per thread
+    nrows = 16 * max(cores, 16)  # 4 block-rows per thread, and at least the 256 rows of the parity check
     M = synth.matrix_rows(spec, 0, nrows)
     s = oracle.encode(M, rate)
     u = synth.u_vector(spec)
-    oracle.gemv_fp64(s, nrows, spec.cols, rate, u, nthreads=cores)  # warm
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        oracle.gemv_fp64(s, nrows, spec.cols, rate, u, nthreads=cores)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el * cores >= 10.0 or reps >= 50:
-            break
+    y_ref = oracle.gemv_fp64(s, nrows, spec.cols, rate, u, nthreads=cores)  # warm, and the parity reference
+
+    def timed(n, threads, budget_s):
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            oracle.gemv_fp64(s, n, spec.cols, rate, u, nthreads=threads)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el * threads >= budget_s or reps >= 50:
+                return el, reps
+
+    el, reps = timed(nrows, cores, 10.0)
     sec = el / reps
     eff_gbs = nrows * spec.cols * 4 / sec / 1e9
-    return {"value": round(eff_gbs, 4), "unit": "GB/s effective (uncompressed FP32 bytes/s)", "cores": cores,
+    n1 = 16  # four block-rows on one core
+    el1, reps1 = timed(n1, 1, 1.0)
+    sec1 = el1 / reps1
+    base = {"value": round(eff_gbs, 4), "unit": "GB/s effective (uncompressed FP32 bytes/s)", "cores": cores,
             "kind": "oracle",
             "sample": f"rows 0..{nrows} of the {spec.rows}x{spec.cols} matrix (all columns), rate {rate}, "
                       f"oracle decode + FP64 GEMV, {reps} reps, {el:.1f} s wall",
-            "gflops": round(nrows * (2 * spec.cols - 1) / sec / 1e9, 4)}
+            "gflops": round(nrows * (2 * spec.cols - 1) / sec / 1e9, 4),
+            "single_core": {"value": round(n1 * spec.cols * 4 / sec1 / 1e9, 4),
+                            "gflops": round(n1 * (2 * spec.cols - 1) / sec1 / 1e9, 4),
+                            "sample": f"rows 0..{n1}, {reps1} reps, {el1:.2f} s wall"}}
+    parity = None
+    if y_gpu is not None:
+        n = min(len(y_gpu), nrows)
+        d = np.asarray(y_gpu[:n], np.float64) - y_ref[:n]
+        parity = {"rows": f"0..{n}", "rel_l2": float(np.linalg.norm(d) / np.linalg.norm(y_ref[:n])),
+                  "max_abs": float(np.abs(d).max()), "tolerance": 1e-6}
+    return base, parity
 
 
 SERVING_SPECS = {
@@ -540,14 +567,26 @@ def main():
     flop = rows * (2 * cols - 1)
     # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes,
     # valid only for the kernel source they were taken on
-    traffic = None
+    traffic = valu_insts = None
     try:
         with open(args.traffic_json) as f:
             tj = json.load(f).get(f"whz_gemv_rate{rate}_{rows}x{cols}")
         if tj and tj.get("kernel_source_sha256_16") == kernel_source_hash():
             traffic = tj.get("bytes_per_launch")
+            valu_insts = tj.get("sq_insts_valu")
     except (OSError, ValueError):
         pass
+    # the timed configuration once more with u = the spec's dose vector: its
+    # first rows go to the oracle's check
+    wh.wh_gemv(ctx, mat, us[0], y, 0, rows, args.flags)
+    torch.cuda.synchronize()
+    y_head = y[:PARITY_ROWS].cpu().numpy()
+    # the box's streaming ceiling: a plain 4 GiB device-to-device copy
+    ca = torch.empty(1 << 30, dtype=torch.int32, device="cuda").fill_(1)
+    cb = torch.empty_like(ca)
+    copy_ms = time_call(lambda i: cb.copy_(ca), 5, 2)
+    copy_gbs = 2 * ca.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del ca, cb
     out = {
         "metric": "decode+GEMV effective GB/s (frac of HBM peak), GFLOP/s; p99 latency vs deadline",
         "value": round(eff_gbs, 2),
@@ -571,8 +610,17 @@ def main():
         "kernel_ms": round(kern_ms, 4),
         "kernel_ms_p10_p50_p90": [round(float(x), 4) for x in __import__("numpy").percentile(ev_ms, [10, 50, 90])],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "copy_ceiling_gbs": round(copy_gbs, 1)},
     }
+    if valu_insts:
+        # the decoder's own bound: VALU issue, 64 lanes per wave64 instruction
+        # (SQ_INSTS_VALU of a counter run on this kernel source) over this run's
+        # kernel time, against one wave64 instruction per CU per cycle
+        ops = valu_insts * 64
+        out["roofline"]["valu"] = {"lane_ops_per_launch": ops, "achieved": round(ops / (kern_ms * 1e-3) / 1e12, 2),
+                                   "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                                   "frac": round(ops / (kern_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
     wh.wh_unload(ctx, mat)
     del stream
     torch.cuda.empty_cache()
@@ -664,8 +712,9 @@ def main():
                                                             n_measured=args.serving_requests)
 
     if args.cpu_baseline:
-        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(size, rate)
+        print("# cpu baseline (oracle), and the oracle's check of the timed launch's first rows",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"], out["parity_vs_oracle"] = cpu_baseline(size, rate, y_head)
     wh.wh_destroy(ctx)
     print(json.dumps(out), flush=True)
 
