@@ -15,8 +15,10 @@
 //
 // Decoding: one lane per group of 32 blocks, the blocks in sequence; the
 // lanes of a wave run the bit planes in lockstep (as the fixed-rate decoder),
-// each with its own lowest plane, reading 32-bit windows of the code from
-// global memory.  The fused GEMV gives 1 to 8 lanes (groups) to a block row
+// each with its own lowest plane.  Before each block a lane copies the next
+// 20 words of its code into its own LDS row (word-major, as the fixed-rate
+// staging), so the decoder's window reads are LDS reads, not chains of
+// dependent global loads.  The fused GEMV gives 1 to 8 lanes (groups) to a block row
 // and multiplies each block's exactly decoded values by u.  The encoder runs
 // on the host (the paper encodes offline, Sec. 3.2).
 #include <hip/hip_runtime.h>
@@ -37,7 +39,7 @@ namespace wh {
 
 namespace {
 
-constexpr int kVarThreads = 512;
+constexpr int kVarThreads = 256;
 
 __device__ const SectionTable g_var_section_table{};
 
@@ -62,6 +64,36 @@ __device__ __forceinline__ uint32_t vwindow(const uint32_t* __restrict__ g, uint
     return funnel(vword(g, lim, q + 1), vword(g, lim, q), pos & 31u);
 }
 
+// Words of code staged in LDS per block, and the zero words after them.  A
+// block of P planes takes at most 25 + 17 P bits: the 9-bit header, at most
+// 16 verbatim bits a plane after the first, one ending group bit a plane,
+// and across all planes at most 16 run-starting group bits and 16 run bits
+// (a run passes each coefficient once).  With P <= 32, the start offset
+// (< 32) and the last 32-bit window, every read stays below bit 632: 20
+// words hold any block.
+constexpr uint32_t kVarStage = 20, kVarPad = 3, kVarRow = kVarStage + kVarPad;
+
+// Reading a lane's code straight from global memory: two loads a window.
+struct GlobalBits {
+    const uint32_t* g;
+    uint32_t lim;
+    __device__ __forceinline__ uint32_t window(uint32_t pos) const { return vwindow(g, lim, pos); }
+};
+
+// Reading a lane's block staged in LDS: words 0..kVarStage-1 of its view
+// from word b0 at lw[k * kVarThreads], then kVarPad zero words; positions
+// count from bit 32 * b0.  A window past the staged words reads the zero
+// padding (the word index is clamped to it), so a block that runs past
+// 32 * (kVarStage - 1) bits must be decoded again from global memory.
+struct StagedBits {
+    const uint32_t* lw;
+    __device__ __forceinline__ uint32_t window(uint32_t pos) const
+    {
+        const uint32_t q = __builtin_elementwise_min(pos >> 5, kVarStage + 1u);
+        return funnel(lw[(q + 1) * kVarThreads], lw[q * kVarThreads], pos & 31u);
+    }
+};
+
 // Planes coded for a block with exponent emax (mode 0: fixed precision,
 // param = P; mode 1: fixed accuracy, param = minexp).
 __host__ __device__ __forceinline__ int var_planes(int mode, int param, int emax)
@@ -76,12 +108,12 @@ __host__ __device__ __forceinline__ int var_planes(int mode, int param, int emax
 // is above P reads zero bits: its plane word is zero, and its position and
 // significance count stay put.  With no bit budget, the implied 1 at the end
 // of a run is always coefficient 15's.
-template <int P>
-__device__ __forceinline__ void var_plane(const uint32_t* g, uint32_t lim, const uint32_t* tab, uint32_t lo,
-                                          uint32_t& pos, uint32_t& nsig, uint32_t (&A)[16])
+template <int P, typename Bits>
+__device__ __forceinline__ void var_plane(const Bits& rd, const uint32_t* tab, uint32_t lo, uint32_t& pos,
+                                          uint32_t& nsig, uint32_t (&A)[16])
 {
     const bool live = (uint32_t)P >= lo;
-    const uint32_t w = live ? vwindow(g, lim, pos) : 0u;
+    const uint32_t w = live ? rd.window(pos) : 0u;
     const uint32_t xv = __builtin_amdgcn_ubfe(w, 0u, nsig);
     uint32_t e = tab[(nsig << 9) | __builtin_amdgcn_ubfe(w, nsig, 8u)];
     uint32_t acc = e;
@@ -89,7 +121,7 @@ __device__ __forceinline__ void var_plane(const uint32_t* g, uint32_t lim, const
     nsig += ent_adv(e);
     if (__any(ent_open(e))) {
         do {
-            const uint32_t bits = live ? vwindow(g, lim, at) : 0u;
+            const uint32_t bits = live ? rd.window(at) : 0u;
             uint32_t idx = (nsig << 9) + ent_next(e);
             idx |= bits & 0xFFu;
             e = tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
@@ -107,9 +139,9 @@ __device__ __forceinline__ void var_plane(const uint32_t* g, uint32_t lim, const
         A[P] ^= x;
 }
 
-template <int P>
-__device__ __forceinline__ void var_planes_from(const uint32_t* g, uint32_t lim, const uint32_t* tab, uint32_t lo,
-                                                uint32_t& pos, uint32_t& nsig, uint32_t (&A)[16])
+template <int P, typename Bits>
+__device__ __forceinline__ void var_planes_from(const Bits& rd, const uint32_t* tab, uint32_t lo, uint32_t& pos,
+                                                uint32_t& nsig, uint32_t (&A)[16])
 {
     if constexpr (P >= 0) {
         if (!__any((uint32_t)P >= lo)) { // every lane is done: planes P..0 stay zero
@@ -120,8 +152,8 @@ __device__ __forceinline__ void var_planes_from(const uint32_t* g, uint32_t lim,
             }
             return;
         }
-        var_plane<P>(g, lim, tab, lo, pos, nsig, A);
-        var_planes_from<P - 1>(g, lim, tab, lo, pos, nsig, A);
+        var_plane<P>(rd, tab, lo, pos, nsig, A);
+        var_planes_from<P - 1>(rd, tab, lo, pos, nsig, A);
     }
 }
 
@@ -129,10 +161,11 @@ __device__ __forceinline__ void var_planes_from(const uint32_t* g, uint32_t lim,
 // coefficients (two's complement, local order 4r + c) and emax.  A lane with
 // live == false decodes a zero block and does not move.  Returns whether the
 // block is nonzero.
-__device__ __forceinline__ bool var_block_coeffs(const uint32_t* g, uint32_t lim, const uint32_t* tab, int mode,
-                                                 int param, bool live, uint32_t& pos, int& emax, uint32_t (&cf)[16])
+template <typename Bits>
+__device__ __forceinline__ bool var_block_coeffs(const Bits& rd, const uint32_t* tab, int mode, int param, bool live,
+                                                 uint32_t& pos, int& emax, uint32_t (&cf)[16])
 {
-    const uint32_t h = live ? vwindow(g, lim, pos) : 0u;
+    const uint32_t h = live ? rd.window(pos) : 0u;
     const bool nz = (h & 1u) != 0;
     emax = (int)((h >> 1) & 0xFFu) - 127;
     if (live)
@@ -140,7 +173,7 @@ __device__ __forceinline__ bool var_block_coeffs(const uint32_t* g, uint32_t lim
     const uint32_t lo = nz ? (uint32_t)(32 - var_planes(mode, param, emax)) : 32u;
     uint32_t nsig = 0u;
     uint32_t A[16];
-    var_planes_from<31>(g, lim, tab, lo, pos, nsig, A);
+    var_planes_from<31>(rd, tab, lo, pos, nsig, A);
     transpose_planes(A);
 #pragma unroll
     for (int s = 0; s < 16; ++s)
@@ -159,6 +192,42 @@ __device__ __forceinline__ void lane_view(const uint32_t* code, uint64_t nwords,
     pos = (uint32_t)(start & 31u);
 }
 
+// The next block of a lane's view at bit pos (advanced past it): staged in
+// the lane's LDS row and decoded there.  A block that read past the staged
+// words would be decoded again from global memory; by the bound above that
+// never happens for codes of at most 32 planes, and the check keeps a code
+// that breaks the bound (a corrupt stream) from decoding out of padding.
+__device__ __forceinline__ bool var_next_block(const uint32_t* g, uint32_t lim, uint32_t* row, const uint32_t* tab,
+                                               int mode, int param, bool live, uint32_t& pos, int& emax,
+                                               uint32_t (&cf)[16])
+{
+    const uint32_t b0 = pos >> 5;
+#pragma unroll
+    for (uint32_t k = 0; k < kVarStage; ++k)
+        row[k * kVarThreads] = live ? vword(g, lim, b0 + k) : 0u;
+    uint32_t lpos = pos & 31u;
+    bool nz = var_block_coeffs(StagedBits{row}, tab, mode, param, live, lpos, emax, cf);
+    const bool over = live && lpos >= 32u * (kVarStage - 1u);
+    if (__any(over)) {
+        if (over) {
+            uint32_t p = pos;
+            nz = var_block_coeffs(GlobalBits{g, lim}, tab, mode, param, true, p, emax, cf);
+            lpos = p - 32u * b0;
+        }
+    }
+    pos = 32u * b0 + lpos;
+    return nz;
+}
+
+// Zero the padding words after a lane's staged block (once per kernel: the
+// staging writes words 0..kVarStage-1 only).
+__device__ __forceinline__ void clear_var_pad(uint32_t* row)
+{
+#pragma unroll
+    for (uint32_t k = kVarStage; k < kVarRow; ++k)
+        row[k * kVarThreads] = 0u;
+}
+
 // Whole matrix into row-major FP32: one lane per (block row, group).
 __global__ void __launch_bounds__(kVarThreads) var_decode_kernel(const uint64_t* __restrict__ index,
                                                                  const uint32_t* __restrict__ code, uint64_t nwords,
@@ -167,6 +236,9 @@ __global__ void __launch_bounds__(kVarThreads) var_decode_kernel(const uint64_t*
                                                                  float* __restrict__ out)
 {
     __shared__ uint32_t tab[kSecEntries];
+    __shared__ uint32_t stage[kVarThreads * kVarRow];
+    uint32_t* row = stage + threadIdx.x;
+    clear_var_pad(row);
     load_table(tab);
     const uint64_t lane_id = (uint64_t)blockIdx.x * kVarThreads + threadIdx.x;
     const bool in = lane_id < nlanes;
@@ -179,7 +251,7 @@ __global__ void __launch_bounds__(kVarThreads) var_decode_kernel(const uint64_t*
         const bool live = in && bj < nbc;
         int emax;
         uint32_t iv[16];
-        var_block_coeffs(g, lim, tab, mode, param, live, pos, emax, iv);
+        var_next_block(g, lim, row, tab, mode, param, live, pos, emax, iv);
         inv_xform(iv);
         if (live) {
 #pragma unroll
@@ -232,7 +304,13 @@ __global__ void __launch_bounds__(kVarThreads) var_gemv_kernel(
     uint32_t bi_begin, uint32_t bi_end, uint32_t nslab, uint32_t cols, uint32_t nrows, uint32_t skip, uint32_t lg)
 {
     __shared__ uint32_t tab[kSecEntries];
-    __shared__ double red[kVarThreads * 4]; // per group (<= 512) and row of the block
+    // the lanes' staging rows; after the blocks, the row sums per group
+    // (<= 512) and row of the block
+    __shared__ double stage_d[kVarThreads * kVarRow / 2];
+    static_assert(kVarRow * kVarThreads / 2 >= 4 * kVarThreads, "the row sums fit the staging area");
+    uint32_t* row = reinterpret_cast<uint32_t*>(stage_d) + threadIdx.x;
+    double* red = stage_d;
+    clear_var_pad(row);
     load_table(tab);
     const uint32_t G = 1u << lg, groups = (uint32_t)kVarThreads >> lg;
     const uint32_t grp = threadIdx.x >> lg, gl = threadIdx.x & (G - 1);
@@ -258,7 +336,7 @@ __global__ void __launch_bounds__(kVarThreads) var_gemv_kernel(
         }
         int emax;
         uint32_t iv[16];
-        const bool nz = var_block_coeffs(g, lim, tab, mode, param, live, pos, emax, iv);
+        const bool nz = var_next_block(g, lim, row, tab, mode, param, live, pos, emax, iv);
         if (live && nz) {
             // the exact integer inverse transform (not B (C (B^T u))): a
             // coefficient cut to its top planes can reach -2^31, where the
@@ -275,7 +353,9 @@ __global__ void __launch_bounds__(kVarThreads) var_gemv_kernel(
             }
         }
     }
-    // across the G lanes of the row (within a wave), then one lane per row
+    // across the G lanes of the row (within a wave), then one lane per row;
+    // the row sums reuse the staging area once every lane is done with it
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         for (int mask = (int)G >> 1; mask >= 1; mask >>= 1)
