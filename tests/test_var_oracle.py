@@ -102,3 +102,24 @@ def test_index(shape):
         A = oracle.decode_var(s, idx, rows, cols, mode, param)
         B = oracle.decode_var(s, None, rows, cols, mode, param)
         assert np.array_equal(A.view(np.uint32), B.view(np.uint32))
+
+
+@pytest.mark.parametrize("planes", [1, 8, 17, 25, 32])
+def test_block_bits_bound(planes):
+    """A block coded to P planes takes at most 25 + 17 P bits: the 9-bit
+    header, at most 16 verbatim bits a plane after the first, one ending
+    group bit a plane, and over all planes at most 16 run-starting group bits
+    and 16 run bits (a run passes each coefficient once).  The GPU decoder
+    stages 20 words a block on this bound."""
+    rng = np.random.default_rng(100 + planes)
+    blocks = [rng.standard_normal((4, 4)) * np.exp2(rng.integers(-40, 40)) for _ in range(300)]
+    blocks += [np.full((4, 4), 1.0), np.eye(4) * 3.0 - 1.0, np.indices((4, 4)).sum(0) % 2 - 0.5,
+               np.where(rng.random((4, 4)) < 0.5, -1.0, 1.0) * rng.integers(1, 1 << 20, (4, 4)),
+               rng.standard_normal((4, 4)) * np.exp2(rng.integers(-30, 30, (4, 4)))]
+    worst = 0
+    for b in blocks:
+        _, _, nb = oracle.encode_var(np.asarray(b, np.float32), oracle.VAR_PRECISION, planes)
+        worst = max(worst, nb)
+    assert worst <= 25 + 17 * planes
+    if planes == 32:
+        assert worst > 16 * 31  # white noise reaches the verbatim-dominated regime the bound covers
