@@ -17,9 +17,13 @@
 //               requests of that matrix (FIFO, up to 64 right-hand sides) form
 //               one batch; requests that arrive while it runs form the next
 //   launch      U rows are copied into the slot, the slot's pre-instantiated
-//               hipGraph for the batch's k-bucket (1, 2, 4, 8, 16, 32, 64;
-//               one fused decode+GEMV launch) is replayed on the matrix's own
-//               stream, Y rows are copied back, an event is recorded
+//               hipGraph for the batch's k-bucket (1, 2, 4, 8, 16, 32, 64) is
+//               replayed on the matrix's own stream, Y rows are copied back,
+//               an event is recorded.  A graph is a chain of fused
+//               decode+GEMV launches over consecutive row chunks of at most
+//               ctx->serve_chunk_values values: a long pass over a big matrix
+//               does not hold every compute unit until it ends, and batches
+//               of other matrices start between its chunks
 //   completion  the worker polls the events; a finished batch stamps t_done
 //               on its requests and frees the slot
 //   poll        never blocks: WH_PENDING, or the result once (then retired)
@@ -109,25 +113,39 @@ struct Server {
 
 namespace {
 
-// Device memory of one batch slot: U and Y for kMaxRhs vectors, and the FP64
-// slab partials the k = 1 or multi-RHS plan needs (none when a plan has one
-// slab).  This is what a slot charges against the context's HBM budget.
-size_t slot_partials(const Matrix& m, int num_cus)
+// The row chunks of one served pass: consecutive ranges of whole block rows
+// holding at most `values` matrix values each (at least one block row).
+std::vector<std::pair<uint32_t, uint32_t>> serve_chunks(const Matrix& m, uint64_t values)
 {
-    const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, num_cus);
-    const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, num_cus);
+    const uint64_t per = std::max<uint64_t>(4, values / std::max<uint32_t>(1, m.desc.cols) / 4 * 4);
+    std::vector<std::pair<uint32_t, uint32_t>> out;
+    for (uint64_t r0 = 0; r0 < m.desc.rows; r0 += per)
+        out.emplace_back((uint32_t)r0, (uint32_t)std::min<uint64_t>(r0 + per, m.desc.rows));
+    return out;
+}
+
+// Device memory of one batch slot: U and Y for kMaxRhs vectors, and the FP64
+// slab partials the k = 1 or multi-RHS plans of its chunks need (none when
+// every plan has one slab; the chunks run in stream order and share them).
+// This is what a slot charges against the context's HBM budget.
+size_t slot_partials(const Matrix& m, const wh_ctx* ctx)
+{
     size_t n = 0;
-    if (gp.nslab > 1)
-        n = std::max(n, (size_t)gp.nslab * gp.part_rows());
-    if (mp.nslab > 1)
-        n = std::max(n, (size_t)mp.nslab * kMaxRhs * mp.part_rows());
+    for (const auto& c : serve_chunks(m, ctx->serve_chunk_values)) {
+        const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
+        const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
+        if (gp.nslab > 1)
+            n = std::max(n, (size_t)gp.nslab * gp.part_rows());
+        if (mp.nslab > 1)
+            n = std::max(n, (size_t)mp.nslab * kMaxRhs * mp.part_rows());
+    }
     return n;
 }
 
-size_t slot_bytes(const Matrix& m, int num_cus)
+size_t slot_bytes(const Matrix& m, const wh_ctx* ctx)
 {
     return (size_t)kMaxRhs * ((size_t)m.desc.cols + m.desc.rows) * sizeof(float) +
-           slot_partials(m, num_cus) * sizeof(double);
+           slot_partials(m, ctx) * sizeof(double);
 }
 
 // Capture one graph per k-bucket for a slot: a single fused launch.
@@ -140,9 +158,8 @@ wh_status build_slot(Server* sv, MatServe& ms, Slot& sl)
     // the rows the graphs may read before a batch writes them must be finite
     if (hipMemset(sl.U, 0, (size_t)kMaxRhs * m.desc.cols * sizeof(float)) != hipSuccess)
         return WH_ERR_DEVICE;
-    const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, sv->ctx->num_cus);
-    const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, 0, m.desc.rows, sv->ctx->num_cus);
-    const size_t part_n = slot_partials(m, sv->ctx->num_cus);
+    const size_t part_n = slot_partials(m, sv->ctx);
+    const auto chunks = serve_chunks(m, sv->ctx->serve_chunk_values);
     if (part_n && hipMalloc(&sl.part, part_n * sizeof(double)) != hipSuccess)
         return WH_ERR_NOMEM;
     if (hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess)
@@ -152,9 +169,19 @@ wh_status build_slot(Server* sv, MatServe& ms, Slot& sl)
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(ms.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return WH_ERR_DEVICE;
-        hipError_t e = k == 1 ? whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, sl.U, sl.Y, sl.part, ms.stream)
-                              : whz_mrhs(m.desc.rate, mp, false, m.dptr, sl.U, m.desc.cols, k, sl.Y, m.desc.rows,
-                                         sl.part, ms.stream);
+        hipError_t e = hipSuccess;
+        for (const auto& c : chunks) {
+            if (k == 1) {
+                const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, c.first, c.second, sv->ctx->num_cus);
+                e = whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, sl.U, sl.Y + c.first, sl.part, ms.stream);
+            } else {
+                const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, sv->ctx->num_cus);
+                e = whz_mrhs(m.desc.rate, mp, false, m.dptr, sl.U, m.desc.cols, k, sl.Y + c.first, m.desc.rows,
+                             sl.part, ms.stream);
+            }
+            if (e != hipSuccess)
+                break;
+        }
         hipError_t e2 = hipStreamEndCapture(ms.stream, &g);
         if (e != hipSuccess || e2 != hipSuccess || !g)
             return WH_ERR_DEVICE;
@@ -195,7 +222,7 @@ size_t first_slot_reserve(Server* sv)
         auto it = sv->mats.find(kv.first);
         if (it != sv->mats.end() && !it->second.slots.empty())
             continue;
-        const size_t b = slot_bytes(kv.second, sv->ctx->num_cus);
+        const size_t b = slot_bytes(kv.second, sv->ctx);
         if (b <= sv->ctx->budget)
             r += b;
     }
@@ -208,7 +235,7 @@ size_t first_slot_reserve(Server* sv)
 // none yet, so a matrix whose first request comes late is not starved.
 bool add_slot(Server* sv, MatServe& ms)
 {
-    const size_t per = slot_bytes(ms.m, sv->ctx->num_cus);
+    const size_t per = slot_bytes(ms.m, sv->ctx);
     const size_t reserve = ms.slots.empty() ? 0 : first_slot_reserve(sv);
     if ((int)ms.slots.size() >= kMaxSlotsPerMatrix || sv->arena_used + per + reserve > sv->ctx->budget)
         return false;
@@ -247,7 +274,7 @@ MatServe* serve_matrix(Server* sv, wh_mat mat, wh_status& st)
         st = WH_ERR_FORMAT;
         return nullptr;
     }
-    if (slot_bytes(m, sv->ctx->num_cus) + sv->arena_used > sv->ctx->budget) {
+    if (slot_bytes(m, sv->ctx) + sv->arena_used > sv->ctx->budget) {
         st = WH_ERR_BUDGET; // cannot hold even one batch of this matrix
         return nullptr;
     }
@@ -449,7 +476,7 @@ void serve_forget(wh_ctx* ctx, wh_mat m)
             r.t_done = now_ns();
             r.status = WH_OK;
         }
-        sv->arena_used -= slot_bytes(ms.m, ctx->num_cus);
+        sv->arena_used -= slot_bytes(ms.m, ctx);
         free_slot(sl);
     }
     for (uint64_t tk : ms.pending) // never started

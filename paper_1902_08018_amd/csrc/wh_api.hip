@@ -58,6 +58,18 @@ GemvTuning gemv_tuning_from_env()
     return t;
 }
 
+// WH_SERVE_CHUNK_VALUES: the most matrix values one serving launch covers
+// (a served pass runs as row chunks of about this size); default 2^29.
+uint64_t serve_chunk_from_env()
+{
+    const char* v = std::getenv("WH_SERVE_CHUNK_VALUES");
+    if (!v || !*v)
+        return 1ull << 29;
+    char* end = nullptr;
+    const unsigned long long x = std::strtoull(v, &end, 10);
+    return (*end == 0 && x > 0) ? (uint64_t)x : (1ull << 29);
+}
+
 wh_status storage_bytes(const wh_matrix_desc& d, uint64_t& nbytes)
 {
     if (d.rows == 0 || d.cols == 0)
@@ -169,6 +181,7 @@ wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
         ctx->device = hip_device;
         ctx->num_cus = prop.multiProcessorCount;
         ctx->gemv_tune = gemv_tuning_from_env();
+        ctx->serve_chunk_values = serve_chunk_from_env();
         ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (1ull << 30);
         if (host_pipe_init(ctx) != WH_OK) {
             delete ctx;

@@ -64,6 +64,7 @@ struct wh_ctx {
     int device = 0;
     int num_cus = 256;
     wh::GemvTuning gemv_tune; // launch-shape overrides read at wh_create
+    uint64_t serve_chunk_values = 1ull << 29; // values per serving launch (WH_SERVE_CHUNK_VALUES)
     uint64_t budget = 0;
     std::mutex mu; // guards mats / next_id
     std::unordered_map<wh_mat, wh::Matrix> mats;

@@ -8,6 +8,9 @@
   deadline       a late result is still delivered and flagged missed
   tickets        unknown tickets give WH_ERR_NOT_FOUND; a ticket retires
                  after its result is read
+  row chunks     with WH_SERVE_CHUNK_VALUES small, every pass runs as many
+                 row-chunk launches (the last one ragged): results still
+                 within 1e-6 of the oracle, k = 1 and multi-RHS
 """
 import time
 
@@ -190,5 +193,34 @@ def test_unload_while_served():
         ref = U2.double().cpu().numpy() @ oracle.decode(oracle.encode(M2, 8), SPECS[2].rows, SPECS[2].cols, 8).astype(np.float64).T
         err = np.linalg.norm(Y2.cpu().numpy() - ref) / np.linalg.norm(ref)
         assert err <= 1e-6
+    finally:
+        wh.wh_destroy(ctx)
+
+
+def test_row_chunked_passes(monkeypatch):
+    monkeypatch.setenv("WH_SERVE_CHUNK_VALUES", str(69632))  # 68 rows of 1024 columns, 32 rows of 2048
+    ctx = wh.wh_create(0, 256 << 20)
+    try:
+        mats, refs = [], []
+        keep = []
+        for sp in SPECS:
+            s = oracle.encode(synth.matrix(sp), 8)
+            d = torch.from_numpy(s).cuda()
+            keep.append(d)
+            mats.append(wh.wh_load_compressed(ctx, sp.rows, sp.cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, d))
+            refs.append(oracle.decode(s, sp.rows, sp.cols, 8).astype(np.float64))
+        tickets, checks = [], []
+        for i, k in enumerate([1, 5, 1, 17, 3, 64]):
+            j = i % 3
+            U = torch.from_numpy(synth.uniform(k * SPECS[j].cols, seed=500 + i).reshape(k, -1)).pin_memory()
+            Y = torch.full((k, SPECS[j].rows), -7.0, dtype=torch.float32).pin_memory()
+            tickets.append(wh.wh_submit(ctx, make_request(mats[j], U, Y)))
+            checks.append((j, U, Y))
+        res = wait(ctx, tickets)
+        assert all(r[0] == wh.WH_OK for r in res.values())
+        for j, U, Y in checks:
+            r = U.numpy().astype(np.float64) @ refs[j].T
+            e = np.linalg.norm(Y.numpy() - r, axis=1) / np.linalg.norm(r, axis=1)
+            assert e.max() <= 1e-6, (j, U.shape[0], e.max())
     finally:
         wh.wh_destroy(ctx)
