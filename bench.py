@@ -228,6 +228,7 @@ def bench_host_pipeline(ctx, rate, steps, modes=("chunk_32MiB", "chunk_8MiB", "d
     res = {}
     for name, spec in (("field_2116x256000", synth.MatrixSpec(FIELD_ROWS, FIELD_COLS, 512, 32.0, seed=4)),
                        ("65536x65536", synth.LARGE)):
+        print(f"# host pipeline: {name}", file=sys.stderr, flush=True)
         rows, cols = spec.rows, spec.cols
         st = workload.build_stream(ctx, spec, rate)
         h = torch.empty(st.numel(), dtype=torch.uint8, pin_memory=True)
@@ -291,9 +292,10 @@ def host_pipeline_child(rate, steps):
     import subprocess
     cmd = [sys.executable, os.path.abspath(__file__), "--leg", "host-pipeline", "--rate", str(rate),
            "--steps", str(steps), "--cpu-baseline", "0", "--serving", "0"]
-    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    # the child's progress lines go to this process's stderr as they come
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600)
     if r.returncode != 0:
-        return {"error": f"child exited {r.returncode}: {r.stderr[-400:]}"}
+        return {"error": f"child exited {r.returncode}"}
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
