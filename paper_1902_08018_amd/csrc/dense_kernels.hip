@@ -419,7 +419,7 @@ wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, cons
         nslab = pl.nslab;
         double* part = nullptr;
         if (nslab > 1) {
-            wh_status s2 = ensure_partials(ctx, (size_t)nslab * nrows);
+            wh_status s2 = ensure_partials(ctx, (size_t)nslab * nrows, st);
             if (s2 != WH_OK)
                 return s2;
             part = ctx->part;
@@ -441,7 +441,7 @@ wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, cons
                                nslab, d_y);
             e = hipGetLastError();
         }
-        return device_error(ctx, e);
+        return device_error(ctx, part ? partials_release(ctx, st, e) : e);
     }
     const int elems = fmt == WH_FMT_F32 ? 4 : 8;
     if (cols % elems)
@@ -451,7 +451,7 @@ wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, cons
     nslab = choose_slabs(ntiles, cols / elems, ctx->num_cus, slab_steps);
     double* part = nullptr;
     if (nslab > 1) {
-        wh_status s2 = ensure_partials(ctx, (size_t)nslab * nrows);
+        wh_status s2 = ensure_partials(ctx, (size_t)nslab * nrows, st);
         if (s2 != WH_OK)
             return s2;
         part = ctx->part;
@@ -484,7 +484,7 @@ wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, cons
                            d_y);
         e = hipGetLastError();
     }
-    return device_error(ctx, e);
+    return device_error(ctx, part ? partials_release(ctx, st, e) : e);
 }
 
 } // namespace wh

@@ -167,11 +167,12 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
             }
             const GemvPlan pl = whz_gemv_plan(rows, cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
             if (pl.nslab > 1) {
-                const wh_status s = ensure_partials(ctx, (size_t)pl.nslab * pl.part_rows());
+                const wh_status s = ensure_partials(ctx, (size_t)pl.nslab * pl.part_rows(), st);
                 if (s != WH_OK)
                     return s;
             }
-            return device_error(ctx, whz_gemv(rate, pl, mode, dev, d_u, d_y, pl.nslab > 1 ? ctx->part : nullptr, st));
+            const hipError_t e = whz_gemv(rate, pl, mode, dev, d_u, d_y, pl.nslab > 1 ? ctx->part : nullptr, st);
+            return device_error(ctx, pl.nslab > 1 ? partials_release(ctx, st, e) : e);
         }
         const uint32_t bb = row_begin / 4, be = (row_end + 3) / 4;
         uint64_t cb = chunk_rows ? chunk_rows / 4 : kPipeChunkBytes / brow_bytes;
@@ -195,7 +196,7 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
                 part_need = std::max(part_need, (size_t)pl.nslab * pl.part_rows());
         }
         if (part_need) {
-            s = ensure_partials(ctx, part_need);
+            s = ensure_partials(ctx, part_need, st);
             if (s != WH_OK)
                 return s;
         }
@@ -230,7 +231,7 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
             if (e == hipSuccess)
                 e = hipEventRecord(p->consumed[k], st);
         }
-        return device_error(ctx, e);
+        return device_error(ctx, part_need ? partials_release(ctx, st, e) : e);
     } catch (const std::bad_alloc&) {
         return WH_ERR_NOMEM;
     } catch (...) {

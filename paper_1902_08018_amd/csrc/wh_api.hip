@@ -100,10 +100,35 @@ wh_status storage_bytes(const wh_matrix_desc& d, uint64_t& nbytes)
     }
 }
 
-wh_status ensure_partials(wh_ctx* ctx, size_t count)
+wh_status grow_partials(wh_ctx* ctx, size_t count);
+
+bool capturing(hipStream_t st)
 {
-    if (count <= ctx->part_cap)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+wh_status ensure_partials(wh_ctx* ctx, size_t count, hipStream_t st)
+{
+    if (count > ctx->part_cap) {
+        const wh_status s = grow_partials(ctx, count);
+        if (s != WH_OK)
+            return s;
+    }
+    if (capturing(st))
         return WH_OK;
+    return device_error(ctx, hipStreamWaitEvent(st, ctx->part_ev, 0));
+}
+
+hipError_t partials_release(wh_ctx* ctx, hipStream_t st, hipError_t e)
+{
+    if (e != hipSuccess || capturing(st))
+        return e;
+    return hipEventRecord(ctx->part_ev, st);
+}
+
+wh_status grow_partials(wh_ctx* ctx, size_t count)
+{
     if (ctx->part) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess)
@@ -183,7 +208,12 @@ wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
         ctx->gemv_tune = gemv_tuning_from_env();
         ctx->serve_chunk_values = serve_chunk_from_env();
         ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (1ull << 30);
+        if (hipEventCreateWithFlags(&ctx->part_ev, hipEventDisableTiming) != hipSuccess) {
+            delete ctx;
+            return WH_ERR_DEVICE;
+        }
         if (host_pipe_init(ctx) != WH_OK) {
+            (void)hipEventDestroy(ctx->part_ev);
             delete ctx;
             return WH_ERR_DEVICE;
         }
@@ -210,6 +240,8 @@ wh_status wh_destroy(wh_ctx* ctx)
                 (void)hipFree(kv.second.dptr);
         if (ctx->part)
             (void)hipFree(ctx->part);
+        if (ctx->part_ev)
+            (void)hipEventDestroy(ctx->part_ev);
         delete ctx;
         return WH_OK;
     } catch (...) {
@@ -361,23 +393,25 @@ wh_status wh_gemv(wh_ctx* ctx, wh_mat m, const float* d_u, float* d_y, uint32_t 
                 return WH_ERR_FORMAT;
             const size_t pn = var_partials(mat, row_begin, row_end);
             if (pn) {
-                wh_status s2 = ensure_partials(ctx, pn);
+                wh_status s2 = ensure_partials(ctx, pn, st);
                 if (s2 != WH_OK)
                     return s2;
             }
-            return device_error(ctx, var_gemv(mat, mode, d_u, d_y, row_begin, row_end, pn ? ctx->part : nullptr, st));
+            hipError_t e = var_gemv(mat, mode, d_u, d_y, row_begin, row_end, pn ? ctx->part : nullptr, st);
+            return device_error(ctx, pn ? partials_release(ctx, st, e) : e);
         }
         if (mat.desc.fmt == WH_FMT_ZFP_FIXED_RATE) {
             const GemvPlan pl =
                 whz_gemv_plan(mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
             double* part = nullptr;
             if (pl.nslab > 1) {
-                wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * pl.part_rows());
+                wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * pl.part_rows(), st);
                 if (s2 != WH_OK)
                     return s2;
                 part = ctx->part;
             }
-            return device_error(ctx, whz_gemv(mat.desc.rate, pl, mode, mat.dptr, d_u, d_y, part, st));
+            hipError_t e = whz_gemv(mat.desc.rate, pl, mode, mat.dptr, d_u, d_y, part, st);
+            return device_error(ctx, part ? partials_release(ctx, st, e) : e);
         }
         return dense_gemv_dispatch(ctx, mat, mode, d_u, d_y, row_begin, row_end, st);
     } catch (...) {
@@ -414,13 +448,13 @@ wh_status wh_gemv_batched(wh_ctx* ctx, wh_mat m, const void* d_U, int u_dtype, u
         const MrhsPlan pl = whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus);
         double* part = nullptr;
         if (pl.nslab > 1) {
-            wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * k * pl.part_rows());
+            wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * k * pl.part_rows(), st);
             if (s2 != WH_OK)
                 return s2;
             part = ctx->part;
         }
-        return device_error(ctx, whz_mrhs(mat.desc.rate, pl, u_dtype == WH_U_BF16, mat.dptr, d_U, ldu, k, d_Y, ldy,
-                                          part, st));
+        hipError_t e = whz_mrhs(mat.desc.rate, pl, u_dtype == WH_U_BF16, mat.dptr, d_U, ldu, k, d_Y, ldy, part, st);
+        return device_error(ctx, part ? partials_release(ctx, st, e) : e);
     } catch (...) {
         return WH_ERR_INVALID;
     }

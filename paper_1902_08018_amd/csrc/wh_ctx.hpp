@@ -45,7 +45,13 @@ hipError_t var_gemv(const Matrix& m, AccMode acc, const float* u, float* y, uint
                     double* part, hipStream_t st);
 
 wh_status device_error(wh_ctx* ctx, hipError_t e);
-wh_status ensure_partials(wh_ctx* ctx, size_t count);
+// The context's FP64 slab-partials workspace, shared by every call that
+// splits columns: grow it to `count` doubles, and make `st` wait until the
+// previous user's work on the device is done (on whatever stream it ran).
+// The user then calls partials_release after its launches.  Neither waits
+// nor records while `st` is being captured into a graph.
+wh_status ensure_partials(wh_ctx* ctx, size_t count, hipStream_t st);
+hipError_t partials_release(wh_ctx* ctx, hipStream_t st, hipError_t e);
 Matrix* find_matrix(wh_ctx* ctx, wh_mat m);
 bool aligned(const void* p, uintptr_t a);
 
@@ -71,6 +77,7 @@ struct wh_ctx {
     wh_mat next_id = 1;
     double* part = nullptr; // FP64 slab partials
     size_t part_cap = 0;
+    hipEvent_t part_ev = nullptr; // recorded after each user of `part`
     std::atomic<bool> failed{false};
     wh::Server* server = nullptr; // owned; freed by serve_shutdown
     wh::HostPipe* pipe = nullptr;  // owned; freed by host_pipe_free
