@@ -611,6 +611,9 @@ def main():
         "compressed_gbs": round(stream_bytes / (kern_ms * 1e-3) / 1e9, 2),
         "kernel_ms": round(kern_ms, 4),
         "kernel_ms_p10_p50_p90": [round(float(x), 4) for x in __import__("numpy").percentile(ev_ms, [10, 50, 90])],
+        "paper_context": {"p100_zfp_decoder_wc_gbs": 33.2, "p100_mixed_precision_gemv_gflops": 198.3,
+                          "note": "the paper's own P100 figures (separate zfp decoder, fixed accuracy; uncompressed "
+                                  "378 x 256000 GEMV): context, not this metric's baseline"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "copy_ceiling_gbs": round(copy_gbs, 1)},
