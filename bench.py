@@ -474,6 +474,7 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
     slot = [0] * nm
     outstanding = {}
     lat, miss, bsz, rejected = [], 0, [], 0
+    per = [{"lat": [], "miss": 0} for _ in range(nm)]
     t0 = time.monotonic_ns() + 50_000_000
     i = 0
     done_count = 0
@@ -500,6 +501,9 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
                     lat.append((r.t_done_ns - r.t_arrive_ns) * 1e-6)
                     miss += r.missed
                     bsz.append(r.batch_size)
+                    pj = per[int(target[idx])]
+                    pj["lat"].append(lat[-1])
+                    pj["miss"] += r.missed
         if i < n:
             nxt = t0 + int(arrive[i] * 1e9) - time.monotonic_ns()
             if nxt > 200_000:
@@ -512,7 +516,12 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
             "p999_ms": round(float(np.percentile(lat, 99.9)), 3), "max_ms": round(float(lat.max()), 3),
             "miss_rate": round(miss / max(1, len(lat)), 4), "throughput_rps": round(done_count / t_total, 1),
             "mean_batch_requests": round(float(np.mean(bsz)), 2), "rejected": rejected,
-            "hbm_budget_mb": budget_mb, "matrices": [f"{sp.rows}x{sp.cols} rate 8" for sp in specs]}
+            "hbm_budget_mb": budget_mb, "matrices": [f"{sp.rows}x{sp.cols} rate 8" for sp in specs],
+            "per_matrix": {f"{sp.rows}x{sp.cols}": {"requests": len(pj["lat"]),
+                                                   "p50_ms": round(float(np.percentile(pj["lat"], 50)), 3),
+                                                   "p99_ms": round(float(np.percentile(pj["lat"], 99)), 3),
+                                                   "miss_rate": round(pj["miss"] / max(1, len(pj["lat"])), 4)}
+                           for sp, pj in zip(specs, per) if pj["lat"]}}
 
 
 def main():
@@ -697,8 +706,10 @@ def main():
         print("# host-resident matrices streamed over the link (child process)", file=sys.stderr, flush=True)
         hp = host_pipeline_child(rate, max(5, args.steps // 2))
         print("# the same pipeline in this process, after the other legs", file=sys.stderr, flush=True)
-        hp["in_process_after_other_legs"] = bench_host_pipeline(ctx, rate, max(5, args.steps // 2),
+        hctx = wh.wh_create(0, 0)  # its copy stream (a hardware queue) goes with it
+        hp["in_process_after_other_legs"] = bench_host_pipeline(hctx, rate, max(5, args.steps // 2),
                                                                 modes=("chunk_32MiB",), parts=False)
+        wh.wh_destroy(hctx)
         extra[f"host_pipeline_rate{rate}"] = hp
         print("# thermal step", file=sys.stderr, flush=True)
         extra["thermal_step_608x608"] = bench_thermal(ctx, args.steps)

@@ -103,7 +103,6 @@ wh_status ensure_pipe(wh_ctx* ctx, size_t bytes)
 
 } // namespace
 
-wh_status host_pipe_init(wh_ctx* ctx) { return ensure_pipe(ctx, 0); }
 
 namespace {
 

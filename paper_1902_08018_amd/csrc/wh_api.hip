@@ -212,11 +212,9 @@ wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
             delete ctx;
             return WH_ERR_DEVICE;
         }
-        if (host_pipe_init(ctx) != WH_OK) {
-            (void)hipEventDestroy(ctx->part_ev);
-            delete ctx;
-            return WH_ERR_DEVICE;
-        }
+        // the host pipeline's copy stream is created on its first use: a
+        // stream holds a hardware queue (HIP maps streams onto a few queues
+        // round-robin), and most contexts never stream from the host
         *out = ctx;
         return WH_OK;
     } catch (const std::bad_alloc&) {

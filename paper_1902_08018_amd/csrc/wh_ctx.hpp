@@ -27,10 +27,6 @@ struct HostPipe; // copy stream and staging of wh_gemv_host (host_stream.hip)
 // compressed bytes per copy.
 constexpr int kPipeBuffers = 2;
 constexpr uint64_t kPipeChunkBytes = 32ull << 20;
-// Creates the pipe's copy stream and events, no buffers (wh_create: the
-// stream is made before the process's other work; copies on a stream made
-// late in a busy process were measured at half speed).
-wh_status host_pipe_init(wh_ctx* ctx);
 // Waits for the pipe's copies and frees it (wh_destroy).
 void host_pipe_free(wh_ctx* ctx);
 
