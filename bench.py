@@ -527,7 +527,7 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+        print(f"bench.py: runs on one GPU only (--gpus {args.gpus} requested); "
               "the row split across GPUs is not built", file=sys.stderr)
         sys.exit(2)
     import torch
