@@ -444,7 +444,7 @@ SERVING_SPECS = {
 
 
 def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measured=20000, warmup_s=1.0,
-                  rate_hz=2000.0, deadline_ms=5.0, budget_mb=160, seed=0):
+                  rate_hz=2000.0, deadline_ms=5.0, budget_mb=160, seed=0, shed=0):
     """Open-loop Poisson load against resident rate-8 matrices (target
     uniform over `names`); k ~ U{1..8} dose vectors in pinned host memory;
     latency measured from the scheduled arrival time."""
@@ -453,7 +453,15 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
     from paper_1902_08018_amd import synth, wh, workload
     specs = [synth.MatrixSpec(*SERVING_SPECS[n]) for n in names]
     nm = len(specs)
-    ctx = wh.wh_create(0, budget_mb << 20)
+    old = os.environ.pop("WH_SERVE_SHED", None)
+    if shed:
+        os.environ["WH_SERVE_SHED"] = str(shed)  # read by wh_create
+    try:
+        ctx = wh.wh_create(0, budget_mb << 20)
+    finally:
+        os.environ.pop("WH_SERVE_SHED", None)
+        if old is not None:
+            os.environ["WH_SERVE_SHED"] = old
     streams, mats = [], []
     for sp in specs:
         st = workload.build_stream(ctx, sp, 8)
@@ -474,7 +482,7 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
     slot = [0] * nm
     outstanding = {}
     lat, miss, bsz, rejected = [], 0, [], 0
-    per = [{"lat": [], "miss": 0} for _ in range(nm)]
+    per = [{"lat": [], "miss": 0, "rejected": 0} for _ in range(nm)]
     t0 = time.monotonic_ns() + 50_000_000
     i = 0
     done_count = 0
@@ -491,6 +499,8 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
                 outstanding[wh.wh_submit(ctx, req)] = i
             except wh.WhError:
                 rejected += 1
+                if i >= n_warm:
+                    per[j]["rejected"] += 1
             i += 1
         for tk in list(outstanding):
             st, r = wh.wh_poll(ctx, tk)
@@ -516,11 +526,13 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
             "p999_ms": round(float(np.percentile(lat, 99.9)), 3), "max_ms": round(float(lat.max()), 3),
             "miss_rate": round(miss / max(1, len(lat)), 4), "throughput_rps": round(done_count / t_total, 1),
             "mean_batch_requests": round(float(np.mean(bsz)), 2), "rejected": rejected,
-            "hbm_budget_mb": budget_mb, "matrices": [f"{sp.rows}x{sp.cols} rate 8" for sp in specs],
+            "hbm_budget_mb": budget_mb, "shed_after_deadlines": shed,
+            "matrices": [f"{sp.rows}x{sp.cols} rate 8" for sp in specs],
             "per_matrix": {f"{sp.rows}x{sp.cols}": {"requests": len(pj["lat"]),
                                                    "p50_ms": round(float(np.percentile(pj["lat"], 50)), 3),
                                                    "p99_ms": round(float(np.percentile(pj["lat"], 99)), 3),
-                                                   "miss_rate": round(pj["miss"] / max(1, len(pj["lat"])), 4)}
+                                                   "miss_rate": round(pj["miss"] / max(1, len(pj["lat"])), 4),
+                                                   "rejected": pj["rejected"]}
                            for sp, pj in zip(specs, per) if pj["lat"]}}
 
 
@@ -726,6 +738,11 @@ def main():
         torch.cuda.empty_cache()
         out["extra"]["serving_two_smaller"] = bench_serving(("16384x16384", "32768x16384"),
                                                             n_measured=args.serving_requests)
+        # the three matrices again, shedding requests for a matrix whose queue
+        # head has waited more than four deadlines
+        print("# serving loop, load shedding", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["extra"]["serving_shed_4"] = bench_serving(n_measured=args.serving_requests, shed=4)
 
     if args.cpu_baseline:
         print("# cpu baseline (oracle), and the oracle's check of the timed launch's first rows",

@@ -124,7 +124,10 @@ const char *wh_status_str(wh_status st);
  * WH_SERVE_CHUNK_VALUES (a positive integer, default 2^29) bounds the matrix
  * values one serving launch covers: the serving loop runs each pass over a
  * larger matrix as launches over consecutive row chunks, so that batches of
- * other matrices get the device between chunks. */
+ * other matrices get the device between chunks.  WH_SERVE_SHED=F (an integer
+ * 1..1000; unset or 0 = off) turns on load shedding: wh_submit rejects a
+ * request with WH_ERR_BUDGET while its matrix's oldest queued request has
+ * waited more than F of its own deadlines. */
 wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx **out);
 
 /* Destroy a context: waits for its work, frees what it owns. */
@@ -299,8 +302,9 @@ typedef struct {
  * context's HBM budget) with one captured hipGraph per k-bucket; a second
  * slot is added later if a batch has to wait and the budget has room.  Rejected at
  * once with WH_ERR_BUDGET if not even one slot of that matrix fits the
- * budget, or if k > 64.  U and Y must stay valid until wh_poll reports the
- * request done.  zfp matrices only. */
+ * budget, if k > 64, or (load shedding, see wh_create) while the matrix's
+ * queue is too far behind.  U and Y must stay valid until wh_poll reports
+ * the request done.  zfp matrices only. */
 wh_status wh_submit(wh_ctx *ctx, const wh_request *req, uint64_t *ticket);
 
 /* Non-blocking: WH_PENDING until the request's result is in Y, then WH_OK

@@ -511,6 +511,16 @@ extern "C" wh_status wh_submit(wh_ctx* ctx, const wh_request* req, uint64_t* tic
         MatServe* ms = serve_matrix(sv, req->mat, st);
         if (!ms)
             return st;
+        // load shedding (off unless WH_SERVE_SHED is set): the matrix's oldest
+        // queued request has already waited longer than `serve_shed` of its
+        // deadlines, so a new one would wait longer still
+        if (ctx->serve_shed && !ms->pending.empty()) {
+            const Req& head = sv->reqs[ms->pending.front()];
+            const uint64_t now = now_ns();
+            if (head.r.deadline_ns && now > head.t_arrive &&
+                now - head.t_arrive > (uint64_t)ctx->serve_shed * head.r.deadline_ns)
+                return WH_ERR_BUDGET;
+        }
         const uint64_t tk = sv->next_ticket++;
         Req& r = sv->reqs[tk];
         r.r = *req;

@@ -207,6 +207,11 @@ wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
         ctx->num_cus = prop.multiProcessorCount;
         ctx->gemv_tune = gemv_tuning_from_env();
         ctx->serve_chunk_values = serve_chunk_from_env();
+        if (const char* v = std::getenv("WH_SERVE_SHED")) {
+            char* end = nullptr;
+            const unsigned long f = std::strtoul(v, &end, 10);
+            ctx->serve_shed = (*v && *end == 0 && f <= 1000) ? (uint32_t)f : 0u;
+        }
         ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (1ull << 30);
         if (hipEventCreateWithFlags(&ctx->part_ev, hipEventDisableTiming) != hipSuccess) {
             delete ctx;

@@ -224,3 +224,45 @@ def test_row_chunked_passes(monkeypatch):
             assert e.max() <= 1e-6, (j, U.shape[0], e.max())
     finally:
         wh.wh_destroy(ctx)
+
+
+def test_load_shedding(monkeypatch):
+    """WH_SERVE_SHED=1: while a matrix's oldest queued request has waited
+    longer than its deadline, new requests for it are rejected at submit
+    with WH_ERR_BUDGET; once the queue drains they are admitted again, and
+    every admitted request completes with a correct result.  Deadlines of 1
+    ns make any queued request overdue at once."""
+    monkeypatch.setenv("WH_SERVE_SHED", "1")
+    ctx = wh.wh_create(0, 256 << 20)
+    try:
+        sp = SPECS[1]
+        s = oracle.encode(synth.matrix(sp), 8)
+        d = torch.from_numpy(s).cuda()
+        mat = wh.wh_load_compressed(ctx, sp.rows, sp.cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, d)
+        ref_M = oracle.decode(s, sp.rows, sp.cols, 8).astype(np.float64)
+        bufs = [(torch.from_numpy(synth.uniform(8 * sp.cols, seed=700 + i).reshape(8, -1)).cuda(),
+                 torch.full((8, sp.rows), -7.0, device="cuda")) for i in range(200)]
+        reqs = [make_request(mat, U, Y, deadline_ns=1) for U, Y in bufs]
+        torch.cuda.synchronize()
+        tickets, rejected = [], 0
+        for req, (U, Y) in zip(reqs, bufs):  # a tight loop: the queue backs up
+            try:
+                tickets.append((wh.wh_submit(ctx, req), U, Y))
+            except wh.WhError as e:
+                assert e.status == wh.WH_ERR_BUDGET
+                rejected += 1
+        assert rejected > 0 and tickets, (rejected, len(tickets))
+        res = wait(ctx, [t for t, _, _ in tickets])
+        assert all(r[0] == wh.WH_OK for r in res.values())
+        torch.cuda.synchronize()
+        for _, U, Y in tickets:
+            r = U.cpu().numpy().astype(np.float64) @ ref_M.T
+            e = np.linalg.norm(Y.cpu().numpy() - r, axis=1) / np.linalg.norm(r, axis=1)
+            assert e.max() <= 1e-6
+        # drained: admitted again
+        U = torch.from_numpy(synth.uniform(sp.cols, seed=999).reshape(1, -1)).cuda()
+        Y = torch.empty((1, sp.rows), device="cuda")
+        t = wh.wh_submit(ctx, make_request(mat, U, Y, deadline_ns=1))
+        wait(ctx, [t])
+    finally:
+        wh.wh_destroy(ctx)
