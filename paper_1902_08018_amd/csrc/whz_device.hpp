@@ -165,8 +165,12 @@ __device__ __forceinline__ void transpose_planes(uint32_t (&A)[16])
 // the scan reaches coefficient 15 inside a run its 1 is implied.
 //
 // Table entry for (nsig, state, 8 bits), state 0 = at a group bit, 1 =
-// inside a run; index (nsig << 9) | (state << 8) | bits.  The fields sit
-// where the decoder can take them without masking:
+// inside a run; index nsig * kSecRow + (state << 8) + bits.  The row stride
+// kSecRow = 513 is odd on purpose: the decoder carries ns = nsig * kSecRow
+// instead of nsig, and since 513 = 16 * 32 + 1, ns's low byte (and its low
+// five bits, all that v_bfe reads of an offset or a width) is nsig itself.
+// The first lookup's address is then one add of ns and the 8 bits.  The
+// fields sit where the decoder can take them without masking:
 //   bits  0..15  coefficients that became significant, at their absolute
 //                positions (the table is indexed by nsig), including
 //                coefficient 15's implied 1; they OR straight into the plane
@@ -182,10 +186,44 @@ __device__ __forceinline__ void transpose_planes(uint32_t (&A)[16])
 // runs unpredicated.
 constexpr int kSecBits = 8;
 constexpr int kSecN = 17; // nsig 0..16
-constexpr int kSecDone = kSecN * 2 * (1 << kSecBits);
+constexpr int kSecRow = 2 * (1 << kSecBits) + 1;
+constexpr int kSecDone = kSecN * kSecRow;
 constexpr int kSecEntries = kSecDone + 1;
 constexpr uint32_t kEntState = 1u << 24, kEntDone = 1u << 31;
 static_assert(kSecDone <= (int)(kEntDone >> 16), "the done flag must lift an index past the table");
+static_assert((kSecRow & 0x1FF) == 1 && (kSecN - 1) * kSecRow + 2 * (1 << kSecBits) <= kSecDone,
+              "ns = nsig * kSecRow keeps nsig in its low byte, and rows do not overlap");
+// nsig from ns = nsig * kSecRow (nsig <= 16)
+__host__ __device__ __forceinline__ constexpr uint32_t ns_nsig(uint32_t ns) { return ns & 0xFFu; }
+
+// a + nsig for ns = nsig * kSecRow.  On the GPU one SDWA add reads ns's low
+// byte; written plainly the compiler masks first and adds in a second
+// instruction.
+__device__ __forceinline__ uint32_t add_nsig(uint32_t a, uint32_t ns)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t r;
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:DWORD"
+        : "=v"(r)
+        : "v"(ns), "v"(a));
+    return r;
+#else
+    return a + ns_nsig(ns);
+#endif
+}
+
+// tab[ns + bits] (tab in LDS).  On the GPU the byte address is one
+// v_add_lshl; written plainly the compiler scales both terms apart.
+__device__ __forceinline__ uint32_t sec_lookup(const uint32_t* tab, uint32_t ns, uint32_t bits)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t off;
+    asm("v_add_lshl_u32 %0, %1, %2, 2" : "=v"(off) : "v"(ns), "v"(bits));
+    return *(const uint32_t*)((const char*)tab + off);
+#else
+    return tab[ns + bits];
+#endif
+}
 
 __host__ __device__ __forceinline__ constexpr uint32_t ent_used(uint32_t e) { return (e >> 16) & 0xFFu; }
 __host__ __device__ __forceinline__ constexpr uint32_t ent_adv(uint32_t e) { return (e >> 25) & 15u; }
@@ -241,7 +279,7 @@ struct SectionTable {
         for (int n = 0; n < kSecN; ++n)
             for (int st = 0; st < 2; ++st)
                 for (int b = 0; b < (1 << kSecBits); ++b)
-                    e[(n << 9) | (st << 8) | b] = section_entry(st, n, b);
+                    e[n * kSecRow + (st << 8) + b] = section_entry(st, n, b);
         e[kSecDone] = kEntDone;
     }
 };
@@ -268,7 +306,7 @@ __host__ __device__ constexpr uint32_t kOddPlanes(int q) { return (q & 1) ? 0xFF
 // Returns the wave's mask of lanes past their budget.
 template <int NW, int STRIDE, int P>
 __device__ __forceinline__ uint64_t decode_plane(const uint32_t* lw, const uint32_t* tab, uint32_t& pos,
-                                                 uint32_t& nsig, uint32_t (&A)[16])
+                                                 uint32_t& ns, uint32_t (&A)[16])
 {
     constexpr uint32_t kMaxBits = 32u * NW;
     // word of pos (positions stay below 1024: kMaxBits + 32 + one plane)
@@ -276,23 +314,23 @@ __device__ __forceinline__ uint64_t decode_plane(const uint32_t* lw, const uint3
     // 32 bits from pos: the verbatim bits (nsig <= 16) and the first 8
     // section bits always fit
     const uint32_t lo = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], pos & 31u);
-    // (i) verbatim bits of the significant coefficients
-    const uint32_t xv = __builtin_amdgcn_ubfe(lo, 0u, nsig);
+    // (i) verbatim bits of the significant coefficients (v_bfe takes the
+    // width mod 32: nsig)
+    const uint32_t xv = __builtin_amdgcn_ubfe(lo, 0u, ns);
     // (ii) group tests, 8 bits per table lookup.  acc's low half collects
     // the plane's new ones; its high half is the latest entry's fields, so
     // the loop carries no separate copy of the entry
-    uint32_t acc = tab[(nsig << 9) | __builtin_amdgcn_ubfe(lo, nsig, 8u)];
-    uint32_t at = pos + nsig + ent_used(acc); // next unread bit
-    nsig += ent_adv(acc);
+    uint32_t acc = sec_lookup(tab, ns, __builtin_amdgcn_ubfe(lo, ns, 8u));
+    uint32_t at = add_nsig(pos, ns) + ent_used(acc); // next unread bit
+    ns += ent_adv(acc) * (uint32_t)kSecRow;
     if (__any(ent_open(acc))) {
         do {
             q = word_of(at);
             const uint32_t bits = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], at & 31u);
-            uint32_t idx = (nsig << 9) + ent_next(acc); // ended: >= kSecDone
-            idx |= bits & 0xFFu;
+            const uint32_t idx = ns + ent_next(acc) + (bits & 0xFFu); // ended: >= kSecDone
             acc = (acc & 0xFFFFu) | tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
             at += ent_used(acc);
-            nsig += ent_adv(acc);
+            ns += ent_adv(acc) * (uint32_t)kSecRow;
         } while (__any(ent_open(acc)));
     }
     const uint64_t past = __ballot(at >= kMaxBits);
@@ -328,7 +366,7 @@ constexpr int kSafeCutPlane = 26;
 // lanes already past their budget.
 template <int NW, int STRIDE, int P>
 __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uint32_t* tab, uint32_t& pos,
-                                                   uint32_t& nsig, uint32_t (&A)[16], bool& cut, uint64_t past)
+                                                   uint32_t& ns, uint32_t (&A)[16], bool& cut, uint64_t past)
 {
     if constexpr (P >= 0) {
         if (past == __builtin_amdgcn_read_exec()) {
@@ -340,10 +378,10 @@ __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uin
             }
             return;
         }
-        past = decode_plane<NW, STRIDE, P>(lw, tab, pos, nsig, A);
+        past = decode_plane<NW, STRIDE, P>(lw, tab, pos, ns, A);
         if constexpr (P == kSafeCutPlane)
             cut = pos > 32u * NW;
-        decode_planes_from<NW, STRIDE, P - 1>(lw, tab, pos, nsig, A, cut, past);
+        decode_planes_from<NW, STRIDE, P - 1>(lw, tab, pos, ns, A, cut, past);
     }
 }
 
@@ -371,10 +409,10 @@ __device__ __forceinline__ bool decode_block_coeffs(const uint32_t* lw, const ui
     const bool nz = (w0 & 1u) != 0;
     emax = (int)((w0 >> 1) & 0xFFu) - 127;
     uint32_t pos = nz ? 9u : 32u * NW; // next bit to read; decoding stops at 32*NW
-    uint32_t nsig = 0u;                 // coefficients 0..nsig-1 significant
+    uint32_t ns = 0u;                   // nsig * kSecRow: coefficients 0..nsig-1 significant
     uint32_t A[16]; // every word is written by a plane or by the early exit
     cut = nz;       // a zero block is exact; others until plane kSafeCutPlane is read
-    decode_planes_from<NW, STRIDE, 31>(lw, tab, pos, nsig, A, cut, __ballot(!nz));
+    decode_planes_from<NW, STRIDE, 31>(lw, tab, pos, ns, A, cut, __ballot(!nz));
     transpose_planes(A);
     // negabinary -> two's complement (the XOR came with the planes), undo
     // the sequency order

@@ -110,24 +110,23 @@ __host__ __device__ __forceinline__ int var_planes(int mode, int param, int emax
 // of a run is always coefficient 15's.
 template <int P, typename Bits>
 __device__ __forceinline__ void var_plane(const Bits& rd, const uint32_t* tab, uint32_t lo, uint32_t& pos,
-                                          uint32_t& nsig, uint32_t (&A)[16])
+                                          uint32_t& ns, uint32_t (&A)[16])
 {
     const bool live = (uint32_t)P >= lo;
     const uint32_t w = live ? rd.window(pos) : 0u;
-    const uint32_t xv = __builtin_amdgcn_ubfe(w, 0u, nsig);
-    uint32_t e = tab[(nsig << 9) | __builtin_amdgcn_ubfe(w, nsig, 8u)];
+    const uint32_t xv = __builtin_amdgcn_ubfe(w, 0u, ns); // ns = nsig * kSecRow; v_bfe reads nsig
+    uint32_t e = sec_lookup(tab, ns, __builtin_amdgcn_ubfe(w, ns, 8u));
     uint32_t acc = e;
-    uint32_t at = pos + nsig + ent_used(e);
-    nsig += ent_adv(e);
+    uint32_t at = add_nsig(pos, ns) + ent_used(e);
+    ns += ent_adv(e) * (uint32_t)kSecRow;
     if (__any(ent_open(e))) {
         do {
             const uint32_t bits = live ? rd.window(at) : 0u;
-            uint32_t idx = (nsig << 9) + ent_next(e);
-            idx |= bits & 0xFFu;
+            const uint32_t idx = ns + ent_next(e) + (bits & 0xFFu);
             e = tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
             acc |= e;
             at += ent_used(e);
-            nsig += ent_adv(e);
+            ns += ent_adv(e) * (uint32_t)kSecRow;
         } while (__any(ent_open(e)));
     }
     const uint32_t x = (acc & 0xFFFFu) | xv; // coefficient 15's implied 1 is in the table's ones
@@ -141,7 +140,7 @@ __device__ __forceinline__ void var_plane(const Bits& rd, const uint32_t* tab, u
 
 template <int P, typename Bits>
 __device__ __forceinline__ void var_planes_from(const Bits& rd, const uint32_t* tab, uint32_t lo, uint32_t& pos,
-                                                uint32_t& nsig, uint32_t (&A)[16])
+                                                uint32_t& ns, uint32_t (&A)[16])
 {
     if constexpr (P >= 0) {
         if (!__any((uint32_t)P >= lo)) { // every lane is done: planes P..0 stay zero
@@ -152,8 +151,8 @@ __device__ __forceinline__ void var_planes_from(const Bits& rd, const uint32_t* 
             }
             return;
         }
-        var_plane<P>(rd, tab, lo, pos, nsig, A);
-        var_planes_from<P - 1>(rd, tab, lo, pos, nsig, A);
+        var_plane<P>(rd, tab, lo, pos, ns, A);
+        var_planes_from<P - 1>(rd, tab, lo, pos, ns, A);
     }
 }
 
@@ -171,9 +170,9 @@ __device__ __forceinline__ bool var_block_coeffs(const Bits& rd, const uint32_t*
     if (live)
         pos += nz ? 9u : 1u;
     const uint32_t lo = nz ? (uint32_t)(32 - var_planes(mode, param, emax)) : 32u;
-    uint32_t nsig = 0u;
+    uint32_t ns = 0u; // nsig * kSecRow
     uint32_t A[16];
-    var_planes_from<31>(rd, tab, lo, pos, nsig, A);
+    var_planes_from<31>(rd, tab, lo, pos, ns, A);
     transpose_planes(A);
 #pragma unroll
     for (int s = 0; s < 16; ++s)
