@@ -101,25 +101,39 @@ __global__ void __launch_bounds__(kThreads) decode_blocks_kernel(const uint32_t*
     }
 }
 
-// Whole matrix into row-major FP32 (rows x cols).
+// Whole matrix into row-major FP32 (rows x cols).  A wave decodes an 8 x 8
+// patch of blocks (lane l: block row 8i + l / 8, block column 8j + l % 8):
+// the lanes run the bit planes in lockstep, and neighbouring blocks need more
+// alike numbers of planes and lookups than 64 blocks along one row.  Wide
+// workgroups share one copy of the section table among more waves.
 template <int NW>
-__global__ void __launch_bounds__(kThreads) decode_matrix_kernel(const uint32_t* __restrict__ stream, uint32_t nbc,
-                                                                 uint64_t nblocks, uint32_t rows, uint32_t cols,
-                                                                 float* __restrict__ out)
+constexpr int kDecThreads = NW <= 8 ? 1024 : 512;
+
+template <int NW>
+__global__ void __launch_bounds__(kDecThreads<NW>) decode_matrix_kernel(const uint32_t* __restrict__ stream,
+                                                                        uint32_t nbr, uint32_t nbc, uint32_t npc,
+                                                                        uint64_t npatch, uint32_t rows, uint32_t cols,
+                                                                        float* __restrict__ out)
 {
-    __shared__ uint32_t lds[kThreads * kStagedWords<NW>];
+    constexpr int T = kDecThreads<NW>;
+    constexpr uint32_t kWaves = T / 64;
+    __shared__ uint32_t lds[T * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
     uint32_t* row = lds + threadIdx.x;
-    clear_pad<NW, kThreads>(row);
-    load_section_table<kThreads>(tab);
-    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
-    for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < nblocks; b += stride) {
+    clear_pad<NW, T>(row);
+    load_section_table<T>(tab);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
+    const uint32_t lane = threadIdx.x % 64u;
+    const uint64_t stride = (uint64_t)gridDim.x * kWaves;
+    for (uint64_t p = (uint64_t)blockIdx.x * kWaves + wave; p < npatch; p += stride) {
+        const uint64_t bi = (p / npc) * 8u + lane / 8u, bj = (p % npc) * 8u + lane % 8u;
+        if (bi >= nbr || bj >= nbc)
+            continue;
         uint32_t w[NW];
-        stage_block<NW, kThreads>(row, stream + b * NW, w);
+        stage_block<NW, T>(row, stream + (bi * nbc + bj) * NW, w);
         int emax;
         uint32_t iv[16];
-        decode_block_ints<NW, kThreads>(row, tab, w[0], emax, iv);
-        const uint64_t bi = b / nbc, bj = b % nbc;
+        decode_block_ints<NW, T>(row, tab, w[0], emax, iv);
         if ((cols & 3u) == 0 && 4 * bi + 3 < rows) { // a whole block on 16-byte aligned rows
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -719,10 +733,13 @@ hipError_t launch_decode_blocks(const uint32_t* s, uint64_t b0, uint64_t n, floa
 template <int NW>
 hipError_t launch_decode_matrix(const uint32_t* s, uint32_t rows, uint32_t cols, float* out, hipStream_t st)
 {
-    const uint32_t nbc = (cols + 3) / 4;
-    const uint64_t nb = (uint64_t)((rows + 3) / 4) * nbc;
-    hipLaunchKernelGGL(decode_matrix_kernel<NW>, dim3(grid_for(nb, 65536)), dim3(kThreads), 0, st, s, nbc, nb, rows,
-                       cols, out);
+    const uint32_t nbr = (uint32_t)(((uint64_t)rows + 3) / 4), nbc = (uint32_t)(((uint64_t)cols + 3) / 4);
+    const uint32_t npc = (nbc + 7) / 8;
+    const uint64_t npatch = (uint64_t)((nbr + 7) / 8) * npc;
+    constexpr uint64_t waves = kDecThreads<NW> / 64;
+    const uint64_t g = (npatch + waves - 1) / waves;
+    hipLaunchKernelGGL(decode_matrix_kernel<NW>, dim3((unsigned)(g == 0 ? 1 : (g < 65536 ? g : 65536))),
+                       dim3(kDecThreads<NW>), 0, st, s, nbr, nbc, npc, npatch, rows, cols, out);
     return hipGetLastError();
 }
 

@@ -5,7 +5,10 @@ The oracle cannot decode 2^28 blocks in seconds, so it checks sampled
 block-rows: it generates those rows of M on the host, encodes them itself,
 and (1) the GPU-built stream must hold exactly the oracle's bytes there,
 (2) the GPU y on those rows must be within relative L2 1e-6 of the oracle's
-FP64 product.
+FP64 product, (3) the whole-matrix decode into row-major FP32 (the
+separate path's first step, whose launch walks its 8 x 8 block patches in
+a grid-stride loop at this size) must hold exactly the oracle's decoded
+values on those rows.
 """
 import numpy as np
 import pytest
@@ -34,10 +37,11 @@ def test_large_config_sampled_rows(gpu_ctx, rate):
     table = synth.kernel_table(spec)
     per_brow = oracle.stream_nbytes(4, spec.cols, rate)
     errs = []
-    got_all, ref_all = [], []
+    got_all, ref_all, s_refs = [], [], []
     for r0 in SAMPLE_ROWS:
         M = synth.matrix_rows(spec, r0, r0 + 4, table)
         s_ref = oracle.encode(M, rate)
+        s_refs.append(s_ref)
         bi = r0 // 4
         s_gpu = stream[bi * per_brow:(bi + 1) * per_brow].cpu().numpy()
         assert np.array_equal(s_gpu, s_ref), f"stream bytes differ at block-row {bi}"
@@ -51,6 +55,13 @@ def test_large_config_sampled_rows(gpu_ctx, rate):
     assert err <= 1e-6
     # every row of y is finite and positive (M > 0 almost everywhere, u >= 0)
     assert np.all(np.isfinite(y_host))
+    dense = torch.empty((spec.rows, spec.cols), dtype=torch.float32, device="cuda")
+    wh.wh_decode(gpu_ctx, mat, dense)
+    torch.cuda.synchronize()
+    for r0, s_ref in zip(SAMPLE_ROWS, s_refs):
+        got = dense[r0:r0 + 4].cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), oracle.decode(s_ref, 4, spec.cols, rate).view(np.uint32)), r0
+    del dense
     wh.wh_unload(gpu_ctx, mat)
     del stream
     torch.cuda.empty_cache()
