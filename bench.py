@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--probe", type=int, default=0,
                     help="counter-pass mode, prints no JSON: 1 = 3 launches of the timed configuration, then 3 "
                          "plain 4 GiB device copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE); "
-                         "2 = 3 multi-RHS launches (k = 16, FP32 U) on the same matrix")
+                         "2 = 3 multi-RHS launches (k = 16, FP32 U) on the same matrix; 3 = 3 whole-matrix "
+                         "decodes into row-major FP32 (the separate path's first step)")
     ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                                            "traffic.json"))
     return ap.parse_args()
@@ -565,6 +566,14 @@ def main():
             wh.wh_gemv_batched(ctx, mat, U, Y)
         torch.cuda.synchronize()
         print(f"# probe done: 3 x wh_gemv_batched k=16 rate {rate} {rows}x{cols}", file=sys.stderr, flush=True)
+        wh.wh_destroy(ctx)
+        return
+    if args.probe == 3:
+        dense = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            wh.wh_decode(ctx, mat, dense)
+        torch.cuda.synchronize()
+        print(f"# probe done: 3 x wh_decode rate {rate} {rows}x{cols}", file=sys.stderr, flush=True)
         wh.wh_destroy(ctx)
         return
     if args.probe:
