@@ -154,7 +154,7 @@ def bench_multi_rhs(ctx, mat, spec, rate, stream_bytes, steps):
 
 
 # The paper's GEMV shapes (Sec. 5, Fig. 10): the slit matrix, its transpose
-# and a square one; and a field matrix (about 2067 MB of FP32, Sec. 3) whose
+# and a square one; and a field matrix (about 2067 MB of FP32, Sec. 2.1) whose
 # 378-row slit windows are multiplied one after another as the slit moves.
 SLIT_SHAPES = (("wide_378x256000", 378, 256000), ("tall_256000x378", 256000, 378),
                ("square_10000x10000", 10000, 10000))
@@ -219,7 +219,7 @@ def bench_slit_field(ctx, rate, steps):
 def bench_host_pipeline(ctx, rate, steps, modes=("chunk_32MiB", "chunk_8MiB", "direct"), parts=True):
     """Table 1 measured: a compressed matrix kept in page-locked host memory
     and streamed over the link by wh_gemv_host, chunks of block rows copied
-    while the fused kernel works on the chunk before (Sec. 3.1-3.2).  Beside
+    while the fused kernel works on the chunk before (Sec. 4.2-4.3).  Beside
     it, the parts of Table 1's formulas measured on their own: the plain
     host-to-device copy of the same compressed bytes (T_transfer / R) and the
     fused kernel on the resident matrix (T_compute + T_decode).  The pipeline
@@ -274,7 +274,7 @@ def bench_host_pipeline(ctx, rate, steps, modes=("chunk_32MiB", "chunk_8MiB", "d
         link_gbs = h.numel() / (t_copy * 1e-3) / 1e9
         entry.update({"link_h2d_gbs": round(link_gbs, 1), "t_copy_compressed_ms": round(t_copy, 3),
                       "t_fused_resident_ms": round(t_fused, 3)})
-        # Table 1 with the measured parts (T_compute << T_transfer for a GEMV, Sec. 3.2)
+        # Table 1 with the measured parts (T_compute << T_transfer for a GEMV, Sec. 4.3)
         t_transfer = 4.0 * rows * cols / (link_gbs * 1e9) * 1e3
         entry["table1_ms"] = {"period_without_compression": round(t_transfer, 3),
                               "period_with": round(max(t_transfer / entry["R"], t_fused), 3),

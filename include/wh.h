@@ -13,7 +13,8 @@
  *     exactly BPV bits per value) and encoded offline.
  *   - Sec. 4.4, Eq. 5, Fig. 7: mixed-precision GEMV -- FP32 inputs and
  *     outputs, FP32 multiplies, a wide (FP64) reduction.
- *   - Sec. 1 / Sec. 4.2: a firm real-time loop with a per-step deadline.
+ *   - Sec. 1: a firm real-time loop; Sec. 2.1, Fig. 2: one product per
+ *     light-stage millisecond, so every step has a deadline.
  *
  * Conventions (every entry point):
  *   - Returns a wh_status; no C++ exception crosses the ABI.  Out-params are
@@ -163,7 +164,12 @@ wh_status wh_unload(wh_ctx *ctx, wh_mat m);
  * linear part), in FP32; B is applied to each row group's sums.  This equals
  * the product with the decoded matrix up to the transform's floor halvings
  * (a few units of each block's last bit: ~1e-8 relative) for streams an
- * encoder produced.  Row sums are FP64 (default) or compensated FP32 across
+ * encoder produced.  Precondition: a compressed matrix's stream is encoder
+ * output (wh_encode, wh_encode_var, or any encoder of the same format).  On
+ * other bytes the call still runs and stays in bounds, but y is then only
+ * some function of the bytes, not the product with what wh_decode returns
+ * for them; wh_decode is defined on every byte string.  Row sums are FP64
+ * (default) or compensated FP32 across
  * blocks; y is rounded once to FP32 (Fig. 7).  WH_PAPER_MP instead
  * multiplies every bit-exact decoded value by u in FP32 and adds each
  * product to an FP64 sum.  Dense formats multiply the stored values. */
@@ -179,7 +185,9 @@ wh_status wh_gemv(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t 
 wh_status wh_gemv_plan_info(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
                             uint32_t *out8);
 
-/* Y = M U for k right-hand sides (Sec. 4.4, batched).  d_U: k vectors of
+/* Y = M U for k right-hand sides.  The paper's GEMV takes one vector
+ * (Sec. 4.4); several at once is this library's addition, for the serving
+ * loop's batches.  d_U: k vectors of
  * cols values, vector r at d_U + r*ldu (ldu >= cols), dtype 0 = FP32,
  * 1 = BF16.  d_Y: k vectors of rows FP32 at d_Y + r*ldy (ldy >= rows).
  * 1 <= k <= 64.  zfp format only; WH_PAPER_MP only with k = 1.  The matrix
@@ -191,9 +199,9 @@ wh_status wh_gemv_batched(wh_ctx *ctx, wh_mat m, const void *d_U, int u_dtype, u
                           float *d_Y, uint32_t ldy, uint32_t flags, void *stream);
 
 /* y[i - row_begin] = sum_j M[i, j] u[j] for rows [row_begin, row_end) of a
- * WHZ1 matrix that stays in HOST memory (Sec. 3.1-3.2, Table 1: the model
- * matrix lives in host DDR and crosses PCIe compressed, pipelined with the
- * work on the GPU).  h_code: the matrix's whole rate-`rate` stream (rows x
+ * WHZ1 matrix that stays in HOST memory (Sec. 4.2: the model matrix lives
+ * in host DDR and crosses PCIe compressed; Sec. 4.3, Table 1: the
+ * transfers are pipelined with the work on the GPU).  h_code: the matrix's whole rate-`rate` stream (rows x
  * cols, layout as WH_FMT_ZFP_FIXED_RATE), host memory; only the block rows
  * of the range are read.  The block rows cross the link in chunks of
  * chunk_rows rows (a multiple of 4; 0 = about 32 MiB of code per chunk) on
@@ -218,7 +226,7 @@ wh_status wh_gemv_host(wh_ctx *ctx, const void *h_code, uint32_t rows, uint32_t 
 wh_status wh_host_alloc(uint64_t bytes, void **h_ptr);
 wh_status wh_host_free(void *h_ptr);
 
-/* Variable-rate encoder (host; the paper encodes offline, Sec. 3.2): h_M
+/* Variable-rate encoder (host; the paper encodes offline, Sec. 4.3): h_M
  * rows x cols FP32 row-major in host memory -> h_out (cap bytes of host
  * memory), the storage of format fmt (WH_FMT_ZFP_FIXED_PRECISION or
  * _ACCURACY) with parameter `rate` as in wh_matrix_desc; *out_bytes = the

@@ -3,7 +3,7 @@
 //
 // The paper keeps the whole model matrix in host DDR and moves it to the GPU
 // over PCIe compressed, with the transfers pipelined against the work on the
-// GPU (Sec. 3.1 and 3.2, Table 1: with compression the period is
+// GPU (Sec. 4.2 and 4.3, Table 1: with compression the period is
 // max(T_transfer / R, T_compute + T_decode)).  Here the block rows of the
 // requested range cross the link in chunks on a copy stream of the library's,
 // into two device staging buffers used in turn; the fused decode + GEMV of a

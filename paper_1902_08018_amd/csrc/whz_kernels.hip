@@ -443,7 +443,8 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
 }
 
 // ---------------------------------------------------- multi-RHS (MFMA path)
-// Y = M U^T for k right-hand sides (Sec. 4.4 batched).  One workgroup = 8
+// Y = M U^T for k right-hand sides (the paper's GEMV, Sec. 4.4, takes one
+// vector; several at once is this library's addition).  One workgroup = 8
 // waves = 32 block-rows (128 rows).  A block's rows against U are
 // B (C (B^T U)) (C its coefficients, B the inverse transform's linear part;
 // see lin_inv_lift), so the matrix cores contract coefficients, not decoded

@@ -20,7 +20,7 @@
 // staging), so the decoder's window reads are LDS reads, not chains of
 // dependent global loads.  The fused GEMV gives 1 to 8 lanes (groups) to a block row
 // and multiplies each block's exactly decoded values by u.  The encoder runs
-// on the host (the paper encodes offline, Sec. 3.2).
+// on the host (the paper encodes offline, Sec. 4.3).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>

@@ -1,6 +1,6 @@
 """GPU parity of wh_gemv_host: a WHZ1 matrix that stays in host memory,
 its block rows streamed over the link in chunks while the fused kernel works
-on the chunk before (Sec. 3.1-3.2, Table 1).
+on the chunk before (Sec. 4.2-4.3, Table 1).
 
   y against the FP64 oracle within 1e-6 relative L2 (Fig. 7 mode: within 1
   FP32 ulp), for chunk sizes from one block row up, row ranges that start

@@ -195,7 +195,7 @@ def test_slit_shapes(gpu_ctx, rows, cols):
 
 def test_field_slit_windows(gpu_ctx):
     """A field matrix (2116 x 256000, about the paper's 2067 MB of FP32,
-    Sec. 3) resident at rate 8, and 378-row slit windows at offsets that
+    Sec. 2.1) resident at rate 8, and 378-row slit windows at offsets that
     start inside block rows (Fig. 2, Eq. 2 over the slit rows)."""
     rows, cols = 2116, 256000
     spec = synth.MatrixSpec(rows, cols, 512, 32.0, seed=4)
