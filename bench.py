@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--leg", default="", help="internal: 'host-pipeline' runs only that leg and prints its JSON")
     ap.add_argument("--probe", type=int, default=0,
                     help="counter-pass mode, prints no JSON: 1 = 3 launches of the timed configuration, then 3 "
-                         "plain 4 GiB device copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE); "
+                         "plain 4 GiB device copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE) and 3 "
+                         "read-only streams of the same 4 GiB; "
                          "2 = 3 multi-RHS launches (k = 16, FP32 U) on the same matrix; 3 = 3 whole-matrix "
                          "decodes into row-major FP32 (the separate path's first step)")
     ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -104,13 +105,88 @@ def time_call(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def bench_precision(ctx, spec, us, y, steps):
+class SampledRows:
+    """Oracle references for sampled block rows of a synthetic matrix, so that
+    every timed result carries its error: the host generator makes those rows
+    of the FP32 source, the oracle encodes them itself at the rate asked for
+    and decodes them, and the references are FP64 products (numpy) of the
+    source or of the oracle-decoded rows.  `brows` are block-row indices; a
+    partial last block row is taken whole (its real rows only)."""
+
+    def __init__(self, spec, nsample=16, brows=None):
+        import numpy as np
+        from paper_1902_08018_amd import synth
+        self.spec = spec
+        nbr = (spec.rows + 3) // 4
+        if brows is None:
+            brows = sorted(set([0, nbr - 1] + [int(x) for x in np.linspace(0, nbr - 1, nsample)]))
+        self.brows = [b for b in brows if 0 <= b < nbr]
+        table = synth.kernel_table(spec)
+        self.src = [synth.matrix_rows(spec, 4 * b, min(4 * b + 4, spec.rows), table) for b in self.brows]
+        self.idx = np.concatenate([np.arange(4 * b, 4 * b + m.shape[0]) for b, m in zip(self.brows, self.src)])
+        self._dec = {}
+
+    def source(self):
+        import numpy as np
+        return np.concatenate(self.src).astype(np.float64)
+
+    def decoded(self, rate):
+        """FP64 rows of the oracle's own fixed-rate encode + decode."""
+        import numpy as np
+        import oracle
+        if rate not in self._dec:
+            self._dec[rate] = np.concatenate([oracle.decode(oracle.encode(m, rate), m.shape[0], m.shape[1], rate)
+                                              for m in self.src]).astype(np.float64)
+        return self._dec[rate]
+
+    def decoded_var(self, mode, param):
+        import numpy as np
+        import oracle
+        key = ("var", mode, param)
+        if key not in self._dec:
+            out = []
+            for m in self.src:
+                code, index, _ = oracle.encode_var(m, mode, param)
+                out.append(oracle.decode_var(code, index, m.shape[0], m.shape[1], mode, param))
+            self._dec[key] = np.concatenate(out).astype(np.float64)
+        return self._dec[key]
+
+    def take(self, y, row0=0):
+        """y's values at the sampled rows (y holds rows row0, row0 + 1, ...;
+        a torch tensor (k, n) or (n,), or numpy)."""
+        import numpy as np
+        import torch
+        sel = self.idx - row0
+        if isinstance(y, torch.Tensor):
+            t = torch.from_numpy(sel).to(y.device)
+            return (y.index_select(y.dim() - 1, t)).cpu().numpy().astype(np.float64)
+        return np.asarray(y, np.float64)[..., sel]
+
+
+def err_entry(got, ref, tol):
+    """Relative L2 (worst over right-hand sides for 2-D results) of the
+    sampled rows against the oracle, with the bound it must meet."""
+    import numpy as np
+    got = np.atleast_2d(np.asarray(got, np.float64))
+    ref = np.atleast_2d(np.asarray(ref, np.float64))
+    e = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    return {"rel_l2": float(f"{float(e.max()):.4g}"), "tolerance": tol, "ok": bool(e.max() <= tol)}
+
+
+PRECISION_TOL = {"f32": 1e-6, "f16": 2e-3, "bf16": 2e-3, "fp8e4m3_bs4": 2e-2}
+
+
+def bench_precision(ctx, spec, us, y, steps, sample):
     """Dense storage formats of the same FP32 matrix (no compression): FP32,
-    FP16, BF16 and FP8 e4m3 with one FP32 scale per 4x4 block."""
+    FP16, BF16 and FP8 e4m3 with one FP32 scale per 4x4 block.  Each result's
+    error: sampled rows of y for us[0] against the FP64 product of the FP32
+    source rows."""
+    import numpy as np
     import torch
-    from paper_1902_08018_amd import wh, workload
+    from paper_1902_08018_amd import synth, wh, workload
     rows, cols = spec.rows, spec.cols
     dense = workload.build_dense(spec)
+    ref = sample.source() @ synth.u_vector(spec).astype(np.float64)
     res = {}
     for name, fmt in (("f32", wh.WH_FMT_F32), ("f16", wh.WH_FMT_F16), ("bf16", wh.WH_FMT_BF16),
                       ("fp8e4m3_bs4", wh.WH_FMT_FP8E4M3_BS4)):
@@ -122,11 +198,13 @@ def bench_precision(ctx, spec, us, y, steps):
             wh.wh_quantize(ctx, dense, fmt, store)
         m = wh.wh_load_compressed(ctx, rows, cols, fmt, 0, store)
         ms = time_call(lambda i: wh.wh_gemv(ctx, m, us[i % len(us)], y, 0, rows), steps, 2)
+        wh.wh_gemv(ctx, m, us[0], y, 0, rows)
         alg = nbytes + 4 * cols + 4 * rows
         res[name] = {"ms": round(ms, 4), "storage_gb": round(nbytes / 1e9, 3),
                      "hbm_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
                      "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "effective_gbs": round(4.0 * rows * cols / (ms * 1e-3) / 1e9, 1)}
+                     "effective_gbs": round(4.0 * rows * cols / (ms * 1e-3) / 1e9, 1),
+                     "error_vs_fp32_source": err_entry(sample.take(y), ref, PRECISION_TOL[name])}
         wh.wh_unload(ctx, m)
         if fmt != wh.WH_FMT_F32:
             del store
@@ -134,12 +212,16 @@ def bench_precision(ctx, spec, us, y, steps):
     return res
 
 
-def bench_multi_rhs(ctx, mat, spec, rate, stream_bytes, steps):
+def bench_multi_rhs(ctx, mat, spec, rate, stream_bytes, steps, sample):
     """k right-hand sides against the resident rate-`rate` stream (decode ->
-    LDS -> matrix cores), FP32 and BF16 vectors."""
+    LDS -> matrix cores), FP32 and BF16 vectors.  Each result's error: sampled
+    rows of Y against the FP64 product of the oracle-decoded rows with U (U
+    rounded to BF16 for the BF16 leg), worst right-hand side."""
+    import numpy as np
     import torch
     from paper_1902_08018_amd import synth, wh
     rows, cols = spec.rows, spec.cols
+    Mhat = sample.decoded(rate)
     res = {}
     for k in (4, 16, 64):
         U32 = torch.from_numpy(synth.u_batch(spec, k)).cuda()
@@ -147,9 +229,11 @@ def bench_multi_rhs(ctx, mat, spec, rate, stream_bytes, steps):
         for name, U in (("f32", U32), ("bf16", U32.to(torch.bfloat16))):
             ms = time_call(lambda i: wh.wh_gemv_batched(ctx, mat, U, Y), steps, 2)
             alg = stream_bytes + U.numel() * U.element_size() + Y.numel() * 4
+            ref = U.float().cpu().numpy().astype(np.float64) @ Mhat.T
             res[f"k{k}_{name}"] = {"ms": round(ms, 4), "gflops": round(k * rows * (2 * cols - 1) / (ms * 1e-3) / 1e9, 1),
                                    "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                   "ms_per_rhs": round(ms / k, 4)}
+                                   "ms_per_rhs": round(ms / k, 4),
+                                   "error_vs_oracle": err_entry(sample.take(Y), ref, 1e-6 if name == "f32" else 2e-3)}
     return res
 
 
@@ -167,6 +251,7 @@ def bench_slit_field(ctx, rate, steps):
     of 4, which dense storage needs); and slit windows of a field matrix."""
     import torch
     from paper_1902_08018_amd import synth, wh, workload
+    import numpy as np
     res = {}
     for name, rows, cols in SLIT_SHAPES:
         spec = synth.MatrixSpec(rows, cols, 512, 32.0, seed=3)
@@ -175,11 +260,15 @@ def bench_slit_field(ctx, rate, steps):
         us = [workload.u_device(spec, offset=i * cols) for i in range(4)]
         y = torch.empty(rows, dtype=torch.float32, device="cuda")
         ms = time_call(lambda i: wh.wh_gemv(ctx, m, us[i % 4], y, 0, rows), steps, 3)
+        wh.wh_gemv(ctx, m, us[0], y, 0, rows)
+        sample = SampledRows(spec, nsample=8)
+        u64 = synth.u_vector(spec).astype(np.float64)
         wh.wh_unload(ctx, m)
         del st
         flop = rows * (2 * cols - 1)  # Eq. 3's GEMV count
         entry = {"ms": round(ms, 4), "gflops": round(flop / (ms * 1e-3) / 1e9, 1),
-                 "effective_gbs": round(4.0 * rows * cols / (ms * 1e-3) / 1e9, 1)}
+                 "effective_gbs": round(4.0 * rows * cols / (ms * 1e-3) / 1e9, 1),
+                 "error_vs_oracle": err_entry(sample.take(y), sample.decoded(rate) @ u64, 1e-6)}
         prow, pcol = (rows + 3) // 4 * 4, (cols + 3) // 4 * 4
         if pcol == cols:
             pspec = synth.MatrixSpec(prow, cols, 512, 32.0, seed=3)
@@ -187,10 +276,13 @@ def bench_slit_field(ctx, rate, steps):
             md = wh.wh_load_compressed(ctx, prow, cols, wh.WH_FMT_F32, 0, dense)
             yd = torch.empty(prow, dtype=torch.float32, device="cuda")
             msd = time_call(lambda i: wh.wh_gemv(ctx, md, us[i % 4], yd, 0, prow), steps, 3)
+            wh.wh_gemv(ctx, md, us[0], yd, 0, prow)
+            psample = SampledRows(pspec, nsample=8)
             wh.wh_unload(ctx, md)
             del dense
             entry["dense_f32"] = {"ms": round(msd, 4), "gflops": round(flop / (msd * 1e-3) / 1e9, 1),
-                                  "hbm_frac": round(4.0 * prow * cols / (msd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                                  "hbm_frac": round(4.0 * prow * cols / (msd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "error_vs_fp32_source": err_entry(psample.take(yd), psample.source() @ u64, 1e-6)}
         res[name] = entry
     spec = synth.MatrixSpec(FIELD_ROWS, FIELD_COLS, 512, 32.0, seed=4)
     st = workload.build_stream(ctx, spec, rate)
@@ -204,11 +296,18 @@ def bench_slit_field(ctx, rate, steps):
         r0 = starts[i % len(starts)]
         wh.wh_gemv(ctx, m, u, y, r0, r0 + SLIT_ROWS)
     ms = time_call(slit, len(starts), 3)
+    # the last window's y against the oracle, on the block rows inside it
+    r0 = starts[(len(starts) - 1) % len(starts)]
+    torch.cuda.synchronize()
+    fsample = SampledRows(spec, brows=list(range((r0 + 3) // 4, (r0 + SLIT_ROWS) // 4, 8)))
     flop = SLIT_ROWS * (2 * FIELD_COLS - 1)
     res[f"field_{FIELD_ROWS}x{FIELD_COLS}_slit_{SLIT_ROWS}_rows"] = {
         "ms": round(ms, 4), "gflops": round(flop / (ms * 1e-3) / 1e9, 1),
         "effective_gbs": round(4.0 * SLIT_ROWS * FIELD_COLS / (ms * 1e-3) / 1e9, 1),
-        "field_stream_gb": round(st.numel() / 1e9, 3), "window_starts": "0, 7, 14, ... (mod 1739)"}
+        "field_stream_gb": round(st.numel() / 1e9, 3), "window_starts": "0, 7, 14, ... (mod 1739)",
+        "error_vs_oracle": dict(err_entry(fsample.take(y, row0=r0),
+                                          fsample.decoded(rate) @ synth.u_vector(spec).astype(np.float64), 1e-6),
+                                window=f"rows {r0}..{r0 + SLIT_ROWS}")}
     wh.wh_unload(ctx, m)
     del st
     res["rate"] = rate
@@ -224,6 +323,7 @@ def bench_host_pipeline(ctx, rate, steps, modes=("chunk_32MiB", "chunk_8MiB", "d
     host-to-device copy of the same compressed bytes (T_transfer / R) and the
     fused kernel on the resident matrix (T_compute + T_decode).  The pipeline
     is timed first, before the device allocations of the parts."""
+    import numpy as np
     import torch
     from paper_1902_08018_amd import synth, wh, workload
     res = {}
@@ -238,6 +338,8 @@ def bench_host_pipeline(ctx, rate, steps, modes=("chunk_32MiB", "chunk_8MiB", "d
         y = torch.empty(rows, dtype=torch.float32, device="cuda")
         entry = {"compressed_gb": round(h.numel() / 1e9, 3), "uncompressed_gb": round(4.0 * rows * cols / 1e9, 3),
                  "R": 32 / rate}
+        sample = SampledRows(spec, nsample=8)
+        ref = sample.decoded(rate) @ synth.u_vector(spec).astype(np.float64)
         chunk8 = 4 * max(1, (8 << 20) // wh.stream_bytes(4, cols, rate))
         # settle: half a second of calls before timing
         t_end = time.perf_counter() + 0.5
@@ -260,7 +362,8 @@ def bench_host_pipeline(ctx, rate, steps, modes=("chunk_32MiB", "chunk_8MiB", "d
                 torch.cuda.synchronize()
                 lat.append(e0.elapsed_time(e1))
             entry[label] = {"period_ms": round(period, 3), "latency_ms": round(min(lat), 3),
-                            "effective_gbs": round(4.0 * rows * cols / (period * 1e-3) / 1e9, 1)}
+                            "effective_gbs": round(4.0 * rows * cols / (period * 1e-3) / 1e9, 1),
+                            "error_vs_oracle": err_entry(sample.take(y), ref, 1e-6)}
         if not parts:
             res[name] = entry
             del h, st
@@ -316,10 +419,17 @@ def bench_thermal(ctx, steps):
     K = 100
     U = torch.from_numpy(np.stack([synth.thermal_source(spec, k) for k in range(K)])).cuda()
     one = time_call(lambda i: wh.wh_thermal_step(ctx, dev, T[i % 2], U[i % K], T[(i + 1) % 2]), max(steps, 50), 5)
+    # one step from a known state against the oracle's FP64 step
+    import oracle.thermal
+    T0 = synth.thermal_initial(spec)
+    T[0].copy_(torch.from_numpy(T0))
+    wh.wh_thermal_step(ctx, dev, T[0], U[0], T[1])
+    t1 = T[1].cpu().numpy()
+    ref1 = oracle.thermal.thermal_step(row_ptr, col, val, b, T0, U[0].cpu().numpy())
     run = time_call(lambda i: wh.wh_thermal_run(ctx, dev, T[0], U, T[1]), 3, 1) / K
     alg = 4 * (n + 1) + 8 * nnz + 16 * n
     flop = 2 * nnz + n  # Eq. 3's thermal term: 2 nnz(A) + 2 nnz(B) - 1 per row
-    res = {"n": n, "nnz": nnz, "bytes_per_step": alg}
+    res = {"n": n, "nnz": nnz, "bytes_per_step": alg, "error_vs_oracle": err_entry(t1, ref1, 1e-6)}
     for name, ms in (("single_step", one), ("run_100_steps_per_step", run)):
         res[name] = {"us": round(ms * 1e3, 2), "hbm_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
                      "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -345,7 +455,10 @@ def bench_var(ctx, steps):
     M = synth.matrix(spec)
     Md = torch.from_numpy(M).cuda()
     rng = float(M.max() - M.min())
+    import oracle
     u = torch.from_numpy(synth.u_vector(spec)).cuda()
+    u64 = synth.u_vector(spec).astype(np.float64)
+    sample = SampledRows(spec, nsample=8)
     y = torch.empty(rows, device="cuda")
     out = torch.empty((rows, cols), device="cuda")
     res = {"matrix": f"{rows}x{cols}, 128-wide lattices, ell 16"}
@@ -368,6 +481,13 @@ def bench_var(ctx, steps):
         rmse = float(torch.sqrt((err * err).mean()))
         nrmse = rmse / rng
         t_gemv = time_call(lambda i: wh.wh_gemv(ctx, m, u, y, 0, rows), max(5, steps // 2), 2)
+        if fmt == wh.WH_FMT_ZFP_FIXED_RATE:
+            mhat = sample.decoded(rate)
+        elif fmt == wh.WH_FMT_ZFP_FIXED_PRECISION:
+            mhat = sample.decoded_var(oracle.VAR_PRECISION, rate)
+        else:
+            mhat = sample.decoded_var(oracle.VAR_ACCURACY, rate - 1024)
+        gerr = err_entry(sample.take(y), mhat @ u64, 1e-6)
         bpv = 8.0 * buf.numel() / (rows * cols)
         res[name] = {"bits_per_value": round(bpv, 3), "ratio": round(32.0 / bpv, 2),
                      "rmse": float(f"{rmse:.4g}"), "nrmse": float(f"{nrmse:.4g}"),
@@ -375,7 +495,7 @@ def bench_var(ctx, steps):
                      "psnr": round(-20.0 * math.log10(2.0 * nrmse), 2) if nrmse > 0 else None,
                      "encode_s": round(t_enc, 3), "encoder": "GPU" if fmt == wh.WH_FMT_ZFP_FIXED_RATE else "host",
                      "decode_ms": round(t_dec, 3), "decode_wc_gbs": round(4.0 * rows * cols / (t_dec * 1e-3) / 1e9, 1),
-                     "gemv_ms": round(t_gemv, 3),
+                     "gemv_ms": round(t_gemv, 3), "gemv_error_vs_oracle": gerr,
                      "gemv_effective_gbs": round(4.0 * rows * cols / (t_gemv * 1e-3) / 1e9, 1)}
         wh.wh_unload(ctx, m)
         del buf
@@ -383,57 +503,116 @@ def bench_var(ctx, steps):
     return res
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(size, rate, y_gpu=None):
-    """The CPU oracle (decode + FP64 GEMV, threads over block-rows) on a
-    bounded sample: whole rows of the same matrix, encoded by the oracle.
-    Timed on all the process's cores (up to 16) and on one core.  With
+    """The CPU oracle, as it stands, timed on this host's cores (a baseline,
+    not a target), following the plan: decode + FP64 GEMV and decode alone,
+    on one core and on all the process's cores (up to 16), for the 4096^2
+    matrix at rate 16 (whole matrix, median of 10 runs) and for row samples
+    of the 65536^2 matrix at rates 8 and 16 (median of 3).  The oracle's
+    GEMV threads over block rows itself; its decode is single-threaded, so
+    the all-core decode runs it on equal row chunks from a thread pool.
+    Inputs (generation, encoding) are prepared before the clock starts.  With
     y_gpu (the GPU's y for u = the spec's dose vector), also the relative L2
-    error of its first rows against the oracle's FP64 GEMV of the same rows."""
+    error of its first rows against the oracle's FP64 GEMV of those rows."""
+    import statistics
+    from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import oracle
     from paper_1902_08018_amd import synth
-    spec = synth.LARGE if size == 65536 else synth.MatrixSpec(size, size, int(round(size ** 0.5)), 32.0)
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))
-    nrows = 16 * max(cores, 16)  # 4 block-rows per thread, and at least the 256 rows of the parity check
-    M = synth.matrix_rows(spec, 0, nrows)
-    s = oracle.encode(M, rate)
-    u = synth.u_vector(spec)
-    y_ref = oracle.gemv_fp64(s, nrows, spec.cols, rate, u, nthreads=cores)  # warm, and the parity reference
+    pool = ThreadPoolExecutor(max_workers=cores)
 
-    def timed(n, threads, budget_s):
-        t0 = time.perf_counter()
-        reps = 0
-        while True:
-            oracle.gemv_fp64(s, n, spec.cols, rate, u, nthreads=threads)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el * threads >= budget_s or reps >= 50:
-                return el, reps
+    def chunks(n, parts):
+        step = max(4, (n // parts + 3) // 4 * 4)
+        return [(r, min(n, r + step)) for r in range(0, n, step)]
 
-    el, reps = timed(nrows, cores, 10.0)
-    sec = el / reps
-    eff_gbs = nrows * spec.cols * 4 / sec / 1e9
-    n1 = 16  # four block-rows on one core
-    el1, reps1 = timed(n1, 1, 1.0)
-    sec1 = el1 / reps1
-    base = {"value": round(eff_gbs, 4), "unit": "GB/s effective (uncompressed FP32 bytes/s)", "cores": cores,
-            "kind": "oracle",
-            "sample": f"rows 0..{nrows} of the {spec.rows}x{spec.cols} matrix (all columns), rate {rate}, "
-                      f"oracle decode + FP64 GEMV, {reps} reps, {el:.1f} s wall",
-            "gflops": round(nrows * (2 * spec.cols - 1) / sec / 1e9, 4),
-            "single_core": {"value": round(n1 * spec.cols * 4 / sec1 / 1e9, 4),
-                            "gflops": round(n1 * (2 * spec.cols - 1) / sec1 / 1e9, 4),
-                            "sample": f"rows 0..{n1}, {reps1} reps, {el1:.2f} s wall"}}
+    def encode_par(spec, r0, r1, rt):
+        table = synth.kernel_table(spec)
+        parts = pool.map(lambda c: oracle.encode(synth.matrix_rows(spec, r0 + c[0], r0 + c[1], table), rt),
+                         chunks(r1 - r0, cores))
+        return np.concatenate(list(parts))
+
+    def median_s(fn, reps):
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        return statistics.median(t)
+
+    def time_case(spec, code, n, rt, threads, reps, u):
+        per = oracle.stream_nbytes(4, spec.cols, rt)
+        if threads == 1:
+            t_g = median_s(lambda: oracle.gemv_fp64(code, n, spec.cols, rt, u, nthreads=1), reps)
+            t_d = median_s(lambda: oracle.decode(code, n, spec.cols, rt), reps)
+        else:
+            cs = chunks(n, threads)
+            t_g = median_s(lambda: oracle.gemv_fp64(code, n, spec.cols, rt, u, nthreads=threads), reps)
+            t_d = median_s(lambda: list(pool.map(
+                lambda c: oracle.decode(code[c[0] // 4 * per:(c[1] + 3) // 4 * per], c[1] - c[0], spec.cols, rt),
+                cs)), reps)
+        vals = n * spec.cols
+        return {"decode_gemv": {"s": round(t_g, 5), "gflops": round(n * (2 * spec.cols - 1) / t_g / 1e9, 4),
+                                "values_per_s": float(f"{vals / t_g:.4g}"),
+                                "effective_gbs": round(4.0 * vals / t_g / 1e9, 4)},
+                "decode_only": {"s": round(t_d, 5), "values_per_s": float(f"{vals / t_d:.4g}"),
+                                "effective_gbs": round(4.0 * vals / t_d / 1e9, 4)}}
+
+    t_all0 = time.perf_counter()
+    plan = {}
+    # 4096^2, rate 16: the whole matrix, median of 10
+    sm = synth.SMALL
+    code = encode_par(sm, 0, sm.rows, 16)
+    u = synth.u_vector(sm)
+    plan["4096x4096_rate16_whole_matrix"] = {
+        "all_cores": time_case(sm, code, sm.rows, 16, cores, 10, u),
+        "one_core": time_case(sm, code, sm.rows, 16, 1, 10, u), "runs": 10}
+    # 65536^2, rates 8 and 16: row samples (whole rows), median of 3
+    lg = synth.LARGE
+    u = synth.u_vector(lg)
+    n_all, n_one = 1024, 64
+    for rt in (8, 16):
+        code = encode_par(lg, 0, n_all, rt)
+        plan[f"65536x65536_rate{rt}_rows_0_{n_all}"] = {
+            "all_cores": time_case(lg, code, n_all, rt, cores, 3, u),
+            "one_core": dict(time_case(lg, code, n_one, rt, 1, 3, u), rows=f"0..{n_one}"), "runs": 3}
+    head = plan[f"65536x65536_rate{rate}_rows_0_{n_all}"]["all_cores"]["decode_gemv"] if size == 65536 else None
+    wall = time.perf_counter() - t_all0
+    base = {"value": head["effective_gbs"] if head else None,
+            "unit": "GB/s effective (uncompressed FP32 bytes/s)", "cores": cores, "kind": "oracle",
+            "sample": f"rows 0..{n_all} of the 65536x65536 matrix (all columns), rate {rate}, oracle decode + FP64 "
+                      f"GEMV on {cores} threads, median of 3",
+            "gflops": head["gflops"] if head else None,
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "threads_used": cores,
+            "clock": "wall (perf_counter); generation and encoding excluded",
+            "plan": plan, "total_wall_s": round(wall, 1),
+            "paper_context": "CPU-MP (AVX2 + OpenMP, uncompressed, Xeon E5-2660 v4): 23.14 GFLOP/s"}
     parity = None
     if y_gpu is not None:
-        n = min(len(y_gpu), nrows)
-        d = np.asarray(y_gpu[:n], np.float64) - y_ref[:n]
-        parity = {"rows": f"0..{n}", "rel_l2": float(np.linalg.norm(d) / np.linalg.norm(y_ref[:n])),
+        spec = lg if size == 65536 else synth.MatrixSpec(size, size, int(round(size ** 0.5)), 32.0)
+        n = min(len(y_gpu), 256)
+        sref = oracle.encode(synth.matrix_rows(spec, 0, n), rate)
+        y_ref = oracle.gemv_fp64(sref, n, spec.cols, rate, synth.u_vector(spec), nthreads=cores)
+        d = np.asarray(y_gpu[:n], np.float64) - y_ref
+        parity = {"rows": f"0..{n}", "rel_l2": float(np.linalg.norm(d) / np.linalg.norm(y_ref)),
                   "max_abs": float(np.abs(d).max()), "tolerance": 1e-6}
+    pool.shutdown()
     return base, parity
 
 
@@ -482,6 +661,7 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
     Ybuf = [[torch.empty((8, sp.rows), dtype=torch.float32).pin_memory() for _ in range(pool)] for sp in specs]
     slot = [0] * nm
     outstanding = {}
+    last_done = [None] * nm
     lat, miss, bsz, rejected = [], 0, [], 0
     per = [{"lat": [], "miss": 0, "rejected": 0} for _ in range(nm)]
     t0 = time.monotonic_ns() + 50_000_000
@@ -492,12 +672,13 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
         while i < n and t0 + int(arrive[i] * 1e9) <= now:
             j = int(target[i])
             k = int(ks[i])
-            Y = Ybuf[j][slot[j] % pool]
+            yslot = slot[j] % pool
+            Y = Ybuf[j][yslot]
             slot[j] += 1
             req = wh.wh_request(mat=mats[j], U=Ubuf[j].data_ptr(), u_on_device=0, k=k, Y=Y.data_ptr(), y_on_device=0,
                                 deadline_ns=int(deadline_ms * 1e6), arrival_ns=t0 + int(arrive[i] * 1e9))
             try:
-                outstanding[wh.wh_submit(ctx, req)] = i
+                outstanding[wh.wh_submit(ctx, req)] = (i, yslot)
             except wh.WhError:
                 rejected += 1
                 if i >= n_warm:
@@ -506,8 +687,9 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
         for tk in list(outstanding):
             st, r = wh.wh_poll(ctx, tk)
             if st == wh.WH_OK:
-                idx = outstanding.pop(tk)
+                idx, yslot = outstanding.pop(tk)
                 done_count += 1
+                last_done[int(target[idx])] = (idx, yslot)
                 if idx >= n_warm:
                     lat.append((r.t_done_ns - r.t_arrive_ns) * 1e-6)
                     miss += r.missed
@@ -521,6 +703,18 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
                 time.sleep(min(nxt, 1_000_000) * 1e-9 * 0.5)
     t_total = (time.monotonic_ns() - t0) * 1e-9
     wh.wh_destroy(ctx)
+    # the last request each matrix completed, against the oracle on sampled
+    # rows (its Y buffer is not reused after it: nothing else is in flight)
+    checks = {}
+    for j, sp in enumerate(specs):
+        if last_done[j] is None:
+            continue
+        idx, yslot = last_done[j]
+        k = int(ks[idx])
+        smp = SampledRows(sp, nsample=6)
+        ref = Ubuf[j][:k].numpy().astype(np.float64) @ smp.decoded(8).T
+        checks[f"{sp.rows}x{sp.cols}"] = dict(err_entry(smp.take(Ybuf[j][yslot][:k].numpy()), ref, 1e-6),
+                                              request=int(idx), k=k)
     lat = np.array(lat)
     return {"requests": int(len(lat)), "rate_hz": rate_hz, "deadline_ms": deadline_ms,
             "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -529,6 +723,7 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
             "mean_batch_requests": round(float(np.mean(bsz)), 2), "rejected": rejected,
             "hbm_budget_mb": budget_mb, "shed_after_deadlines": shed,
             "matrices": [f"{sp.rows}x{sp.cols} rate 8" for sp in specs],
+            "last_result_error_vs_oracle": checks,
             "per_matrix": {f"{sp.rows}x{sp.cols}": {"requests": len(pj["lat"]),
                                                    "p50_ms": round(float(np.percentile(pj["lat"], 50)), 3),
                                                    "p99_ms": round(float(np.percentile(pj["lat"], 99)), 3),
@@ -584,8 +779,12 @@ def main():
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
+        xo = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            wh.wh_stream_read(ctx, a, xo)
         torch.cuda.synchronize()
-        print(f"# probe done: 3 x wh_gemv rate {rate} {rows}x{cols}, 3 x copy of {a.numel() * 4} bytes",
+        print(f"# probe done: 3 x wh_gemv rate {rate} {rows}x{cols}, 3 x copy and 3 x read-only stream of "
+              f"{a.numel() * 4} bytes",
               file=sys.stderr, flush=True)
         wh.wh_destroy(ctx)
         return
@@ -618,6 +817,10 @@ def main():
     cb = torch.empty_like(ca)
     copy_ms = time_call(lambda i: cb.copy_(ca), 5, 2)
     copy_gbs = 2 * ca.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    # and the read-only ceiling: the library's streaming probe reads 4 GiB once
+    xo = torch.zeros(1, dtype=torch.int32, device="cuda")
+    read_ms = time_call(lambda i: wh.wh_stream_read(ctx, ca, xo), 5, 2)
+    read_gbs = ca.numel() * 4 / (read_ms * 1e-3) / 1e9
     del ca, cb
     out = {
         "metric": "decode+GEMV effective GB/s (frac of HBM peak), GFLOP/s; p99 latency vs deadline",
@@ -646,7 +849,8 @@ def main():
                                   "378 x 256000 GEMV): context, not this metric's baseline"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "copy_ceiling_gbs": round(copy_gbs, 1)},
+                     "copy_ceiling_gbs": round(copy_gbs, 1), "read_ceiling_gbs": round(read_gbs, 1),
+                     "frac_of_read_ceiling": round(achieved / read_gbs, 4)},
     }
     if valu_insts:
         # the decoder's own bound: VALU issue, 64 lanes per wave64 instruction
@@ -661,17 +865,25 @@ def main():
     torch.cuda.empty_cache()
 
     if args.extra:
+        import numpy as np
         extra = {}
+        print("# oracle references for sampled rows", file=sys.stderr, flush=True)
+        sample = SampledRows(spec)
+        u64 = synth.u_vector(spec).astype(np.float64)
+        extra["sampled_rows_for_errors"] = (f"{len(sample.idx)} rows in {len(sample.brows)} block rows spread over "
+                                            f"0..{rows}; references: the oracle's FP64 products")
         # rate 16 on the same matrix
         print("# rate 16", file=sys.stderr, flush=True)
         s16 = workload.build_stream(ctx, spec, 16)
         m16 = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, 16, s16)
         w16, e16 = time_gemv(ctx, m16, us, y, rows, max(5, args.steps // 2), 2, args.flags)
         k16 = sum(e16) / len(e16)
+        wh.wh_gemv(ctx, m16, us[0], y, 0, rows, args.flags)
         extra["rate16"] = {"effective_gbs": round(4.0 * rows * cols / (k16 * 1e-3) / 1e9, 2),
                            "kernel_ms": round(k16, 4),
                            "hbm_frac": round((s16.numel() + 8 * cols) / (k16 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "gflops": round(flop / (k16 * 1e-3) / 1e9, 2)}
+                           "gflops": round(flop / (k16 * 1e-3) / 1e9, 2),
+                           "error_vs_oracle": err_entry(sample.take(y), sample.decoded(16) @ u64, 1e-6)}
         # separate path: decode to dense FP32, then dense GEMV (rate 8)
         print("# separate path", file=sys.stderr, flush=True)
         wh.wh_unload(ctx, m16)
@@ -698,11 +910,17 @@ def main():
             td += e0.elapsed_time(e1)
             tg += e1.elapsed_time(e2)
         td, tg = td / reps, tg / reps
+        wh.wh_gemv(ctx, dm, us[0], y, 0, rows)
+        dec_rows = dense[torch.from_numpy(sample.idx).cuda()].cpu().numpy()
         extra["separate_rate8"] = {"decode_ms": round(td, 4), "dense_gemv_ms": round(tg, 4),
                                    "total_ms": round(td + tg, 4),
                                    "effective_gbs": round(4.0 * rows * cols / ((td + tg) * 1e-3) / 1e9, 2),
                                    "dense_gemv_hbm_frac": round((4.0 * rows * cols + 8 * cols) / (tg * 1e-3) / 1e9
-                                                                / HBM_PEAK_GBS, 4)}
+                                                                / HBM_PEAK_GBS, 4),
+                                   "decode_bitexact_on_sampled_rows": bool(np.array_equal(
+                                       dec_rows.view(np.uint32),
+                                       sample.decoded(rate).astype(np.float32).view(np.uint32))),
+                                   "error_vs_oracle": err_entry(sample.take(y), sample.decoded(rate) @ u64, 1e-6)}
         # one GPU's share of an 8-way row split (the sharded layout needs no
         # exchange: each GPU owns 8192 rows of the stream and of y)
         print("# row shard", file=sys.stderr, flush=True)
@@ -710,18 +928,23 @@ def main():
         for r0 in (0, rows - rows // 8):
             ms = time_call(lambda i: wh.wh_gemv(ctx, m8, us[i % 4], y[: rows // 8], r0, r0 + rows // 8),
                            max(5, args.steps // 2), 2)
+            wh.wh_gemv(ctx, m8, us[0], y[: rows // 8], r0, r0 + rows // 8)
+            sel = (sample.idx >= r0) & (sample.idx < r0 + rows // 8)
+            got = y[torch.from_numpy(sample.idx[sel] - r0).cuda()].cpu().numpy()
             shard[f"rows_{r0}_{r0 + rows // 8}"] = {"ms": round(ms, 4),
-                                                   "effective_gbs": round(4.0 * rows // 8 * cols / (ms * 1e-3) / 1e9, 1)}
+                                                   "effective_gbs": round(4.0 * rows // 8 * cols / (ms * 1e-3) / 1e9, 1),
+                                                   "error_vs_oracle": err_entry(got, (sample.decoded(rate) @ u64)[sel],
+                                                                                1e-6)}
         extra["row_shard_1_of_8_rate8"] = shard
         print("# multi-RHS", file=sys.stderr, flush=True)
-        extra["multi_rhs_rate8"] = bench_multi_rhs(ctx, m8, spec, rate, s8.numel(), max(3, args.steps // 4))
+        extra["multi_rhs_rate8"] = bench_multi_rhs(ctx, m8, spec, rate, s8.numel(), max(3, args.steps // 4), sample)
         out["extra"] = extra
         wh.wh_unload(ctx, dm)
         wh.wh_unload(ctx, m8)
         del dense, s8
         torch.cuda.empty_cache()
         print("# dense precision sweep", file=sys.stderr, flush=True)
-        extra["dense_precision"] = bench_precision(ctx, spec, us, y, max(5, args.steps // 2))
+        extra["dense_precision"] = bench_precision(ctx, spec, us, y, max(5, args.steps // 2), sample)
         print("# the paper's GEMV shapes and slit windows of a field matrix", file=sys.stderr, flush=True)
         extra[f"slit_field_rate{rate}"] = bench_slit_field(ctx, rate, max(10, args.steps))
         print("# host-resident matrices streamed over the link (child process)", file=sys.stderr, flush=True)

@@ -283,6 +283,16 @@ wh_status wh_encode(wh_ctx *ctx, const float *d_M, uint32_t rows, uint32_t cols,
 wh_status wh_quantize(wh_ctx *ctx, const float *d_M, uint32_t rows, uint32_t cols, int32_t fmt, void *d_out,
                       void *stream);
 
+/* Diagnostics: the device's read-only streaming ceiling.  Reads the nbytes
+ * of d_buf (16-byte aligned, nbytes a multiple of 16) once with 16-byte
+ * non-temporal loads and XORs every 32-bit word of it into *d_out (device
+ * uint32, not cleared by the call: clear it first to get the buffer's XOR).
+ * The time of this call is the HBM read rate a kernel that only streams its
+ * input can reach -- the practical ceiling for the compressed GEMV, which
+ * reads its stream once and writes almost nothing (the paper prices its
+ * kernels against memory bandwidth, Sec. 4.1, Fig. 4). */
+wh_status wh_stream_read(wh_ctx *ctx, const void *d_buf, uint64_t nbytes, uint32_t *d_out, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Serving loop (Sec. 1: firm deadlines; Fig. 2: per-millisecond calls) */
 /* ------------------------------------------------------------------ */

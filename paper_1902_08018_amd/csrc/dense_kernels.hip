@@ -362,6 +362,45 @@ __global__ void __launch_bounds__(kThreads) quant_fp8bs_kernel(const float* __re
     }
 }
 
+// Read-only streaming probe: every 16-byte vector of the buffer is loaded
+// once (non-temporal, 4 vectors in flight per lane per step, grid-stride)
+// and folded by XOR; one atomic XOR per workgroup publishes the fold.  Its
+// time is the practical HBM read ceiling of the device for a stream that is
+// read once and not written, the access pattern of the compressed GEMV.
+__global__ void __launch_bounds__(kThreads) stream_read_kernel(const u32x4* __restrict__ buf, uint64_t nvec,
+                                                               uint32_t* __restrict__ out)
+{
+    __shared__ uint32_t red[kThreads / 64];
+    constexpr uint64_t kUnroll = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    uint32_t x = 0;
+    uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    for (; i + (kUnroll - 1) * stride < nvec; i += kUnroll * stride) {
+        u32x4 v[kUnroll];
+#pragma unroll
+        for (uint64_t k = 0; k < kUnroll; ++k)
+            v[k] = __builtin_nontemporal_load(buf + i + k * stride);
+#pragma unroll
+        for (uint64_t k = 0; k < kUnroll; ++k)
+            x ^= v[k].x ^ v[k].y ^ v[k].z ^ v[k].w;
+    }
+    for (; i < nvec; i += stride) {
+        const u32x4 v = __builtin_nontemporal_load(buf + i);
+        x ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    for (int m = 32; m >= 1; m >>= 1)
+        x ^= (uint32_t)__shfl_xor((int)x, m, 64);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kThreads / 64; ++w)
+            t ^= red[w];
+        atomicXor(out, t);
+    }
+}
+
 unsigned grid_for(uint64_t items, unsigned cap = 65536)
 {
     uint64_t g = (items + kThreads - 1) / kThreads;
@@ -525,4 +564,27 @@ extern "C" wh_status wh_quantize(wh_ctx* ctx, const float* d_M, uint32_t rows, u
     } catch (...) {
         return WH_ERR_INVALID;
     }
+}
+
+extern "C" wh_status wh_stream_read(wh_ctx* ctx, const void* d_buf, uint64_t nbytes, uint32_t* d_out, void* stream)
+{
+    using namespace wh;
+    if (!ctx)
+        return WH_ERR_INVALID;
+    if (ctx->failed.load())
+        return WH_ERR_DEVICE;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return WH_ERR_DEVICE;
+    if (!d_buf || !d_out || !aligned(d_buf, 16) || nbytes % 16 != 0)
+        return WH_ERR_INVALID;
+    const uint64_t nvec = nbytes / 16;
+    if (nvec == 0)
+        return WH_OK;
+    // about 8 workgroups of 256 lanes per CU, each lane with 4 loads in flight
+    const uint64_t want = (nvec + kThreads - 1) / kThreads;
+    const uint64_t cap = (uint64_t)(ctx->num_cus > 0 ? ctx->num_cus : 256) * 8;
+    const unsigned grid = (unsigned)(want < cap ? want : cap);
+    hipLaunchKernelGGL(stream_read_kernel, dim3(grid), dim3(kThreads), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const u32x4*>(d_buf), nvec, d_out);
+    return device_error(ctx, hipGetLastError());
 }

@@ -84,6 +84,7 @@ _sig = {
     "wh_decode": ([_P, _U64, _P, _P], _I32),
     "wh_encode": ([_P, _P, _U32, _U32, _U32, _P, _P, _P], _I32),
     "wh_quantize": ([_P, _P, _U32, _U32, _I32, _P, _P], _I32),
+    "wh_stream_read": ([_P, _P, _U64, _P, _P], _I32),
     "wh_submit": ([_P, ctypes.POINTER(wh_request), ctypes.POINTER(_U64)], _I32),
     "wh_poll": ([_P, _U64, ctypes.POINTER(wh_result)], _I32),
 }
@@ -370,6 +371,12 @@ def wh_quantize(ctx: int, M: torch.Tensor, fmt: int, out: torch.Tensor, stream=N
           f"out holds {_nbytes(out)} bytes, the format takes {wh_storage_bytes(rows, cols, fmt)}")
     _check(_lib.wh_quantize(ctx, _dptr(M, torch.float32, "M"), rows, cols, fmt, _dptr(out, name="out"),
                             _stream(stream)), "wh_quantize")
+
+
+def wh_stream_read(ctx: int, buf: torch.Tensor, out: torch.Tensor, stream=None) -> None:
+    nbytes = buf.numel() * buf.element_size()
+    _check(_lib.wh_stream_read(ctx, _dptr(buf, name="buf"), nbytes, _dptr(out, torch.int32, "out"), _stream(stream)),
+           "wh_stream_read")
 
 
 def wh_submit(ctx: int, req: wh_request) -> int:
