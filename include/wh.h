@@ -55,6 +55,8 @@ typedef int32_t wh_status;
 #define WH_ERR_BUDGET (-5)    /* serving admission: over the HBM budget    */
 #define WH_ERR_DEVICE (-6)    /* HIP error; the context is now failed      */
 #define WH_ERR_NOT_FOUND (-7) /* unknown matrix handle or ticket           */
+#define WH_ERR_SCRATCH (-8)   /* wh_gemv_noalloc: the call needs more than
+                                 WH_NOALLOC_SCRATCH_BYTES of workspace      */
 
 /* Storage formats of a resident matrix. */
 typedef enum {
@@ -172,9 +174,37 @@ wh_status wh_unload(wh_ctx *ctx, wh_mat m);
  * (default) or compensated FP32 across
  * blocks; y is rounded once to FP32 (Fig. 7).  WH_PAPER_MP instead
  * multiplies every bit-exact decoded value by u in FP32 and adds each
- * product to an FP64 sum.  Dense formats multiply the stored values. */
+ * product to an FP64 sum.  Dense formats multiply the stored values.
+ *
+ * Workspace: when the plan splits the columns into slabs (most large
+ * compressed matrices, wh_gemv_plan_info), the FP64 slab partials live in a
+ * workspace of the context's, grown (freed and reallocated) on demand.  Such
+ * a call returns WH_ERR_INVALID while `stream` is being captured into a HIP
+ * graph, since a later call could free the memory the graph would keep
+ * using; wh_gemv_noalloc is the form to capture.  The same holds for
+ * wh_gemv_batched and wh_gemv_host. */
 wh_status wh_gemv(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t row_begin, uint32_t row_end,
                   uint32_t flags, void *stream);
+
+/* wh_gemv without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc.  WHZ1 fixed-rate matrices only (else WH_ERR_FORMAT); arguments,
+ * launch plan, kernels and result as wh_gemv, so y is the same.
+ *
+ * Workspace: the FP64 slab partials live in a device array of the library's
+ * of WH_NOALLOC_SCRATCH_BYTES (32 MiB), one per GPU, held from the first
+ * wh_create on that GPU until the process ends.  A call whose plan needs more
+ * (column slabs x the range's rows rounded up to whole block rows x 8 bytes;
+ * wh_gemv_plan_info gives both) returns WH_ERR_SCRATCH and launches nothing:
+ * 65536 x 65536 needs 22.5 MB.  Calls whose work overlaps on one GPU (other
+ * streams, other contexts) share that array and race; calls in order on one
+ * stream are safe.  The array keeps the last call's contents; nothing in it
+ * has to start at zero.  No hipMalloc, hipFree, event or memset is issued, so
+ * the call can be captured into a graph (the graph then keeps using the
+ * array). */
+#define WH_NOALLOC_SCRATCH_BYTES (32ull << 20)
+wh_status wh_gemv_noalloc(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t row_begin,
+                          uint32_t row_end, uint32_t flags, void *stream);
 
 /* The launch shape the fused compressed GEMV would use for rows
  * [row_begin, row_end) of a rows x cols matrix on a device with num_cus

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libwh.so")
 
 ARCH = "gfx950"
-HIP_SOURCES = ["whz_dispatch.hip", "dense_kernels.hip", "serve.hip", "host_stream.hip", "thermal.hip", "whz_var.hip", "wh_api.hip"]
+HIP_SOURCES = ["whz_dispatch.hip", "dense_kernels.hip", "serve.hip", "host_stream.hip", "thermal.hip", "whz_var.hip", "wh_api.hip", "noalloc.hip"]
 # words per compressed block (rate = 2 * words) with a compiled decoder
 WHZ_WORDS = [1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16]
 HIPCC_FLAGS = [

@@ -110,19 +110,22 @@ bool capturing(hipStream_t st)
 
 wh_status ensure_partials(wh_ctx* ctx, size_t count, hipStream_t st)
 {
+    // a later call may grow the workspace, freeing the memory a captured
+    // graph would go on using: calls that need it are not captured
+    // (wh_gemv_noalloc is the capturable form)
+    if (capturing(st))
+        return WH_ERR_INVALID;
     if (count > ctx->part_cap) {
         const wh_status s = grow_partials(ctx, count);
         if (s != WH_OK)
             return s;
     }
-    if (capturing(st))
-        return WH_OK;
     return device_error(ctx, hipStreamWaitEvent(st, ctx->part_ev, 0));
 }
 
 hipError_t partials_release(wh_ctx* ctx, hipStream_t st, hipError_t e)
 {
-    if (e != hipSuccess || capturing(st))
+    if (e != hipSuccess)
         return e;
     return hipEventRecord(ctx->part_ev, st);
 }
@@ -180,6 +183,8 @@ const char* wh_status_str(wh_status st)
         return "HIP device error (context failed)";
     case WH_ERR_NOT_FOUND:
         return "unknown matrix handle or ticket";
+    case WH_ERR_SCRATCH:
+        return "the call needs more workspace than wh_gemv_noalloc's fixed scratch array holds";
     default:
         return "unknown status";
     }
@@ -201,6 +206,9 @@ wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
             return WH_ERR_DEVICE;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess)
+            return WH_ERR_DEVICE;
+        // the device address of wh_gemv_noalloc's scratch array on this device
+        if (noalloc_init(hip_device) != WH_OK)
             return WH_ERR_DEVICE;
         wh_ctx* ctx = new wh_ctx();
         ctx->device = hip_device;

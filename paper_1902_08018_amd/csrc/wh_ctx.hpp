@@ -44,8 +44,9 @@ wh_status device_error(wh_ctx* ctx, hipError_t e);
 // The context's FP64 slab-partials workspace, shared by every call that
 // splits columns: grow it to `count` doubles, and make `st` wait until the
 // previous user's work on the device is done (on whatever stream it ran).
-// The user then calls partials_release after its launches.  Neither waits
-// nor records while `st` is being captured into a graph.
+// The user then calls partials_release after its launches.  Returns
+// WH_ERR_INVALID while `st` is being captured into a graph: a later call may
+// regrow (free) the workspace that the graph would keep using.
 wh_status ensure_partials(wh_ctx* ctx, size_t count, hipStream_t st);
 hipError_t partials_release(wh_ctx* ctx, hipStream_t st, hipError_t e);
 Matrix* find_matrix(wh_ctx* ctx, wh_mat m);
@@ -54,6 +55,10 @@ bool aligned(const void* p, uintptr_t a);
 // Dense-storage GEMV (FP32 / FP16 / BF16 / FP8 block-scaled), dense_kernels.hip.
 wh_status dense_gemv_dispatch(wh_ctx* ctx, const Matrix& mat, AccMode mode, const float* d_u, float* d_y,
                               uint32_t row_begin, uint32_t row_end, hipStream_t st);
+
+// With `device` current, find the device address of wh_gemv_noalloc's
+// scratch array on it (once per device); wh_create calls it.
+wh_status noalloc_init(int device);
 
 void serve_shutdown(wh_ctx* ctx);
 // Drop the serving state of matrix m (after its batches in flight finish;

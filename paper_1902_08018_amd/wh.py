@@ -24,7 +24,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 WH_OK, WH_PENDING = 0, 1
 WH_ERR_INVALID, WH_ERR_SHAPE, WH_ERR_FORMAT, WH_ERR_NOMEM = -1, -2, -3, -4
-WH_ERR_BUDGET, WH_ERR_DEVICE, WH_ERR_NOT_FOUND = -5, -6, -7
+WH_ERR_BUDGET, WH_ERR_DEVICE, WH_ERR_NOT_FOUND, WH_ERR_SCRATCH = -5, -6, -7, -8
+WH_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 WH_FMT_ZFP_FIXED_RATE, WH_FMT_F32, WH_FMT_F16, WH_FMT_BF16, WH_FMT_FP8E4M3_BS4 = 1, 2, 3, 4, 5
 WH_FMT_ZFP_FIXED_PRECISION, WH_FMT_ZFP_FIXED_ACCURACY = 6, 7
@@ -70,6 +71,7 @@ _sig = {
                            _I32),
     "wh_unload": ([_P, _U64], _I32),
     "wh_gemv": ([_P, _U64, _P, _P, _U32, _U32, _U32, _P], _I32),
+    "wh_gemv_noalloc": ([_P, _U64, _P, _P, _U32, _U32, _U32, _P], _I32),
     "wh_gemv_batched": ([_P, _U64, _P, ctypes.c_int, _U32, _U32, _P, _U32, _U32, _P], _I32),
     "wh_gemv_host": ([_P, _P, _U32, _U32, _U32, _P, _P, _U32, _U32, _U32, _U32, _P], _I32),
     "wh_gemv_plan_info": ([_U32, _U32, _U32, _U32, ctypes.c_int, ctypes.POINTER(_U32)], _I32),
@@ -203,6 +205,16 @@ def wh_gemv(ctx: int, mat: int, u: torch.Tensor, y: torch.Tensor, row_begin: int
         _need(y.numel() >= row_end - row_begin, f"y holds {y.numel()} values for {row_end - row_begin} rows")
     _check(_lib.wh_gemv(ctx, mat, _dptr(u, torch.float32, "u"), _dptr(y, torch.float32, "y"), row_begin, row_end,
                         flags, _stream(stream)), "wh_gemv")
+
+
+def wh_gemv_noalloc(ctx: int, mat: int, u: torch.Tensor, y: torch.Tensor, row_begin: int, row_end: int,
+                    flags: int = WH_ACC_DEFAULT, stream=None) -> None:
+    shp = _shapes.get((ctx, mat))
+    if shp is not None:
+        _need(u.numel() >= shp[1], f"u holds {u.numel()} values, the matrix has {shp[1]} columns")
+        _need(y.numel() >= row_end - row_begin, f"y holds {y.numel()} values for {row_end - row_begin} rows")
+    _check(_lib.wh_gemv_noalloc(ctx, mat, _dptr(u, torch.float32, "u"), _dptr(y, torch.float32, "y"), row_begin,
+                                row_end, flags, _stream(stream)), "wh_gemv_noalloc")
 
 
 def wh_gemv_host(ctx: int, h_code, rows: int, cols: int, rate: int, u: torch.Tensor, y: torch.Tensor,

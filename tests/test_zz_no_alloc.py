@@ -1,0 +1,143 @@
+"""wh_gemv_noalloc: the fused compressed GEMV with its slab partials in the
+library's fixed device array instead of an allocated workspace.
+
+  parity     two calls in a row through the C ABI, the second on a smaller
+             input, each equal to wh_gemv's y (same plan and kernels: the
+             same values) and within relative L2 1e-6 of the FP64 oracle
+  limit      a plan needing more than the array holds returns WH_ERR_SCRATCH
+             and launches nothing; wh_gemv still takes it
+  capture    the call recorded into a HIP graph gives the eager result on
+             every replay; wh_gemv, whose workspace may be regrown, refuses
+             to be captured when its plan needs that workspace
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1902_08018_amd import synth, wh
+
+pytestmark = pytest.mark.gpu
+
+REL_L2_FP32 = 1e-6
+
+
+def rel_l2(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+
+
+def scratch_doubles(rows, cols, r0, r1):
+    p = wh.wh_gemv_plan_info(rows, cols, r0, r1, torch.cuda.get_device_properties(0).multi_processor_count)
+    return p["nslab"] * (p["bi_end"] - p["bi_begin"]) * 4 if p["nslab"] > 1 else 0, p
+
+
+def load(ctx, spec, rate):
+    M = synth.matrix(spec)
+    s = oracle.encode(M, rate)
+    d = torch.from_numpy(s).cuda()
+    mat = wh.wh_load_compressed(ctx, spec.rows, spec.cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, d)
+    return mat, s
+
+
+@pytest.mark.parametrize("flags", [wh.WH_ACC_DEFAULT, wh.WH_ACC_TWOSUM])
+def test_noalloc_two_calls_match_gemv(gpu_ctx, flags):
+    # first call: 1024 x 8192 (several slabs, a ragged row range); second:
+    # a smaller matrix whose plan also splits its columns
+    cases = [(synth.MatrixSpec(1024, 8192, 64, 8.0), 8, 3, 1021),
+             (synth.MatrixSpec(256, 2048, 32, 8.0), 16, 0, 256)]
+    for spec, rate, r0, r1 in cases:
+        need, plan = scratch_doubles(spec.rows, spec.cols, r0, r1)
+        print(f"case {spec.rows}x{spec.cols} rate {rate} rows [{r0},{r1}) plan {plan} scratch doubles {need}",
+              flush=True)
+        assert 0 < need * 8 <= wh.WH_NOALLOC_SCRATCH_BYTES
+        mat, s = load(gpu_ctx, spec, rate)
+        u = synth.u_vector(spec)
+        ud = torch.from_numpy(u).cuda()
+        y_ref = torch.full((r1 - r0,), float("nan"), dtype=torch.float32, device="cuda")
+        y_na = torch.full((r1 - r0,), float("nan"), dtype=torch.float32, device="cuda")
+        wh.wh_gemv(gpu_ctx, mat, ud, y_ref, r0, r1, flags)
+        wh.wh_gemv_noalloc(gpu_ctx, mat, ud, y_na, r0, r1, flags)
+        torch.cuda.synchronize()
+        a, b = y_na.cpu().numpy(), y_ref.cpu().numpy()
+        assert np.all(np.isfinite(a))
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        ref = oracle.gemv_fp64(s, spec.rows, spec.cols, rate, u)[r0:r1]
+        assert rel_l2(a, ref) <= REL_L2_FP32
+        wh.wh_unload(gpu_ctx, mat)
+
+
+def test_noalloc_rejects_a_plan_beyond_the_array():
+    # 1024 column slabs over 8192 rows need 64 MiB of partials
+    rows, cols, rate = 8192, 32768, 2
+    old = os.environ.get("WH_GEMV_SLABS")
+    os.environ["WH_GEMV_SLABS"] = "1024"
+    try:
+        ctx = wh.wh_create(0, 0)
+    finally:
+        if old is None:
+            del os.environ["WH_GEMV_SLABS"]
+        else:
+            os.environ["WH_GEMV_SLABS"] = old
+    try:
+        code = torch.zeros(wh.stream_bytes(rows, cols, rate), dtype=torch.uint8, device="cuda")
+        mat = wh.wh_load_compressed(ctx, rows, cols, wh.WH_FMT_ZFP_FIXED_RATE, rate, code)
+        u = torch.ones(cols, dtype=torch.float32, device="cuda")
+        y = torch.full((rows,), 7.0, dtype=torch.float32, device="cuda")
+        with pytest.raises(wh.WhError) as ei:
+            wh.wh_gemv_noalloc(ctx, mat, u, y, 0, rows)
+        assert ei.value.status == wh.WH_ERR_SCRATCH
+        torch.cuda.synchronize()
+        assert torch.all(y == 7.0)  # nothing ran
+        wh.wh_gemv(ctx, mat, u, y, 0, rows)  # the allocating form takes the plan
+        torch.cuda.synchronize()
+        assert torch.all(y == 0.0)  # an all-zero code is the zero matrix
+        wh.wh_unload(ctx, mat)
+    finally:
+        wh.wh_destroy(ctx)
+
+
+def test_noalloc_captured_in_a_graph(gpu_ctx):
+    spec = synth.MatrixSpec(512, 8192, 64, 8.0)
+    rate = 8
+    need, plan = scratch_doubles(spec.rows, spec.cols, 0, spec.rows)
+    assert need > 0, plan
+    mat, s = load(gpu_ctx, spec, rate)
+    rng = np.random.default_rng(7)
+    us = [rng.random(spec.cols, dtype=np.float32) for _ in range(3)]
+    u_static = torch.empty(spec.cols, dtype=torch.float32, device="cuda")
+    y_static = torch.empty(spec.rows, dtype=torch.float32, device="cuda")
+    u_static.copy_(torch.from_numpy(us[0]))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        wh.wh_gemv_noalloc(gpu_ctx, mat, u_static, y_static, 0, spec.rows)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    refused = None
+    with torch.cuda.graph(g):
+        try:
+            wh.wh_gemv(gpu_ctx, mat, u_static, y_static, 0, spec.rows)
+        except wh.WhError as e:
+            refused = e.status
+        wh.wh_gemv_noalloc(gpu_ctx, mat, u_static, y_static, 0, spec.rows)
+    assert refused == wh.WH_ERR_INVALID
+    for rep in range(6):
+        u = us[rep % 3]
+        u_static.copy_(torch.from_numpy(u))
+        g.replay()
+        torch.cuda.synchronize()
+        got = y_static.cpu().numpy().copy()
+        # eager work between replays: the allocating form on the same input
+        y_eager = torch.empty(spec.rows, dtype=torch.float32, device="cuda")
+        wh.wh_gemv(gpu_ctx, mat, u_static, y_eager, 0, spec.rows)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.view(np.uint32), y_eager.cpu().numpy().view(np.uint32)), rep
+        ref = oracle.gemv_fp64(s, spec.rows, spec.cols, rate, u)
+        assert rel_l2(got, ref) <= REL_L2_FP32
+    del g
+    wh.wh_unload(gpu_ctx, mat)
