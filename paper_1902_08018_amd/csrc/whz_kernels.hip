@@ -473,7 +473,12 @@ constexpr int kMrhsThreads = 64 * kMrhsWaves;
 static_assert(4 * kMrhsWaves == (int)kMrhsTileBlockRows, "block rows per multi-RHS workgroup");
 constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's quarter tile
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
-typedef short mbf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// the BF16 tile of a wave: 16 rows of 32 BF16 coefficients (8 block columns)
+// plus 8 of padding, in the same LDS as the FP32 quarter tile
+constexpr int kATile16Stride = 40;
+static_assert(16 * kATile16Stride * 2 <= 16 * kATileStride * 4, "the BF16 tile fits the FP32 one");
 
 // Staged B^T U.  FP32: row (m * 16 + c) holds column 4c + m of the step for
 // the 16*NT right-hand sides; the odd row length keeps both the staging
@@ -505,6 +510,103 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// B^T U staging items of one step: item i = (right-hand side i / 16, block
+// column i % 16); a thread takes items threadIdx.x + kMrhsThreads * q.
+template <int NT>
+constexpr int kMrhsItems = (16 * 16 * NT + kMrhsThreads - 1) / kMrhsThreads;
+
+// Load the four U values of each of this thread's staging items of the step
+// at block column cb (zero past the last column, past the slab and past k).
+template <bool BF16U, int NT>
+__device__ __forceinline__ void mrhs_load_u(const void* __restrict__ Uv, uint32_t ldu, uint32_t k, uint32_t cols,
+                                            uint32_t cb, uint32_t bc1, float4 (&uv)[kMrhsItems<NT>])
+{
+#pragma unroll
+    for (int q = 0; q < kMrhsItems<NT>; ++q) {
+        const uint32_t i = threadIdx.x + (uint32_t)kMrhsThreads * q;
+        const uint32_t rhs = i >> 4, bcol = i & 15u;
+        float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f;
+        if (i < 16u * 16u * NT && rhs < k && cb + bcol < bc1) {
+            const uint32_t j = 4 * (cb + bcol), nv = cols - j < 4u ? cols - j : 4u;
+            const uint64_t o = (uint64_t)rhs * ldu + j;
+            if constexpr (BF16U) {
+                const uint16_t* U = static_cast<const uint16_t*>(Uv) + o;
+                u0 = bf16_to_float(U[0]);
+                u1 = nv > 1 ? bf16_to_float(U[1]) : 0.f;
+                u2 = nv > 2 ? bf16_to_float(U[2]) : 0.f;
+                u3 = nv > 3 ? bf16_to_float(U[3]) : 0.f;
+            } else {
+                const float* U = static_cast<const float*>(Uv) + o;
+                u0 = U[0];
+                u1 = nv > 1 ? U[1] : 0.f;
+                u2 = nv > 2 ? U[2] : 0.f;
+                u3 = nv > 3 ? U[3] : 0.f;
+            }
+        }
+        uv[q] = make_float4(u0, u1, u2, u3);
+    }
+}
+
+// B^T U of this thread's items into one staging buffer.
+template <bool BF16U, int NT>
+__device__ __forceinline__ void mrhs_stage_u(uint32_t* utw, const float4 (&uv)[kMrhsItems<NT>])
+{
+    using UT = MrhsUt<NT>;
+#pragma unroll
+    for (int q = 0; q < kMrhsItems<NT>; ++q) {
+        const uint32_t i = threadIdx.x + (uint32_t)kMrhsThreads * q;
+        if (i >= 16u * 16u * NT)
+            break;
+        const uint32_t rhs = i >> 4, bcol = i & 15u;
+        float ut[4];
+        lin_bt_u<float>(uv[q].x, uv[q].y, uv[q].z, uv[q].w, ut);
+        if constexpr (BF16U) {
+            uint16_t* utb = reinterpret_cast<uint16_t*>(utw);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                utb[rhs * UT::kBf16Stride + 4 * bcol + m] = to_bf16_rne(ut[m]);
+        } else {
+            float* utf = reinterpret_cast<float*>(utw);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                utf[(m * 16 + bcol) * UT::kF32Stride + rhs] = ut[m];
+        }
+    }
+}
+
+// Loads of a lane's block words (no LDS yet): NW words at g.
+template <int NW>
+__device__ __forceinline__ void load_block_words(const uint32_t* __restrict__ g, uint32_t (&w)[NW])
+{
+    if constexpr (NW % 4 == 0) {
+        const u32x4* g4 = reinterpret_cast<const u32x4*>(g);
+#pragma unroll
+        for (int k = 0; k < NW / 4; ++k) {
+            const u32x4 v = __builtin_nontemporal_load(g4 + k);
+            w[4 * k] = v.x;
+            w[4 * k + 1] = v.y;
+            w[4 * k + 2] = v.z;
+            w[4 * k + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            w[k] = g[k];
+    }
+}
+
+// The step pipeline: while step s is decoded and contracted, the stream words
+// of step s + 1 and the U values of the next step to stage are in flight.
+// With two B^T U buffers (kMrhsBuffers), B^T U of step s + 1 is staged in the
+// other buffer during step s, so one workgroup barrier per step suffices: it
+// orders the contraction of step s (reading buffer s & 1) before the staging
+// of step s + 2 (writing it again), and the staging of step s + 1 before its
+// contraction.  FP32 U with more than 32 right-hand sides keeps one buffer
+// (two would leave LDS for only one workgroup per CU): a barrier before its
+// contraction and one after.
+template <bool BF16U, int NT>
+constexpr int kMrhsBuffers = (BF16U || NT <= 2) ? 2 : 1;
+
 template <int NW, bool BF16U, int NT>
 __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __restrict__ stream,
                                                             const void* __restrict__ Uv, uint32_t ldu, uint32_t k,
@@ -514,13 +616,14 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                                                             uint32_t nslab, uint32_t cols, uint32_t nrows_out)
 {
     using UT = MrhsUt<NT>;
+    constexpr int kUtWords = BF16U ? UT::kBf16Words : UT::kF32Words;
     __shared__ uint32_t lds[kMrhsThreads * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
-    __shared__ float atile[kMrhsWaves][16 * kATileStride];
-    __shared__ uint32_t utw[BF16U ? UT::kBf16Words : UT::kF32Words];
+    __shared__ __align__(16) float atile[kMrhsWaves][16 * kATileStride];
+    constexpr int NB = kMrhsBuffers<BF16U, NT>;
+    __shared__ __align__(16) uint32_t utw[NB][kUtWords];
     uint32_t* row = lds + threadIdx.x;
     clear_pad<NW, kMrhsThreads>(row);
-    load_section_table<kMrhsThreads>(tab);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
@@ -528,9 +631,27 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
     const uint32_t bc0 = slab * slab_bc;
     const uint32_t bc1 = bc0 + slab_bc < nbc ? bc0 + slab_bc : nbc;
     const int t = lane >> 4, c = lane & 15; // this lane's block in the wave's 4 x 16 step tile
+    const uint32_t bi = bw + t;
     float* at = atile[wave];
-    float* utf = reinterpret_cast<float*>(utw);
-    uint16_t* utb = reinterpret_cast<uint16_t*>(utw);
+
+    // prologue: B^T U of step 0 staged, the U values of step 1 and the
+    // block words of step 0 in flight
+    float4 uv[kMrhsItems<NT>];
+    mrhs_load_u<BF16U, NT>(Uv, ldu, k, cols, bc0, bc1, uv);
+    load_section_table<kMrhsThreads>(tab);
+    mrhs_stage_u<BF16U, NT>(utw[0], uv);
+    mrhs_load_u<BF16U, NT>(Uv, ldu, k, cols, bc0 + 16, bc1, uv);
+    uint32_t w[NW];
+    {
+        const bool valid = bi < bi_end && bc0 + c < bc1;
+        if (valid)
+            load_block_words<NW>(stream + ((uint64_t)bi * nbc + bc0 + c) * NW, w);
+        else
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+                w[q] = 0u; // decodes as a zero block
+    }
+    __syncthreads();
 
     mf32x4 acc[NT];
     double sum[NT][4];
@@ -540,72 +661,61 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
         for (int j = 0; j < 4; ++j)
             sum[n][j] = 0.0;
 
-    for (uint32_t cb = bc0; cb < bc1; cb += 16) {
-        __syncthreads(); // the previous step's contraction is done with the staged slice
-        // ---- stage B^T U: item i = (right-hand side, block column), block
-        // columns fastest so that the loads of a wave are contiguous
-        for (int i = threadIdx.x; i < 16 * NT * 16; i += kMrhsThreads) {
-            const uint32_t rhs = (uint32_t)i >> 4, bcol = (uint32_t)i & 15u;
-            float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f;
-            if (rhs < k && cb + bcol < bc1) {
-                // zero past the last column (the partial last block column)
-                const uint32_t j = 4 * (cb + bcol), nv = cols - j < 4u ? cols - j : 4u;
-                const uint64_t o = (uint64_t)rhs * ldu + j;
-                if constexpr (BF16U) {
-                    const uint16_t* U = static_cast<const uint16_t*>(Uv) + o;
-                    u0 = bf16_to_float(U[0]);
-                    u1 = nv > 1 ? bf16_to_float(U[1]) : 0.f;
-                    u2 = nv > 2 ? bf16_to_float(U[2]) : 0.f;
-                    u3 = nv > 3 ? bf16_to_float(U[3]) : 0.f;
-                } else {
-                    const float* U = static_cast<const float*>(Uv) + o;
-                    u0 = U[0];
-                    u1 = nv > 1 ? U[1] : 0.f;
-                    u2 = nv > 2 ? U[2] : 0.f;
-                    u3 = nv > 3 ? U[3] : 0.f;
-                }
+    uint32_t sb = 0; // staging buffer of the current step
+    for (uint32_t cb = bc0; cb < bc1; cb += 16, sb ^= NB - 1) {
+        if constexpr (NB == 1) {
+            // the previous step's contraction is done (barrier at its end):
+            // stage this step's B^T U (step 0: staged before the loop)
+            if (cb != bc0) {
+                mrhs_stage_u<BF16U, NT>(utw[0], uv);
+                mrhs_load_u<BF16U, NT>(Uv, ldu, k, cols, cb + 16, bc1, uv);
             }
-            float ut[4];
-            lin_bt_u<float>(u0, u1, u2, u3, ut);
-            if constexpr (BF16U) {
+        }
+        // ---- this step's block: its words to the lane's LDS row; the next
+        // step's words in flight meanwhile
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    utb[rhs * UT::kBf16Stride + 4 * bcol + m] = to_bf16_rne(ut[m]);
-            } else {
+        for (int q = 0; q < NW; ++q)
+            row[q * kMrhsThreads] = w[q];
+        const uint32_t w0 = w[0];
+        {
+            const bool valid = bi < bi_end && cb + 16 + c < bc1;
+            if (valid)
+                load_block_words<NW>(stream + ((uint64_t)bi * nbc + cb + 16 + c) * NW, w);
+            else
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    utf[(m * 16 + bcol) * UT::kF32Stride + rhs] = ut[m];
-            }
+                for (int q = 0; q < NW; ++q)
+                    w[q] = 0u;
         }
         // ---- decode one block per lane: scaled coefficients (registers)
-        const uint32_t bi = bw + t, bj = cb + c;
-        const bool valid = bi < bi_end && bj < bc1;
-        uint32_t w[NW];
-        if (valid) {
-            stage_block<NW, kMrhsThreads>(row, stream + ((uint64_t)bi * nbc + bj) * NW, w);
-        } else {
-#pragma unroll
-            for (int q = 0; q < NW; ++q)
-                row[q * kMrhsThreads] = 0u; // decodes as a zero block
-            w[0] = 0u;
-        }
         int emax;
         uint32_t cf[16];
         bool cut;
-        decode_block_coeffs<NW, kMrhsThreads>(row, tab, w[0], emax, cf, cut);
+        decode_block_coeffs<NW, kMrhsThreads>(row, tab, w0, emax, cf, cut);
         float sc[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v)
             sc[v] = __builtin_ldexpf((float)(int32_t)cf[v], emax - 30);
         if (__any(cut) && cut) // rare: the exact lift (see exact_block_coeffs)
             exact_block_coeffs(cf, emax, sc);
-        __syncthreads(); // staged slice complete
+        // ---- B^T U of the next step into the other buffer; the U values of
+        // the step after it in flight
+        if constexpr (NB == 2) {
+            if (cb + 16 < bc1) {
+                mrhs_stage_u<BF16U, NT>(utw[sb ^ 1u], uv);
+                mrhs_load_u<BF16U, NT>(Uv, ldu, k, cols, cb + 32, bc1, uv);
+            }
+        } else {
+            __syncthreads(); // this step's slice is staged
+        }
+        const float* utf = reinterpret_cast<const float*>(utw[sb]);
+        const uint16_t* utb = reinterpret_cast<const uint16_t*>(utw[sb]);
 #pragma unroll
         for (int n = 0; n < NT; ++n)
             acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
-        // ---- four quarters of 4 block columns: write, then contract
+        // ---- FP32 U: four quarters of 4 block columns, each written to the
+        // wave's tile and then contracted (K = 4 per MFMA)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < (BF16U ? 0 : 4); ++q) {
             // the tile is the wave's own: lanes read what other lanes of the
             // wave wrote, so each hand-over is a wave-scope release/acquire
             // (no workgroup barrier is needed)
@@ -617,7 +727,7 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                         f32x4{sc[4 * r], sc[4 * r + 1], sc[4 * r + 2], sc[4 * r + 3]};
             }
             wave_sync_lds();
-            if constexpr (!BF16U) {
+            {
 #pragma unroll
                 for (int kq = 0; kq < 4; ++kq) {
                     const int m = lane >> 4;     // column 4 kb + m of the step, kb = 4 q + kq
@@ -627,19 +737,38 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                     for (int n = 0; n < NT; ++n)
                         acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ub[16 * n], acc[n], 0, 0, 0);
                 }
-            } else {
-                // K = 16: lane holds A[i][4(lane/16) .. +3], one block column
-                const f32x4 av = *reinterpret_cast<const f32x4*>(at + (lane & 15) * kATileStride + 4 * (lane >> 4));
-                mbf16x4 a;
-                a[0] = (short)to_bf16_rne(av.x);
-                a[1] = (short)to_bf16_rne(av.y);
-                a[2] = (short)to_bf16_rne(av.z);
-                a[3] = (short)to_bf16_rne(av.w);
+            }
+        }
+        if constexpr (BF16U) {
+            // ---- two halves of 8 block columns (K = 32): the lanes of a half
+            // write their blocks' coefficients, rounded to BF16, to the tile
+            // (row 4t + r, columns 4 (c % 8) .. + 3); lane l then holds
+            // A[l % 16][8 (l / 16) .. + 7] (two block columns) and
+            // B[8 (l / 16) .. + 7][l % 16]
+            uint16_t* at16 = reinterpret_cast<uint16_t*>(at);
+            uint32_t pk[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v)
+                pk[v] = (uint32_t)to_bf16_rne(sc[2 * v]) | (uint32_t)to_bf16_rne(sc[2 * v + 1]) << 16;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                wave_sync_lds();
+                if ((c >> 3) == h) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        *reinterpret_cast<u32x2*>(at16 + (4 * t + r) * kATile16Stride + 4 * (c & 7)) =
+                            u32x2{pk[2 * r], pk[2 * r + 1]};
+                }
+                wave_sync_lds();
+                const u32x4 av =
+                    *reinterpret_cast<const u32x4*>(at16 + (lane & 15) * kATile16Stride + 8 * (lane >> 4));
+                const mbf16x8 a = __builtin_bit_cast(mbf16x8, av);
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
-                    const mbf16x4 b = *reinterpret_cast<const mbf16x4*>(
-                        utb + (16 * n + (lane & 15)) * UT::kBf16Stride + 16 * q + 4 * (lane >> 4));
-                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[n], 0, 0, 0);
+                    const u32x4 bv = *reinterpret_cast<const u32x4*>(
+                        utb + (16 * n + (lane & 15)) * UT::kBf16Stride + 32 * h + 8 * (lane >> 4));
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(mbf16x8, bv), acc[n], 0,
+                                                                     0, 0);
                 }
             }
         }
@@ -648,6 +777,7 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 sum[n][j] += (double)acc[n][j];
+        __syncthreads(); // this step's slice is read (and, two buffers: the next one staged)
     }
 
     // ---- B on each block row's four coefficient-row sums; D[i][j]: lane
