@@ -225,6 +225,35 @@ __device__ __forceinline__ uint32_t sec_lookup(const uint32_t* tab, uint32_t ns,
 #endif
 }
 
+// a + (b & 0xFF).  On the GPU one SDWA add reads b's low byte.
+__device__ __forceinline__ uint32_t add_byte0(uint32_t a, uint32_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t r;
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:DWORD"
+        : "=v"(r)
+        : "v"(b), "v"(a));
+    return r;
+#else
+    return a + (b & 0xFFu);
+#endif
+}
+
+// tab[min(i + j, kSecDone)] (tab in LDS).  On the GPU the byte offset is one
+// v_add_lshl and the clamp one v_min on it; written plainly the compiler adds,
+// clamps and then scales.
+__device__ __forceinline__ uint32_t sec_lookup_clamped(const uint32_t* tab, uint32_t i, uint32_t j)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t off;
+    asm("v_add_lshl_u32 %0, %1, %2, 2" : "=v"(off) : "v"(i), "v"(j));
+    off = __builtin_elementwise_min(off, 4u * (uint32_t)kSecDone);
+    return *(const uint32_t*)((const char*)tab + off);
+#else
+    return tab[__builtin_elementwise_min(i + j, (uint32_t)kSecDone)];
+#endif
+}
+
 __host__ __device__ __forceinline__ constexpr uint32_t ent_used(uint32_t e) { return (e >> 16) & 0xFFu; }
 __host__ __device__ __forceinline__ constexpr uint32_t ent_adv(uint32_t e) { return (e >> 25) & 15u; }
 __host__ __device__ __forceinline__ constexpr bool ent_open(uint32_t e) { return (int32_t)e >= 0; }
@@ -286,8 +315,50 @@ struct SectionTable {
 
 // A[q] starts as plane q | plane q+16 << 16 with every odd plane
 // complemented: the transpose then yields n ^ 0xAAAAAAAA for each negabinary
-// coefficient n, the first half of the conversion to two's complement.
+// coefficient n, the first half of the conversion to two's complement.  (The
+// variable-rate decoder keeps this form; the fixed-rate one stores the planes
+// as they are and converts after the transpose.)
 __host__ __device__ constexpr uint32_t kOddPlanes(int q) { return (q & 1) ? 0xFFFFFFFFu : 0u; }
+
+// Negabinary n -> two's complement (n ^ 0xAAAAAAAA) - 0xAAAAAAAA, modulo
+// 2^32: one v_xad on the GPU.
+__device__ __forceinline__ uint32_t nega_to_int(uint32_t n)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t r;
+    // one SGPR operand at most (constant bus): the addend comes in a VGPR
+    asm("v_xad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(n), "s"(kNega), "v"(0u - kNega));
+    return r;
+#else
+    return (n ^ kNega) - kNega;
+#endif
+}
+
+// Plane P's word, (acc & 0xFFFF) | xv (disjoint bits), into A: plane P >= 16
+// as the high half of A[P - 16] (low half zero); plane P < 16 as the low half
+// of A[P], whose high half already holds plane P + 16.  One instruction each:
+// an SDWA or writing one half of its destination (the other half zeroed, or
+// kept).
+template <int P>
+__device__ __forceinline__ void store_plane(uint32_t (&A)[16], uint32_t acc, uint32_t xv)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (P >= 16)
+        asm("v_or_b32_sdwa %0, %1, %2 dst_sel:WORD_1 dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:DWORD"
+            : "=v"(A[P - 16])
+            : "v"(acc), "v"(xv));
+    else
+        asm("v_or_b32_sdwa %0, %1, %2 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:DWORD src1_sel:DWORD"
+            : "+v"(A[P])
+            : "v"(acc), "v"(xv));
+#else
+    const uint32_t x = (acc & 0xFFFFu) | xv;
+    if constexpr (P >= 16)
+        A[P - 16] = x << 16;
+    else
+        A[P] = (A[P] & 0xFFFF0000u) | x;
+#endif
+}
 
 // One bit plane of the embedded code (plane P, decoded in lockstep by all
 // lanes of the wave; P is a template argument so A[] is indexed at compile
@@ -327,8 +398,8 @@ __device__ __forceinline__ uint64_t decode_plane(const uint32_t* lw, const uint3
         do {
             q = word_of(at);
             const uint32_t bits = funnel(lw[(q + 1) * STRIDE], lw[q * STRIDE], at & 31u);
-            const uint32_t idx = ns + ent_next(acc) + (bits & 0xFFu); // ended: >= kSecDone
-            acc = (acc & 0xFFFFu) | tab[__builtin_elementwise_min(idx, (uint32_t)kSecDone)];
+            // ended: the index is past kSecDone and clamps onto it
+            acc = (acc & 0xFFFFu) | sec_lookup_clamped(tab, add_byte0(ns, bits), ent_next(acc));
             at += ent_used(acc);
             ns += ent_adv(acc) * (uint32_t)kSecRow;
         } while (__any(ent_open(acc)));
@@ -346,12 +417,7 @@ __device__ __forceinline__ uint64_t decode_plane(const uint32_t* lw, const uint3
         at = __builtin_elementwise_min(at, kMaxBits + 32u);
     }
     pos = at;
-    const uint32_t x = (acc & 0xFFFFu) | xv; // disjoint bit ranges
-    // plane words arrive complemented on odd planes (see decode_block_coeffs)
-    if constexpr (P >= 16)
-        A[P - 16] = (x << 16) ^ kOddPlanes(P - 16);
-    else
-        A[P] ^= x;
+    store_plane<P>(A, acc, xv);
     return past;
 }
 
@@ -374,7 +440,7 @@ __device__ __forceinline__ void decode_planes_from(const uint32_t* lw, const uin
             if constexpr (P >= 16) {
 #pragma unroll
                 for (int q = 0; q <= P - 16; ++q)
-                    A[q] = kOddPlanes(q);
+                    A[q] = 0u;
             }
             return;
         }
@@ -414,11 +480,11 @@ __device__ __forceinline__ bool decode_block_coeffs(const uint32_t* lw, const ui
     cut = nz;       // a zero block is exact; others until plane kSafeCutPlane is read
     decode_planes_from<NW, STRIDE, 31>(lw, tab, pos, ns, A, cut, __ballot(!nz));
     transpose_planes(A);
-    // negabinary -> two's complement (the XOR came with the planes), undo
-    // the sequency order
+    // negabinary -> two's complement (one v_xad each), undo the sequency
+    // order
 #pragma unroll
     for (int s = 0; s < 16; ++s)
-        cf[order_of(s)] = A[s] - kNega;
+        cf[order_of(s)] = nega_to_int(A[s]);
     return nz;
 }
 
