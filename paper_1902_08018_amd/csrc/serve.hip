@@ -6,30 +6,38 @@
 // Here many such dose-vector requests, against several resident matrices of
 // different sizes, share one GPU:
 //
-//   submit      any thread; the request is validated, stamped and queued
-//   admission   each matrix gets device slots (U, Y and the FP64 slab
-//               partials of one batch) carved out of the context's HBM
-//               budget: one on first use, a second (one batch runs while the
-//               next is staged) if the budget still holds the first slots of
-//               every other resident matrix; a batch waits for a free slot;
-//               a request that can never fit is rejected at submit
-//   batching    continuous: whenever a slot of a matrix is free, all queued
-//               requests of that matrix (FIFO, up to 64 right-hand sides) form
-//               one batch; requests that arrive while it runs form the next
-//   launch      U rows are copied into the slot, the slot's pre-instantiated
-//               hipGraph for the batch's k-bucket (1, 2, 4, 8, 16, 32, 64) is
-//               replayed on the matrix's own stream, Y rows are copied back,
-//               an event is recorded.  A graph is a chain of fused
-//               decode+GEMV launches over consecutive row chunks of at most
-//               ctx->serve_chunk_values values: a long pass over a big matrix
-//               does not hold every compute unit until it ends, and batches
-//               of other matrices start between its chunks
-//   completion  the worker polls the events; a finished batch stamps t_done
-//               on its requests and frees the slot
+//   submit      any thread; the request is validated (host buffers must be
+//               page-locked), stamped and queued.  The first request for a
+//               matrix sets up its slot outside the loop's lock
+//   slot        per matrix, carved out of the context's HBM budget: U and Y
+//               for 64 right-hand-side columns, the FP64 slab partials of its
+//               plans, and one pre-instantiated hipGraph per (row chunk,
+//               k-bucket 1, 2, 4, ..., 64).  A request that can never fit is
+//               rejected at submit
+//   cyclic scan each matrix's rows are split into chunks of at most
+//               ctx->serve_chunk_values values.  The loop launches one chunk
+//               at a time, cycling through them, over every column held by a
+//               request.  A queued request joins at the next chunk launch: its
+//               U is copied into free columns, and it is complete once the
+//               scan has gone round once from there (Y copied back after its
+//               last chunk).  So a request waits at most one chunk for the
+//               pass it joins, not for a whole pass to end, and requests that
+//               arrive while others run share the same launches
+//   order       each matrix has at most two chunk launches in flight, on its
+//               own stream; the streams of different matrices run side by
+//               side, so a small matrix's pass is never queued behind a long
+//               scan of a big one.  Launches are issued in order of urgency:
+//               the earliest deadline among requests that can still meet
+//               theirs (estimated from the measured chunk time), then late
+//               work, least remaining scan first
+//   completion  the worker polls each launch's event; the requests whose last
+//               chunk it was are stamped done
 //   poll        never blocks: WH_PENDING, or the result once (then retired)
 //
-// Streams of different matrices run concurrently on the device.  All streams
-// keep the default priority.
+// Every launch of a matrix goes to that matrix's stream, so a column freed by
+// one request (its Y copy queued) is reused by the next only after that copy,
+// and the slab partials are shared by the chunks in order.  All streams keep
+// the default priority.
 #include <hip/hip_runtime.h>
 
 #include <time.h>
@@ -60,7 +68,10 @@ uint64_t now_ns()
 
 constexpr uint32_t kBuckets[] = {1, 2, 4, 8, 16, 32, 64};
 constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
-constexpr int kMaxSlotsPerMatrix = 2;
+// chunk launches of one matrix in flight on the device (the second keeps
+// its stream busy while the worker notices the first one end)
+constexpr size_t kMaxInflight = 2;
+static_assert(kMaxRhs == 64, "a slot's columns are the bits of a uint64_t");
 
 int bucket_index(uint32_t k)
 {
@@ -74,26 +85,34 @@ struct Req {
     wh_request r;
     uint64_t t_arrive = 0, t_start = 0, t_done = 0;
     wh_status status = WH_PENDING;
-    uint32_t batch_size = 0;
-    uint32_t row_off = 0; // first right-hand side of this request in its batch
+    uint32_t batch_size = 0; // requests that joined the scan at the same launch
+    uint32_t col0 = 0;       // first of its k consecutive columns in the slot
+    uint32_t left = 0;       // chunk launches still to issue for it
 };
 
-struct Slot {
-    float* U = nullptr;    // kMaxRhs x cols
-    float* Y = nullptr;    // kMaxRhs x rows
-    double* part = nullptr; // slab partials for the graphs
-    hipEvent_t done_ev = nullptr;
-    hipGraphExec_t exec[kNumBuckets] = {};
-    bool busy = false;
-    std::vector<uint64_t> batch; // tickets
+struct Launch {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    std::vector<uint64_t> done; // requests whose last chunk this launch is
 };
 
 struct MatServe {
     Matrix m{};
     hipStream_t stream = nullptr;
-    std::vector<Slot> slots;
-    std::deque<uint64_t> pending;
-    bool usable = false;
+    std::vector<std::pair<uint32_t, uint32_t>> chunks;
+    float* U = nullptr;      // kMaxRhs x cols
+    float* Y = nullptr;      // kMaxRhs x rows
+    double* part = nullptr;  // slab partials of the chunk plans
+    std::vector<hipGraphExec_t> exec; // [chunk * kNumBuckets + bucket]
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spare; // event pairs not in use
+    std::deque<Launch> inflight;
+    std::deque<uint64_t> pending; // queued, not yet in the scan
+    std::vector<uint64_t> active; // in the scan, chunks left to launch
+    uint64_t used = 0;            // columns held by active requests
+    uint32_t next_chunk = 0;
+    double chunk_ms = 0.0;        // running estimate of one chunk launch
+    size_t bytes = 0;             // charged to the budget
+    bool building = false, usable = false;
+    wh_status build_status = WH_OK;
 };
 
 } // namespace
@@ -124,218 +143,226 @@ std::vector<std::pair<uint32_t, uint32_t>> serve_chunks(const Matrix& m, uint64_
     return out;
 }
 
-// Device memory of one batch slot: U and Y for kMaxRhs vectors, and the FP64
-// slab partials the k = 1 or multi-RHS plans of its chunks need (none when
-// every plan has one slab; the chunks run in stream order and share them).
-// This is what a slot charges against the context's HBM budget.
+// Workspace (doubles) the k = 1 or multi-RHS plans of the chunks need: FP64
+// slab partials, and B^T U for the multi-RHS kernel (the chunks run in
+// stream order and share it).
 size_t slot_partials(const Matrix& m, const wh_ctx* ctx)
 {
     size_t n = 0;
     for (const auto& c : serve_chunks(m, ctx->serve_chunk_values)) {
         const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
-        const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
         if (gp.nslab > 1)
             n = std::max(n, (size_t)gp.nslab * gp.part_rows());
-        if (mp.nslab > 1)
-            n = std::max(n, (size_t)mp.nslab * kMaxRhs * mp.part_rows());
+        for (uint32_t k = 16; k <= kMaxRhs; k += 16) { // the plan depends on k's group count
+            const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k);
+            n = std::max(n, mrhs_workspace(mp, k, false).total);
+        }
     }
     return n;
 }
 
+// What a matrix's slot charges against the context's HBM budget.
 size_t slot_bytes(const Matrix& m, const wh_ctx* ctx)
 {
     return (size_t)kMaxRhs * ((size_t)m.desc.cols + m.desc.rows) * sizeof(float) +
            slot_partials(m, ctx) * sizeof(double);
 }
 
-// Capture one graph per k-bucket for a slot: a single fused launch.
-wh_status build_slot(Server* sv, MatServe& ms, Slot& sl)
+// A chunk launch's time before any is measured: about a microsecond per
+// million matrix values (the fused decoder's rate on a full device).
+double model_chunk_ms(const Matrix& m, const std::pair<uint32_t, uint32_t>& c)
+{
+    return 1e-9 * (double)(c.second - c.first) * (double)m.desc.cols;
+}
+
+void free_slot(MatServe& ms)
+{
+    for (hipGraphExec_t g : ms.exec)
+        if (g)
+            (void)hipGraphExecDestroy(g);
+    ms.exec.clear();
+    for (auto& e : ms.spare) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    ms.spare.clear();
+    for (Launch& l : ms.inflight) {
+        (void)hipEventDestroy(l.t0);
+        (void)hipEventDestroy(l.t1);
+    }
+    ms.inflight.clear();
+    if (ms.U)
+        (void)hipFree(ms.U);
+    if (ms.Y)
+        (void)hipFree(ms.Y);
+    if (ms.part)
+        (void)hipFree(ms.part);
+    ms.U = ms.Y = nullptr;
+    ms.part = nullptr;
+    if (ms.stream)
+        (void)hipStreamDestroy(ms.stream);
+    ms.stream = nullptr;
+}
+
+// Device memory, streams, events and graphs of a matrix's slot.  Runs
+// without the server lock (the worker does not touch a slot being built).
+wh_status build_slot(wh_ctx* ctx, MatServe& ms)
 {
     const Matrix& m = ms.m;
-    if (hipMalloc(&sl.U, (size_t)kMaxRhs * m.desc.cols * sizeof(float)) != hipSuccess ||
-        hipMalloc(&sl.Y, (size_t)kMaxRhs * m.desc.rows * sizeof(float)) != hipSuccess)
-        return WH_ERR_NOMEM;
-    // the rows the graphs may read before a batch writes them must be finite
-    if (hipMemset(sl.U, 0, (size_t)kMaxRhs * m.desc.cols * sizeof(float)) != hipSuccess)
+    if (hipStreamCreateWithFlags(&ms.stream, hipStreamNonBlocking) != hipSuccess)
         return WH_ERR_DEVICE;
-    const size_t part_n = slot_partials(m, sv->ctx);
-    const auto chunks = serve_chunks(m, sv->ctx->serve_chunk_values);
-    if (part_n && hipMalloc(&sl.part, part_n * sizeof(double)) != hipSuccess)
+    if (hipMalloc(&ms.U, (size_t)kMaxRhs * m.desc.cols * sizeof(float)) != hipSuccess ||
+        hipMalloc(&ms.Y, (size_t)kMaxRhs * m.desc.rows * sizeof(float)) != hipSuccess)
         return WH_ERR_NOMEM;
-    if (hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess)
+    // columns the graphs read before a request writes them must be finite
+    if (hipMemset(ms.U, 0, (size_t)kMaxRhs * m.desc.cols * sizeof(float)) != hipSuccess)
         return WH_ERR_DEVICE;
-    for (int b = 0; b < kNumBuckets; ++b) {
-        const uint32_t k = kBuckets[b];
-        hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(ms.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    const size_t part_n = slot_partials(m, ctx);
+    if (part_n && hipMalloc(&ms.part, part_n * sizeof(double)) != hipSuccess)
+        return WH_ERR_NOMEM;
+    ms.chunks = serve_chunks(m, ctx->serve_chunk_values);
+    for (size_t i = 0; i < kMaxInflight + 1; ++i) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
             return WH_ERR_DEVICE;
-        hipError_t e = hipSuccess;
-        for (const auto& c : chunks) {
-            if (k == 1) {
-                const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, c.first, c.second, sv->ctx->num_cus);
-                e = whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, sl.U, sl.Y + c.first, sl.part, ms.stream);
-            } else {
-                const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, sv->ctx->num_cus);
-                e = whz_mrhs(m.desc.rate, mp, false, m.dptr, sl.U, m.desc.cols, k, sl.Y + c.first, m.desc.rows,
-                             sl.part, ms.stream);
-            }
-            if (e != hipSuccess)
-                break;
-        }
-        hipError_t e2 = hipStreamEndCapture(ms.stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess || !g)
-            return WH_ERR_DEVICE;
-        e = hipGraphInstantiate(&sl.exec[b], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess)
-            return WH_ERR_DEVICE;
+        ms.spare.emplace_back(a, b);
     }
+    ms.exec.assign(ms.chunks.size() * kNumBuckets, nullptr);
+    double model = 0.0;
+    for (size_t ci = 0; ci < ms.chunks.size(); ++ci) {
+        const auto& c = ms.chunks[ci];
+        model = std::max(model, model_chunk_ms(m, c));
+        for (int b = 0; b < kNumBuckets; ++b) {
+            const uint32_t k = kBuckets[b];
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(ms.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return WH_ERR_DEVICE;
+            hipError_t e;
+            if (k == 1) {
+                const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
+                e = whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, ms.U, ms.Y + c.first, ms.part, ms.stream);
+            } else {
+                const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k);
+                e = whz_mrhs(m.desc.rate, mp, false, m.dptr, ms.U, m.desc.cols, k, ms.Y + c.first, m.desc.rows,
+                             ms.part, ms.stream);
+            }
+            const hipError_t e2 = hipStreamEndCapture(ms.stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess || !g)
+                return WH_ERR_DEVICE;
+            e = hipGraphInstantiate(&ms.exec[ci * kNumBuckets + b], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess)
+                return WH_ERR_DEVICE;
+        }
+    }
+    ms.chunk_ms = model;
     return WH_OK;
 }
 
-void free_slot(Slot& sl)
+// The first of k consecutive free columns, or -1.
+int free_run(uint64_t used, uint32_t k)
 {
-    for (int b = 0; b < kNumBuckets; ++b)
-        if (sl.exec[b])
-            (void)hipGraphExecDestroy(sl.exec[b]);
-    if (sl.done_ev)
-        (void)hipEventDestroy(sl.done_ev);
-    if (sl.U)
-        (void)hipFree(sl.U);
-    if (sl.Y)
-        (void)hipFree(sl.Y);
-    if (sl.part)
-        (void)hipFree(sl.part);
-    sl = Slot{};
+    const uint64_t want = k >= 64 ? ~0ull : ((1ull << k) - 1);
+    for (uint32_t c = 0; c + k <= 64; ++c)
+        if (((used >> c) & want) == 0)
+            return (int)c;
+    return -1;
 }
 
-// Called with sv->mu held (takes ctx->mu).  The first slots still owed to
-// the context's resident compressed matrices that have none yet (each one
-// that fits the budget on its own).
-size_t first_slot_reserve(Server* sv)
-{
-    size_t r = 0;
-    std::lock_guard<std::mutex> lk(sv->ctx->mu);
-    for (const auto& kv : sv->ctx->mats) {
-        if (kv.second.desc.fmt != WH_FMT_ZFP_FIXED_RATE)
-            continue;
-        auto it = sv->mats.find(kv.first);
-        if (it != sv->mats.end() && !it->second.slots.empty())
-            continue;
-        const size_t b = slot_bytes(kv.second, sv->ctx);
-        if (b <= sv->ctx->budget)
-            r += b;
-    }
-    return r;
-}
+uint64_t run_mask(uint32_t c0, uint32_t k) { return (k >= 64 ? ~0ull : ((1ull << k) - 1)) << c0; }
 
-// Called with sv->mu held.  Adds a slot to a matrix if the budget has room
-// for it; the slot's bytes are charged only when it is built.  A second slot
-// must leave room for the first slots of the resident matrices that have
-// none yet, so a matrix whose first request comes late is not starved.
-bool add_slot(Server* sv, MatServe& ms)
-{
-    const size_t per = slot_bytes(ms.m, sv->ctx);
-    const size_t reserve = ms.slots.empty() ? 0 : first_slot_reserve(sv);
-    if ((int)ms.slots.size() >= kMaxSlotsPerMatrix || sv->arena_used + per + reserve > sv->ctx->budget)
-        return false;
-    Slot sl;
-    if (build_slot(sv, ms, sl) != WH_OK) {
-        free_slot(sl);
-        return false;
-    }
-    sv->arena_used += per;
-    ms.slots.push_back(std::move(sl));
-    return true;
-}
-
-// Called with sv->mu held.  Sets up serving state for a matrix on first use:
-// one slot now; a second one later, when a batch of this matrix has to wait
-// and the budget has room beyond the first slots owed to the other resident
-// matrices.
-MatServe* serve_matrix(Server* sv, wh_mat mat, wh_status& st)
-{
-    auto it = sv->mats.find(mat);
-    if (it != sv->mats.end()) {
-        st = it->second.usable ? WH_OK : WH_ERR_BUDGET;
-        return it->second.usable ? &it->second : nullptr;
-    }
-    Matrix m;
-    {
-        std::lock_guard<std::mutex> lk(sv->ctx->mu);
-        Matrix* p = find_matrix(sv->ctx, mat);
-        if (!p) {
-            st = WH_ERR_NOT_FOUND;
-            return nullptr;
-        }
-        m = *p;
-    }
-    if (m.desc.fmt != WH_FMT_ZFP_FIXED_RATE) {
-        st = WH_ERR_FORMAT;
-        return nullptr;
-    }
-    if (slot_bytes(m, sv->ctx) + sv->arena_used > sv->ctx->budget) {
-        st = WH_ERR_BUDGET; // cannot hold even one batch of this matrix
-        return nullptr;
-    }
-    MatServe& ms = sv->mats[mat];
-    ms.m = m;
-    if (hipStreamCreateWithFlags(&ms.stream, hipStreamNonBlocking) != hipSuccess) {
-        st = WH_ERR_DEVICE;
-        return nullptr;
-    }
-    if (!add_slot(sv, ms)) {
-        st = WH_ERR_NOMEM;
-        return nullptr;
-    }
-    ms.usable = true;
-    st = WH_OK;
-    return &ms;
-}
-
-// Issue one batch on a free slot.  Called with sv->mu held (the HIP calls
-// below are asynchronous and short).
-wh_status launch_batch(Server* sv, MatServe& ms, Slot& sl)
+// Called with sv->mu held.  Issues the next chunk launch of a matrix: queued
+// requests join (FIFO, while columns last), the chunk's graph runs over every
+// held column, and the requests whose last chunk this was get their Y copied
+// back.  The HIP calls are asynchronous: copies from and to page-locked or
+// device memory only.
+wh_status issue_chunk(Server* sv, MatServe& ms)
 {
     const Matrix& m = ms.m;
-    uint32_t ktot = 0;
-    sl.batch.clear();
+    const size_t cols = m.desc.cols, rows = m.desc.rows;
+    const uint32_t nchunks = (uint32_t)ms.chunks.size();
+    const uint64_t t0 = now_ns();
+    std::vector<uint64_t> joined;
     while (!ms.pending.empty()) {
         Req& r = sv->reqs[ms.pending.front()];
-        if (ktot + r.r.k > kMaxRhs)
+        const int c0 = free_run(ms.used, r.r.k);
+        if (c0 < 0)
             break;
-        r.row_off = ktot;
-        ktot += r.r.k;
-        sl.batch.push_back(ms.pending.front());
+        r.col0 = (uint32_t)c0;
+        r.left = nchunks;
+        r.t_start = t0;
+        ms.used |= run_mask(r.col0, r.r.k);
+        const hipMemcpyKind kind = r.r.u_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        if (hipMemcpyAsync(ms.U + (size_t)r.col0 * cols, r.r.U, (size_t)r.r.k * cols * sizeof(float), kind,
+                           ms.stream) != hipSuccess)
+            return WH_ERR_DEVICE;
+        joined.push_back(ms.pending.front());
+        ms.active.push_back(ms.pending.front());
         ms.pending.pop_front();
     }
-    if (sl.batch.empty())
+    for (uint64_t t : joined)
+        sv->reqs[t].batch_size = (uint32_t)joined.size();
+    if (ms.active.empty())
         return WH_OK;
-    const int b = bucket_index(ktot);
-    const uint64_t t0 = now_ns();
-    const size_t cols = m.desc.cols, rows = m.desc.rows;
-    for (uint64_t t : sl.batch) {
-        Req& r = sv->reqs[t];
-        r.t_start = t0;
-        r.batch_size = (uint32_t)sl.batch.size();
-        const hipMemcpyKind kind = r.r.u_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-        if (hipMemcpyAsync(sl.U + (size_t)r.row_off * cols, r.r.U, (size_t)r.r.k * cols * sizeof(float), kind,
-                           ms.stream) != hipSuccess)
-            return WH_ERR_DEVICE;
-    }
-    if (hipGraphLaunch(sl.exec[b], ms.stream) != hipSuccess)
+    const uint32_t kmax = 64u - (uint32_t)__builtin_clzll(ms.used);
+    const int b = bucket_index(kmax);
+    const uint32_t c = ms.next_chunk;
+    Launch l;
+    l.t0 = ms.spare.back().first;
+    l.t1 = ms.spare.back().second;
+    ms.spare.pop_back();
+    if (hipEventRecord(l.t0, ms.stream) != hipSuccess ||
+        hipGraphLaunch(ms.exec[(size_t)c * kNumBuckets + b], ms.stream) != hipSuccess)
         return WH_ERR_DEVICE;
-    for (uint64_t t : sl.batch) {
-        Req& r = sv->reqs[t];
+    ms.next_chunk = (c + 1) % nchunks;
+    size_t keep = 0;
+    for (size_t i = 0; i < ms.active.size(); ++i) {
+        Req& r = sv->reqs[ms.active[i]];
+        if (--r.left > 0) {
+            ms.active[keep++] = ms.active[i];
+            continue;
+        }
         const hipMemcpyKind kind = r.r.y_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        if (hipMemcpyAsync(r.r.Y, sl.Y + (size_t)r.row_off * rows, (size_t)r.r.k * rows * sizeof(float), kind,
+        if (hipMemcpyAsync(r.r.Y, ms.Y + (size_t)r.col0 * rows, (size_t)r.r.k * rows * sizeof(float), kind,
                            ms.stream) != hipSuccess)
             return WH_ERR_DEVICE;
+        ms.used &= ~run_mask(r.col0, r.r.k); // later users of these columns come after this copy
+        l.done.push_back(ms.active[i]);
     }
-    if (hipEventRecord(sl.done_ev, ms.stream) != hipSuccess)
+    ms.active.resize(keep);
+    if (hipEventRecord(l.t1, ms.stream) != hipSuccess)
         return WH_ERR_DEVICE;
-    sl.busy = true;
+    ms.inflight.push_back(std::move(l));
     return WH_OK;
+}
+
+// Called with sv->mu held.  How urgent a matrix's next chunk launch is: the
+// earliest deadline among its requests that can still meet theirs
+// (`feasible`), and the least remaining scan time of its other requests
+// (`late`, ns).  Returns false if it has nothing to launch.
+bool urgency(Server* sv, const MatServe& ms, uint64_t now, uint64_t& feasible, uint64_t& late)
+{
+    feasible = late = UINT64_MAX;
+    const double chunk_ns = ms.chunk_ms * 1e6;
+    auto consider = [&](const Req& r, uint32_t left) {
+        const uint64_t due = r.r.deadline_ns ? r.t_arrive + r.r.deadline_ns : UINT64_MAX;
+        const double rest = left * chunk_ns;
+        if ((double)now + rest <= (double)due)
+            feasible = std::min(feasible, due);
+        else
+            late = std::min(late, (uint64_t)rest);
+    };
+    for (uint64_t t : ms.active)
+        consider(sv->reqs.at(t), sv->reqs.at(t).left);
+    bool joinable = false;
+    if (!ms.pending.empty()) {
+        const Req& head = sv->reqs.at(ms.pending.front());
+        if (free_run(ms.used, head.r.k) >= 0) {
+            joinable = true;
+            consider(head, (uint32_t)ms.chunks.size());
+        }
+    }
+    return !ms.active.empty() || joinable;
 }
 
 void fail_all(Server* sv, wh_status st)
@@ -344,8 +371,10 @@ void fail_all(Server* sv, wh_status st)
     for (auto& kv : sv->reqs)
         if (kv.second.status == WH_PENDING)
             kv.second.status = st;
-    for (auto& mv : sv->mats)
+    for (auto& mv : sv->mats) {
         mv.second.pending.clear();
+        mv.second.active.clear();
+    }
 }
 
 void worker_main(Server* sv)
@@ -353,65 +382,65 @@ void worker_main(Server* sv)
     (void)hipSetDevice(sv->ctx->device);
     std::unique_lock<std::mutex> lk(sv->mu);
     while (!sv->stop) {
-        bool busy_any = false;
-        // completion
+        // completion, in launch order per matrix
+        size_t inflight = 0;
         for (auto& mv : sv->mats) {
-            for (Slot& sl : mv.second.slots) {
-                if (!sl.busy)
-                    continue;
-                hipError_t q = hipEventQuery(sl.done_ev);
-                if (q == hipErrorNotReady) {
-                    busy_any = true;
-                    continue;
-                }
+            MatServe& ms = mv.second;
+            while (!ms.inflight.empty()) {
+                Launch& l = ms.inflight.front();
+                const hipError_t q = hipEventQuery(l.t1);
+                if (q == hipErrorNotReady)
+                    break;
                 const uint64_t t = now_ns();
                 const wh_status st = q == hipSuccess ? WH_OK : WH_ERR_DEVICE;
-                for (uint64_t tk : sl.batch) {
+                for (uint64_t tk : l.done) {
                     Req& r = sv->reqs[tk];
                     r.t_done = t;
                     r.status = st;
                 }
-                sl.batch.clear();
-                sl.busy = false;
+                float ms_el = 0.f;
+                if (st == WH_OK && hipEventElapsedTime(&ms_el, l.t0, l.t1) == hipSuccess && ms_el > 0.f)
+                    ms.chunk_ms = 0.8 * ms.chunk_ms + 0.2 * (double)ms_el;
+                ms.spare.emplace_back(l.t0, l.t1);
+                ms.inflight.pop_front();
                 if (st != WH_OK) {
                     sv->ctx->failed.store(true);
                     fail_all(sv, st);
                 }
             }
+            inflight += ms.inflight.size();
         }
-        // dispatch: every free slot of a matrix with queued requests
-        if (sv->sticky == WH_OK) {
+        // dispatch: earliest feasible deadline first, then late work with
+        // the least scan left; each matrix up to kMaxInflight launches
+        while (sv->sticky == WH_OK) {
+            const uint64_t now = now_ns();
+            MatServe* pick = nullptr;
+            uint64_t best_f = UINT64_MAX, best_l = UINT64_MAX;
             for (auto& mv : sv->mats) {
                 MatServe& ms = mv.second;
-                bool all_busy = true;
-                for (Slot& sl : ms.slots) {
-                    if (ms.pending.empty())
-                        break;
-                    if (sl.busy)
-                        continue;
-                    all_busy = false;
-                    const wh_status st = launch_batch(sv, ms, sl);
-                    if (st != WH_OK) {
-                        sv->ctx->failed.store(true);
-                        fail_all(sv, st);
-                        break;
-                    }
-                    busy_any = true;
-                }
-                // a batch is waiting on a busy matrix: add a slot if the
-                // budget allows, and use it at once
-                if (sv->sticky == WH_OK && all_busy && !ms.pending.empty() && add_slot(sv, ms)) {
-                    const wh_status st = launch_batch(sv, ms, ms.slots.back());
-                    if (st != WH_OK) {
-                        sv->ctx->failed.store(true);
-                        fail_all(sv, st);
-                    }
-                    busy_any = true;
+                if (!ms.usable || ms.inflight.size() >= kMaxInflight || ms.spare.empty())
+                    continue;
+                uint64_t f, l;
+                if (!urgency(sv, ms, now, f, l))
+                    continue;
+                if (!pick || f < best_f || (f == best_f && l < best_l)) {
+                    pick = &ms;
+                    best_f = f;
+                    best_l = l;
                 }
             }
+            if (!pick)
+                break;
+            const wh_status st = issue_chunk(sv, *pick);
+            if (st != WH_OK) {
+                sv->ctx->failed.store(true);
+                fail_all(sv, st);
+                break;
+            }
+            ++inflight;
         }
-        // sleep briefly while batches run; block while idle
-        if (busy_any)
+        // sleep briefly while launches run; block while idle
+        if (inflight)
             sv->cv.wait_for(lk, std::chrono::microseconds(20));
         else
             sv->cv.wait_for(lk, std::chrono::milliseconds(5));
@@ -429,6 +458,21 @@ Server* ensure_server(wh_ctx* ctx)
         ctx->server = sv;
     }
     return ctx->server;
+}
+
+// Host memory given to the loop must be page-locked: its copies are then
+// asynchronous, so the loop never waits on one.  Device memory is checked to
+// be on the context's device.
+bool buffer_ok(const void* p, int on_device, int device)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError(); // pageable host memory: unknown to HIP
+        return false;
+    }
+    if (on_device)
+        return a.type == hipMemoryTypeDevice && a.device == device;
+    return a.type == hipMemoryTypeHost;
 }
 
 } // namespace
@@ -449,10 +493,7 @@ void serve_shutdown(wh_ctx* ctx)
         MatServe& ms = mv.second;
         if (ms.stream)
             (void)hipStreamSynchronize(ms.stream);
-        for (Slot& sl : ms.slots)
-            free_slot(sl);
-        if (ms.stream)
-            (void)hipStreamDestroy(ms.stream);
+        free_slot(ms);
     }
     delete sv;
     ctx->server = nullptr;
@@ -463,26 +504,31 @@ void serve_forget(wh_ctx* ctx, wh_mat m)
     Server* sv = ctx->server;
     if (!sv)
         return;
-    std::lock_guard<std::mutex> lk(sv->mu);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    // a slot still being built is finished first (its builder holds no lock)
+    sv->cv.wait(lk, [&] {
+        auto it = sv->mats.find(m);
+        return it == sv->mats.end() || !it->second.building;
+    });
     auto it = sv->mats.find(m);
     if (it == sv->mats.end())
         return;
     MatServe& ms = it->second;
     if (ms.stream)
-        (void)hipStreamSynchronize(ms.stream); // batches in flight finish
-    for (Slot& sl : ms.slots) {
-        for (uint64_t tk : sl.batch) { // finished on the device: deliver
+        (void)hipStreamSynchronize(ms.stream); // launches in flight finish
+    for (Launch& l : ms.inflight)
+        for (uint64_t tk : l.done) { // their last chunk ran: deliver
             Req& r = sv->reqs[tk];
             r.t_done = now_ns();
             r.status = WH_OK;
         }
-        sv->arena_used -= slot_bytes(ms.m, ctx);
-        free_slot(sl);
-    }
+    for (uint64_t tk : ms.active) // part of the way round the scan
+        sv->reqs[tk].status = WH_ERR_NOT_FOUND;
     for (uint64_t tk : ms.pending) // never started
         sv->reqs[tk].status = WH_ERR_NOT_FOUND;
-    if (ms.stream)
-        (void)hipStreamDestroy(ms.stream);
+    if (ms.usable)
+        sv->arena_used -= ms.bytes;
+    free_slot(ms);
     sv->mats.erase(it);
 }
 
@@ -498,24 +544,78 @@ extern "C" wh_status wh_submit(wh_ctx* ctx, const wh_request* req, uint64_t* tic
     if (!req->U || !req->Y || req->k == 0)
         return WH_ERR_INVALID;
     if (req->k > kMaxRhs)
-        return WH_ERR_BUDGET; // larger than any batch slot
+        return WH_ERR_BUDGET; // larger than a slot
     try {
         const uint64_t t = req->arrival_ns ? req->arrival_ns : now_ns();
-        Server* sv = ensure_server(ctx);
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->sticky != WH_OK)
-            return sv->sticky;
         if (hipSetDevice(ctx->device) != hipSuccess)
             return WH_ERR_DEVICE;
-        wh_status st = WH_OK;
-        MatServe* ms = serve_matrix(sv, req->mat, st);
-        if (!ms)
-            return st;
+        if (!buffer_ok(req->U, req->u_on_device, ctx->device) || !buffer_ok(req->Y, req->y_on_device, ctx->device))
+            return WH_ERR_INVALID;
+        Server* sv = ensure_server(ctx);
+        std::unique_lock<std::mutex> lk(sv->mu);
+        if (sv->sticky != WH_OK)
+            return sv->sticky;
+        auto it = sv->mats.find(req->mat);
+        if (it == sv->mats.end()) {
+            // first request for this matrix: admit its slot, build it unlocked
+            Matrix m;
+            {
+                std::lock_guard<std::mutex> lk2(ctx->mu);
+                Matrix* p = find_matrix(ctx, req->mat);
+                if (!p)
+                    return WH_ERR_NOT_FOUND;
+                m = *p;
+            }
+            if (m.desc.fmt != WH_FMT_ZFP_FIXED_RATE)
+                return WH_ERR_FORMAT;
+            const size_t bytes = slot_bytes(m, ctx);
+            if (bytes + sv->arena_used > ctx->budget)
+                return WH_ERR_BUDGET; // cannot hold even one slot of this matrix
+            sv->arena_used += bytes;
+            MatServe& ms = sv->mats[req->mat];
+            ms.m = m;
+            ms.bytes = bytes;
+            ms.building = true;
+            lk.unlock();
+            MatServe tmp;
+            tmp.m = m;
+            wh_status bst = build_slot(ctx, tmp);
+            lk.lock();
+            MatServe& ms2 = sv->mats[req->mat];
+            if (bst == WH_OK) {
+                ms2.stream = tmp.stream;
+                ms2.chunks = std::move(tmp.chunks);
+                ms2.U = tmp.U;
+                ms2.Y = tmp.Y;
+                ms2.part = tmp.part;
+                ms2.exec = std::move(tmp.exec);
+                ms2.spare = std::move(tmp.spare);
+                ms2.chunk_ms = tmp.chunk_ms;
+                ms2.usable = true;
+            } else {
+                free_slot(tmp);
+                ms2.build_status = bst;
+                sv->arena_used -= ms2.bytes;
+                for (uint64_t tk : ms2.pending) // requests queued meanwhile
+                    sv->reqs[tk].status = bst;
+                ms2.pending.clear();
+            }
+            ms2.building = false;
+            sv->cv.notify_all();
+            if (bst != WH_OK) {
+                sv->mats.erase(req->mat);
+                return bst;
+            }
+            it = sv->mats.find(req->mat);
+        }
+        MatServe& ms = it->second;
+        if (!ms.usable && !ms.building)
+            return ms.build_status != WH_OK ? ms.build_status : WH_ERR_BUDGET;
         // load shedding (off unless WH_SERVE_SHED is set): the matrix's oldest
         // queued request has already waited longer than `serve_shed` of its
         // deadlines, so a new one would wait longer still
-        if (ctx->serve_shed && !ms->pending.empty()) {
-            const Req& head = sv->reqs[ms->pending.front()];
+        if (ctx->serve_shed && !ms.pending.empty()) {
+            const Req& head = sv->reqs[ms.pending.front()];
             const uint64_t now = now_ns();
             if (head.r.deadline_ns && now > head.t_arrive &&
                 now - head.t_arrive > (uint64_t)ctx->serve_shed * head.r.deadline_ns)
@@ -525,9 +625,9 @@ extern "C" wh_status wh_submit(wh_ctx* ctx, const wh_request* req, uint64_t* tic
         Req& r = sv->reqs[tk];
         r.r = *req;
         r.t_arrive = t;
-        ms->pending.push_back(tk);
+        ms.pending.push_back(tk);
         *ticket = tk;
-        sv->cv.notify_one();
+        sv->cv.notify_all();
         return WH_OK;
     } catch (const std::bad_alloc&) {
         return WH_ERR_NOMEM;

@@ -456,16 +456,14 @@ wh_status wh_gemv_batched(wh_ctx* ctx, wh_mat m, const void* d_U, int u_dtype, u
             return wh_gemv(ctx, m, static_cast<const float*>(d_U), d_Y, 0, mat.desc.rows, flags, stream);
         if (flags & WH_PAPER_MP)
             return WH_ERR_INVALID; // Fig. 7 per-product sums exist for one vector only
-        const MrhsPlan pl = whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus);
-        double* part = nullptr;
-        if (pl.nslab > 1) {
-            wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * k * pl.part_rows(), st);
-            if (s2 != WH_OK)
-                return s2;
-            part = ctx->part;
-        }
-        hipError_t e = whz_mrhs(mat.desc.rate, pl, u_dtype == WH_U_BF16, mat.dptr, d_U, ldu, k, d_Y, ldy, part, st);
-        return device_error(ctx, part ? partials_release(ctx, st, e) : e);
+        const MrhsPlan pl = whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus, k);
+        // slab partials and B^T U share the context's workspace
+        wh_status s2 = ensure_partials(ctx, mrhs_workspace(pl, k, u_dtype == WH_U_BF16).total, st);
+        if (s2 != WH_OK)
+            return s2;
+        hipError_t e =
+            whz_mrhs(mat.desc.rate, pl, u_dtype == WH_U_BF16, mat.dptr, d_U, ldu, k, d_Y, ldy, ctx->part, st);
+        return device_error(ctx, partials_release(ctx, st, e));
     } catch (...) {
         return WH_ERR_INVALID;
     }

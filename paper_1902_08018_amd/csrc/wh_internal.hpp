@@ -50,14 +50,36 @@ struct GemvTuning {
     uint32_t slabs = 0; // column slabs (at most one per group width of block columns)
 };
 
-// Launch geometry of the multi-RHS kernel: tiles of 16 block-rows x slabs of
-// block-columns (multiples of 16).
+// Launch geometry of the multi-RHS kernel: tiles of 4 block-rows per wave x
+// slabs of block-columns (multiples of 16).  Waves per workgroup for NT
+// groups of 16 right-hand sides.
 typedef GemvPlan MrhsPlan;
-constexpr uint32_t kMrhsTileBlockRows = 32;
+constexpr int mrhs_waves(int nt) { return nt == 1 ? 12 : 8; }
+constexpr uint32_t kMrhsMaxTileBlockRows = 48;
 constexpr uint32_t kMaxRhs = 64;
 
+// The multi-RHS workspace, in doubles: FP64 slab partials [nslab][k][rows]
+// (only when the plan splits the columns), then, from btu_offset (a whole
+// number of 256-byte lines in), B^T U for every block column rounded up to
+// 16 and every group of 16 right-hand sides (FP32, or BF16 with BF16 U).
+struct MrhsWorkspace {
+    size_t btu_offset;
+    size_t total;
+};
+inline MrhsWorkspace mrhs_workspace(const MrhsPlan& pl, uint32_t k, bool bf16)
+{
+    const size_t part = pl.nslab > 1 ? (size_t)pl.nslab * k * pl.part_rows() : 0;
+    const size_t off = (part + 31) / 32 * 32;
+    const size_t nbc16 = ((size_t)pl.nbc + 15) / 16 * 16;
+    const size_t nt = (k + 15) / 16;
+    const size_t btu_bytes = nbc16 * nt * 64 * (bf16 ? 2 : 4);
+    return MrhsWorkspace{off, off + (btu_bytes + 7) / 8};
+}
+
 bool whz_rate_supported(uint32_t rate);
-MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus);
+// for k right-hand sides
+MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t k);
+// `ws`: mrhs_workspace(pl, k, bf16).total doubles of device memory
 hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu,
                     uint32_t k, float* Y, uint32_t ldy, double* part, hipStream_t st);
 GemvPlan whz_gemv_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,

@@ -195,7 +195,7 @@ hipError_t whz_gemv(uint32_t rate, const GemvPlan& pl, AccMode mode, const void*
     }
 }
 
-MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus)
+MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t k)
 {
     (void)rows;
     MrhsPlan pl{};
@@ -205,10 +205,11 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
     pl.cols = cols;
     pl.nrows = row_end - row_begin;
     const uint32_t nbr = pl.bi_end - pl.bi_begin;
-    pl.ntiles = (nbr + kMrhsTileBlockRows - 1) / kMrhsTileBlockRows;
-    // two 8-wave workgroups are resident per CU: one full round of them;
-    // more column slabs would only add FP64 partials (slabs x k x rows)
-    const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 2;
+    const uint32_t tile_rows = 4u * (uint32_t)mrhs_waves((int)((k + 15) / 16));
+    pl.ntiles = (nbr + tile_rows - 1) / tile_rows;
+    // two workgroups are resident per CU: about two rounds of them (each
+    // column slab adds FP64 partials, slabs x k x rows)
+    const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 4;
     const uint32_t max_slabs = (pl.nbc + 15) / 16;
     uint32_t nslab = pl.ntiles ? (uint32_t)((want + pl.ntiles - 1) / pl.ntiles) : 1;
     if (nslab < 1)

@@ -444,33 +444,40 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
 
 // ---------------------------------------------------- multi-RHS (MFMA path)
 // Y = M U^T for k right-hand sides (the paper's GEMV, Sec. 4.4, takes one
-// vector; several at once is this library's addition).  One workgroup = 8
-// waves = 32 block-rows (128 rows).  A block's rows against U are
-// B (C (B^T U)) (C its coefficients, B the inverse transform's linear part;
-// see lin_inv_lift), so the matrix cores contract coefficients, not decoded
-// values, against B^T U, and B is applied once to each block row's sums at
-// the end.  Per step (16 block columns = 64 columns):
-//   * the workgroup stages B^T U for the step's 64 columns and 16*NT
-//     right-hand sides in LDS (coalesced loads, shared by the 8 waves);
-//   * every wave decodes a 4 x 16 tile of blocks (one per lane) and keeps
-//     the coefficients, scaled by the block's 2^(emax-30), in registers;
-//   * four times, the lanes of one block-column quarter write their blocks
-//     to the wave's 16 x 16 LDS tile, which is contracted at once:
-//       FP32 U   v_mfma_f32_16x16x4f32, 4 MFMAs per quarter and 16 RHS
-//       BF16 U   v_mfma_f32_16x16x16bf16_1k (coefficients and B^T U rounded
-//                to BF16), 1 MFMA per quarter and 16 RHS
-//     (a quarter-width tile keeps the LDS per workgroup low enough for four
-//     waves per SIMD).
+// vector; several at once is this library's addition).  A block's rows
+// against U are B (C (B^T U)) (C its coefficients, B the inverse transform's
+// linear part; see lin_inv_lift), so the matrix cores contract coefficients,
+// not decoded values, against B^T U, and B is applied once to each block
+// row's sums at the end.
+//
+// B^T U is computed once per call by a small kernel into a workspace laid out
+// as the MFMA B operands (below); every wave then loads the operands of its
+// block columns itself, so the main kernel has no workgroup barrier after its
+// start: each wave runs on its own.
+//
+// Workgroup = mrhs_waves(NT) waves, a tile of 4 block rows per wave x a slab
+// of block columns: 12 waves (768 lanes) for up to 16 right-hand sides, so
+// that two workgroups fit a CU in LDS and 24 waves in registers; 8 waves for
+// more, whose FP64 sums leave registers for 16 to 20 waves.  Per step of
+// 16 block columns, each lane decodes one block of its wave's 4 x 16 tile
+// (the next step's block words are already in flight) and keeps its
+// coefficients, scaled by the block's 2^(emax - 30), in registers; then
+//   FP32 U   four quarters of 4 block columns: the quarter's lanes write their
+//            blocks to the wave's 16 x 16 LDS tile, which is contracted with
+//            v_mfma_f32_16x16x4f32 (K = 4: one block column), 4 MFMAs per
+//            quarter and 16 right-hand sides
+//   BF16 U   two halves of 8 block columns, written rounded to BF16 and
+//            contracted with v_mfma_f32_16x16x32_bf16 (K = 32), 1 MFMA per
+//            half and 16 right-hand sides
 // Operand layouts (16x16 output tile D[i][j], lane l):
-//   A[i][kk]  lane = i + 16*(kk/g), element kk % g   (g = 1 FP32, 4 BF16)
+//   A[i][kk]  lane = i + 16*(kk/g), element kk % g   (g = 1 FP32, 8 BF16)
 //   B[kk][j]  lane = j + 16*(kk/g), element kk % g
 //   D[i][j]   lane = j + 16*(i/4), register i % 4
 // so each lane's four accumulators are the four coefficient rows of one
-// block row.  The FP32 MFMA accumulators cover one step; after every step
-// they are added into FP64 sums.
-constexpr int kMrhsWaves = 8;
-constexpr int kMrhsThreads = 64 * kMrhsWaves;
-static_assert(4 * kMrhsWaves == (int)kMrhsTileBlockRows, "block rows per multi-RHS workgroup");
+// block row.  The FP32 MFMA accumulators cover one step (K = 64); after
+// every step they are added into FP64 sums.
+static_assert(4 * mrhs_waves(1) <= (int)kMrhsMaxTileBlockRows && 4 * mrhs_waves(4) <= (int)kMrhsMaxTileBlockRows,
+              "block rows per multi-RHS workgroup");
 constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's quarter tile
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
@@ -479,18 +486,6 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // plus 8 of padding, in the same LDS as the FP32 quarter tile
 constexpr int kATile16Stride = 40;
 static_assert(16 * kATile16Stride * 2 <= 16 * kATileStride * 4, "the BF16 tile fits the FP32 one");
-
-// Staged B^T U.  FP32: row (m * 16 + c) holds column 4c + m of the step for
-// the 16*NT right-hand sides; the odd row length keeps both the staging
-// writes and the MFMA operand reads on distinct banks.  BF16: row rhs holds
-// the step's 64 columns (4 consecutive columns = one 8-byte operand).
-template <int NT>
-struct MrhsUt {
-    static constexpr int kF32Stride = 16 * NT + 1;
-    static constexpr int kBf16Stride = 64 + 8;
-    static constexpr int kF32Words = 64 * kF32Stride;
-    static constexpr int kBf16Words = 16 * NT * kBf16Stride / 2;
-};
 
 __device__ __forceinline__ uint16_t to_bf16_rne(float f)
 {
@@ -510,67 +505,58 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// B^T U staging items of one step: item i = (right-hand side i / 16, block
-// column i % 16); a thread takes items threadIdx.x + kMrhsThreads * q.
-template <int NT>
-constexpr int kMrhsItems = (16 * 16 * NT + kMrhsThreads - 1) / kMrhsThreads;
-
-// Load the four U values of each of this thread's staging items of the step
-// at block column cb (zero past the last column, past the slab and past k).
-template <bool BF16U, int NT>
-__device__ __forceinline__ void mrhs_load_u(const void* __restrict__ Uv, uint32_t ldu, uint32_t k, uint32_t cols,
-                                            uint32_t cb, uint32_t bc1, float4 (&uv)[kMrhsItems<NT>])
+// B^T U for NT groups of 16 right-hand sides (zero past k and past the last
+// column), over nbc16 block columns (a multiple of 16; zero past the
+// matrix), in the layout the MFMA B operands are loaded in:
+//   FP32  float[bc][n][m][16]:      B[m][j] of block column bc, right-hand
+//                                   side 16 n + j (64 consecutive floats per
+//                                   (bc, n): one coalesced load per MFMA)
+//   BF16  bf16[bc / 2][n][16][8]:   for lane (j, g) of a K = 32 MFMA, the
+//                                   eight values (bc & 1, m) of block
+//                                   columns 2p, 2p + 1: one 16-byte load
+// One thread per (right-hand side, block column), block columns fastest so
+// that the loads of U are contiguous.
+template <bool BF16U>
+__global__ void __launch_bounds__(kThreads) mrhs_btu_kernel(const void* __restrict__ Uv, uint32_t ldu, uint32_t k,
+                                                            uint32_t nt, uint32_t cols, uint32_t nbc16,
+                                                            void* __restrict__ out)
 {
-#pragma unroll
-    for (int q = 0; q < kMrhsItems<NT>; ++q) {
-        const uint32_t i = threadIdx.x + (uint32_t)kMrhsThreads * q;
-        const uint32_t rhs = i >> 4, bcol = i & 15u;
-        float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f;
-        if (i < 16u * 16u * NT && rhs < k && cb + bcol < bc1) {
-            const uint32_t j = 4 * (cb + bcol), nv = cols - j < 4u ? cols - j : 4u;
-            const uint64_t o = (uint64_t)rhs * ldu + j;
-            if constexpr (BF16U) {
-                const uint16_t* U = static_cast<const uint16_t*>(Uv) + o;
-                u0 = bf16_to_float(U[0]);
-                u1 = nv > 1 ? bf16_to_float(U[1]) : 0.f;
-                u2 = nv > 2 ? bf16_to_float(U[2]) : 0.f;
-                u3 = nv > 3 ? bf16_to_float(U[3]) : 0.f;
-            } else {
-                const float* U = static_cast<const float*>(Uv) + o;
-                u0 = U[0];
-                u1 = nv > 1 ? U[1] : 0.f;
-                u2 = nv > 2 ? U[2] : 0.f;
-                u3 = nv > 3 ? U[3] : 0.f;
-            }
-        }
-        uv[q] = make_float4(u0, u1, u2, u3);
-    }
-}
-
-// B^T U of this thread's items into one staging buffer.
-template <bool BF16U, int NT>
-__device__ __forceinline__ void mrhs_stage_u(uint32_t* utw, const float4 (&uv)[kMrhsItems<NT>])
-{
-    using UT = MrhsUt<NT>;
-#pragma unroll
-    for (int q = 0; q < kMrhsItems<NT>; ++q) {
-        const uint32_t i = threadIdx.x + (uint32_t)kMrhsThreads * q;
-        if (i >= 16u * 16u * NT)
-            break;
-        const uint32_t rhs = i >> 4, bcol = i & 15u;
-        float ut[4];
-        lin_bt_u<float>(uv[q].x, uv[q].y, uv[q].z, uv[q].w, ut);
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= (uint64_t)nbc16 * 16 * nt)
+        return;
+    const uint32_t bc = (uint32_t)(i % nbc16), rhs = (uint32_t)(i / nbc16);
+    float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f;
+    const uint32_t j = 4 * bc;
+    if (rhs < k && j < cols) {
+        const uint32_t nv = cols - j < 4u ? cols - j : 4u;
+        const uint64_t o = (uint64_t)rhs * ldu + j;
         if constexpr (BF16U) {
-            uint16_t* utb = reinterpret_cast<uint16_t*>(utw);
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                utb[rhs * UT::kBf16Stride + 4 * bcol + m] = to_bf16_rne(ut[m]);
+            const uint16_t* U = static_cast<const uint16_t*>(Uv) + o;
+            u0 = bf16_to_float(U[0]);
+            u1 = nv > 1 ? bf16_to_float(U[1]) : 0.f;
+            u2 = nv > 2 ? bf16_to_float(U[2]) : 0.f;
+            u3 = nv > 3 ? bf16_to_float(U[3]) : 0.f;
         } else {
-            float* utf = reinterpret_cast<float*>(utw);
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                utf[(m * 16 + bcol) * UT::kF32Stride + rhs] = ut[m];
+            const float* U = static_cast<const float*>(Uv) + o;
+            u0 = U[0];
+            u1 = nv > 1 ? U[1] : 0.f;
+            u2 = nv > 2 ? U[2] : 0.f;
+            u3 = nv > 3 ? U[3] : 0.f;
         }
+    }
+    float ut[4];
+    lin_bt_u<float>(u0, u1, u2, u3, ut);
+    const uint32_t n = rhs >> 4, jj = rhs & 15u;
+    if constexpr (BF16U) {
+        uint16_t* o = static_cast<uint16_t*>(out) + ((((uint64_t)(bc >> 1) * nt + n) * 16 + jj) * 8 + (bc & 1u) * 4);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            o[m] = to_bf16_rne(ut[m]);
+    } else {
+        float* o = static_cast<float*>(out) + (((uint64_t)bc * nt + n) * 4) * 16 + jj;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            o[16 * m] = ut[m];
     }
 }
 
@@ -595,52 +581,51 @@ __device__ __forceinline__ void load_block_words(const uint32_t* __restrict__ g,
     }
 }
 
-// The step pipeline: while step s is decoded and contracted, the stream words
-// of step s + 1 and the U values of the next step to stage are in flight.
-// With two B^T U buffers (kMrhsBuffers), B^T U of step s + 1 is staged in the
-// other buffer during step s, so one workgroup barrier per step suffices: it
-// orders the contraction of step s (reading buffer s & 1) before the staging
-// of step s + 2 (writing it again), and the staging of step s + 1 before its
-// contraction.  FP32 U with more than 32 right-hand sides keeps one buffer
-// (two would leave LDS for only one workgroup per CU): a barrier before its
-// contraction and one after.
-template <bool BF16U, int NT>
-constexpr int kMrhsBuffers = (BF16U || NT <= 2) ? 2 : 1;
+// FP32 U: the B operands of one quarter (4 block columns from bc) for this
+// lane: B[m][j] of each block column and group of 16 right-hand sides.
+template <int NT>
+__device__ __forceinline__ void mrhs_load_bq(const float* __restrict__ btf, uint32_t bc, int lane, float (&b)[4][NT])
+{
+    const uint32_t mj = (uint32_t)lane; // m = lane / 16, j = lane % 16: offset 16 m + j
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+            b[kq][n] = btf[((uint64_t)(bc + kq) * NT + n) * 64 + mj];
+}
+
+// Quarters of B operands loaded ahead (FP32 U): all four before the decode
+// when one group of right-hand sides leaves the registers for it, else two.
+template <int NT>
+constexpr int kMrhsAhead = NT == 1 ? 4 : 2;
 
 template <int NW, bool BF16U, int NT>
-__global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __restrict__ stream,
-                                                            const void* __restrict__ Uv, uint32_t ldu, uint32_t k,
-                                                            float* __restrict__ Y, uint32_t ldy,
-                                                            double* __restrict__ part, uint32_t nbc,
-                                                            uint32_t bi_begin, uint32_t bi_end, uint32_t slab_bc,
-                                                            uint32_t nslab, uint32_t cols, uint32_t nrows_out)
+__global__ void __launch_bounds__(64 * mrhs_waves(NT)) mrhs_kernel(const uint32_t* __restrict__ stream,
+                                                                   const void* __restrict__ btu, uint32_t k,
+                                                                   float* __restrict__ Y, uint32_t ldy,
+                                                                   double* __restrict__ part, uint32_t nbc,
+                                                                   uint32_t bi_begin, uint32_t bi_end,
+                                                                   uint32_t slab_bc, uint32_t nslab, uint32_t nrows_out)
 {
-    using UT = MrhsUt<NT>;
-    constexpr int kUtWords = BF16U ? UT::kBf16Words : UT::kF32Words;
-    __shared__ uint32_t lds[kMrhsThreads * kStagedWords<NW>];
+    constexpr int W = mrhs_waves(NT), T = 64 * W;
+    __shared__ uint32_t lds[T * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
-    __shared__ __align__(16) float atile[kMrhsWaves][16 * kATileStride];
-    constexpr int NB = kMrhsBuffers<BF16U, NT>;
-    __shared__ __align__(16) uint32_t utw[NB][kUtWords];
+    __shared__ __align__(16) float atile[W][16 * kATileStride];
     uint32_t* row = lds + threadIdx.x;
-    clear_pad<NW, kMrhsThreads>(row);
+    clear_pad<NW, T>(row);
+    load_section_table<T>(tab); // the last workgroup barrier
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
-    const uint32_t bw = bi_begin + tile * kMrhsTileBlockRows + 4 * wave; // first block-row of this wave
+    const uint32_t bw = bi_begin + tile * (4 * W) + 4 * wave; // first block-row of this wave
     const uint32_t bc0 = slab * slab_bc;
     const uint32_t bc1 = bc0 + slab_bc < nbc ? bc0 + slab_bc : nbc;
     const int t = lane >> 4, c = lane & 15; // this lane's block in the wave's 4 x 16 step tile
     const uint32_t bi = bw + t;
     float* at = atile[wave];
+    const float* btf = static_cast<const float*>(btu);
+    const uint16_t* btb = static_cast<const uint16_t*>(btu);
 
-    // prologue: B^T U of step 0 staged, the U values of step 1 and the
-    // block words of step 0 in flight
-    float4 uv[kMrhsItems<NT>];
-    mrhs_load_u<BF16U, NT>(Uv, ldu, k, cols, bc0, bc1, uv);
-    load_section_table<kMrhsThreads>(tab);
-    mrhs_stage_u<BF16U, NT>(utw[0], uv);
-    mrhs_load_u<BF16U, NT>(Uv, ldu, k, cols, bc0 + 16, bc1, uv);
     uint32_t w[NW];
     {
         const bool valid = bi < bi_end && bc0 + c < bc1;
@@ -651,7 +636,6 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
             for (int q = 0; q < NW; ++q)
                 w[q] = 0u; // decodes as a zero block
     }
-    __syncthreads();
 
     mf32x4 acc[NT];
     double sum[NT][4];
@@ -661,21 +645,12 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
         for (int j = 0; j < 4; ++j)
             sum[n][j] = 0.0;
 
-    uint32_t sb = 0; // staging buffer of the current step
-    for (uint32_t cb = bc0; cb < bc1; cb += 16, sb ^= NB - 1) {
-        if constexpr (NB == 1) {
-            // the previous step's contraction is done (barrier at its end):
-            // stage this step's B^T U (step 0: staged before the loop)
-            if (cb != bc0) {
-                mrhs_stage_u<BF16U, NT>(utw[0], uv);
-                mrhs_load_u<BF16U, NT>(Uv, ldu, k, cols, cb + 16, bc1, uv);
-            }
-        }
-        // ---- this step's block: its words to the lane's LDS row; the next
-        // step's words in flight meanwhile
+    for (uint32_t cb = bc0; cb < bc1; cb += 16) {
+        // ---- this step's block words to the lane's LDS row; the next
+        // step's in flight
 #pragma unroll
         for (int q = 0; q < NW; ++q)
-            row[q * kMrhsThreads] = w[q];
+            row[q * T] = w[q];
         const uint32_t w0 = w[0];
         {
             const bool valid = bi < bi_end && cb + 16 + c < bc1;
@@ -686,60 +661,66 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                 for (int q = 0; q < NW; ++q)
                     w[q] = 0u;
         }
+        // ---- B operands in flight during the decode (block columns cb ..
+        // cb + 15 lie inside the workspace: it spans whole steps)
+        constexpr int AH = kMrhsAhead<NT>;
+        float bq[BF16U ? 1 : AH][4][NT];
+        u32x4 bh[BF16U ? 2 : 1][NT];
+        if constexpr (BF16U) {
+            const uint32_t g = (uint32_t)lane >> 4, j = (uint32_t)lane & 15u;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    bh[h][n] = *reinterpret_cast<const u32x4*>(
+                        btb + (((uint64_t)(cb / 2 + 4 * h + g) * NT + n) * 16 + j) * 8);
+        } else {
+#pragma unroll
+            for (int q = 0; q < AH; ++q)
+                mrhs_load_bq<NT>(btf, cb + 4 * q, lane, bq[q]);
+        }
         // ---- decode one block per lane: scaled coefficients (registers)
         int emax;
         uint32_t cf[16];
         bool cut;
-        decode_block_coeffs<NW, kMrhsThreads>(row, tab, w0, emax, cf, cut);
+        decode_block_coeffs<NW, T>(row, tab, w0, emax, cf, cut);
         float sc[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v)
             sc[v] = __builtin_ldexpf((float)(int32_t)cf[v], emax - 30);
         if (__any(cut) && cut) // rare: the exact lift (see exact_block_coeffs)
             exact_block_coeffs(cf, emax, sc);
-        // ---- B^T U of the next step into the other buffer; the U values of
-        // the step after it in flight
-        if constexpr (NB == 2) {
-            if (cb + 16 < bc1) {
-                mrhs_stage_u<BF16U, NT>(utw[sb ^ 1u], uv);
-                mrhs_load_u<BF16U, NT>(Uv, ldu, k, cols, cb + 32, bc1, uv);
-            }
-        } else {
-            __syncthreads(); // this step's slice is staged
-        }
-        const float* utf = reinterpret_cast<const float*>(utw[sb]);
-        const uint16_t* utb = reinterpret_cast<const uint16_t*>(utw[sb]);
 #pragma unroll
         for (int n = 0; n < NT; ++n)
             acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
-        // ---- FP32 U: four quarters of 4 block columns, each written to the
-        // wave's tile and then contracted (K = 4 per MFMA)
+        if constexpr (!BF16U) {
+            // ---- four quarters of 4 block columns: write, then contract
 #pragma unroll
-        for (int q = 0; q < (BF16U ? 0 : 4); ++q) {
-            // the tile is the wave's own: lanes read what other lanes of the
-            // wave wrote, so each hand-over is a wave-scope release/acquire
-            // (no workgroup barrier is needed)
-            wave_sync_lds();
-            if ((c >> 2) == q) {
+            for (int q = 0; q < 4; ++q) {
+                // the tile is the wave's own: lanes read what other lanes of
+                // the wave wrote, so each hand-over is a wave-scope
+                // release/acquire (no workgroup barrier is needed)
+                wave_sync_lds();
+                if ((c >> 2) == q) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    *reinterpret_cast<f32x4*>(at + (4 * t + r) * kATileStride + 4 * (c & 3)) =
-                        f32x4{sc[4 * r], sc[4 * r + 1], sc[4 * r + 2], sc[4 * r + 3]};
-            }
-            wave_sync_lds();
-            {
+                    for (int r = 0; r < 4; ++r)
+                        *reinterpret_cast<f32x4*>(at + (4 * t + r) * kATileStride + 4 * (c & 3)) =
+                            f32x4{sc[4 * r], sc[4 * r + 1], sc[4 * r + 2], sc[4 * r + 3]};
+                }
+                wave_sync_lds();
+                const int slot = q % AH;
 #pragma unroll
                 for (int kq = 0; kq < 4; ++kq) {
-                    const int m = lane >> 4;     // column 4 kb + m of the step, kb = 4 q + kq
+                    const int m = lane >> 4; // column 4 kb + m of the step, kb = 4 q + kq
                     const float a = at[(lane & 15) * kATileStride + 4 * kq + m];
-                    const float* ub = utf + (m * 16 + 4 * q + kq) * UT::kF32Stride + (lane & 15);
 #pragma unroll
                     for (int n = 0; n < NT; ++n)
-                        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ub[16 * n], acc[n], 0, 0, 0);
+                        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq[slot][kq][n], acc[n], 0, 0, 0);
                 }
+                if (q + AH < 4) // the quarter after next into the slot just used
+                    mrhs_load_bq<NT>(btf, cb + 4 * (q + AH), lane, bq[slot]);
             }
-        }
-        if constexpr (BF16U) {
+        } else {
             // ---- two halves of 8 block columns (K = 32): the lanes of a half
             // write their blocks' coefficients, rounded to BF16, to the tile
             // (row 4t + r, columns 4 (c % 8) .. + 3); lane l then holds
@@ -764,12 +745,9 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
                     *reinterpret_cast<const u32x4*>(at16 + (lane & 15) * kATile16Stride + 8 * (lane >> 4));
                 const mbf16x8 a = __builtin_bit_cast(mbf16x8, av);
 #pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const u32x4 bv = *reinterpret_cast<const u32x4*>(
-                        utb + (16 * n + (lane & 15)) * UT::kBf16Stride + 32 * h + 8 * (lane >> 4));
-                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(mbf16x8, bv), acc[n], 0,
-                                                                     0, 0);
-                }
+                for (int n = 0; n < NT; ++n)
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(mbf16x8, bh[h][n]), acc[n],
+                                                                     0, 0, 0);
             }
         }
 #pragma unroll
@@ -777,7 +755,6 @@ __global__ void __launch_bounds__(kMrhsThreads) mrhs_kernel(const uint32_t* __re
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 sum[n][j] += (double)acc[n][j];
-        __syncthreads(); // this step's slice is read (and, two buffers: the next one staged)
     }
 
     // ---- B on each block row's four coefficient-row sums; D[i][j]: lane
@@ -917,29 +894,42 @@ hipError_t launch_gemv(const GemvPlan& pl, AccMode mode, const uint32_t* s, cons
 }
 
 template <int NW, bool BF, int NT>
-hipError_t launch_mrhs_t(const MrhsPlan& pl, const uint32_t* s, const void* U, uint32_t ldu, uint32_t k, float* Y,
-                         uint32_t ldy, double* part, hipStream_t st)
+hipError_t launch_mrhs_t(const MrhsPlan& pl, const uint32_t* s, const void* btu, uint32_t k, float* Y, uint32_t ldy,
+                         double* part, hipStream_t st)
 {
-    hipLaunchKernelGGL((mrhs_kernel<NW, BF, NT>), dim3(pl.ntiles * pl.nslab), dim3(kMrhsThreads), 0, st, s, U, ldu, k,
-                       Y, ldy, part, pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab, pl.cols, pl.nrows);
+    hipLaunchKernelGGL((mrhs_kernel<NW, BF, NT>), dim3(pl.ntiles * pl.nslab), dim3(64 * mrhs_waves(NT)), 0, st, s,
+                       btu, k, Y, ldy, part, pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab, pl.nrows);
     return hipGetLastError();
 }
 
 template <int NW>
 hipError_t launch_mrhs(const MrhsPlan& pl, bool bf16, const uint32_t* s, const void* U, uint32_t ldu, uint32_t k,
-                       float* Y, uint32_t ldy, double* part, hipStream_t st)
+                       float* Y, uint32_t ldy, double* ws, hipStream_t st)
 {
     const int nt = (int)((k + 15) / 16);
-    hipError_t e = hipErrorInvalidValue;
+    const MrhsWorkspace w = mrhs_workspace(pl, k, bf16);
+    double* part = pl.nslab > 1 ? ws : nullptr;
+    void* btu = ws + w.btu_offset;
+    const uint32_t nbc16 = (pl.nbc + 15) / 16 * 16;
+    const uint64_t items = (uint64_t)nbc16 * 16 * nt;
+    if (bf16)
+        hipLaunchKernelGGL(mrhs_btu_kernel<true>, dim3((unsigned)((items + kThreads - 1) / kThreads)), dim3(kThreads),
+                           0, st, U, ldu, k, (uint32_t)nt, pl.cols, nbc16, btu);
+    else
+        hipLaunchKernelGGL(mrhs_btu_kernel<false>, dim3((unsigned)((items + kThreads - 1) / kThreads)),
+                           dim3(kThreads), 0, st, U, ldu, k, (uint32_t)nt, pl.cols, nbc16, btu);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
     switch (nt * 2 + (bf16 ? 1 : 0)) {
-    case 2: e = launch_mrhs_t<NW, false, 1>(pl, s, U, ldu, k, Y, ldy, part, st); break;
-    case 3: e = launch_mrhs_t<NW, true, 1>(pl, s, U, ldu, k, Y, ldy, part, st); break;
-    case 4: e = launch_mrhs_t<NW, false, 2>(pl, s, U, ldu, k, Y, ldy, part, st); break;
-    case 5: e = launch_mrhs_t<NW, true, 2>(pl, s, U, ldu, k, Y, ldy, part, st); break;
-    case 6: e = launch_mrhs_t<NW, false, 3>(pl, s, U, ldu, k, Y, ldy, part, st); break;
-    case 7: e = launch_mrhs_t<NW, true, 3>(pl, s, U, ldu, k, Y, ldy, part, st); break;
-    case 8: e = launch_mrhs_t<NW, false, 4>(pl, s, U, ldu, k, Y, ldy, part, st); break;
-    case 9: e = launch_mrhs_t<NW, true, 4>(pl, s, U, ldu, k, Y, ldy, part, st); break;
+    case 2: e = launch_mrhs_t<NW, false, 1>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 3: e = launch_mrhs_t<NW, true, 1>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 4: e = launch_mrhs_t<NW, false, 2>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 5: e = launch_mrhs_t<NW, true, 2>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 6: e = launch_mrhs_t<NW, false, 3>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 7: e = launch_mrhs_t<NW, true, 3>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 8: e = launch_mrhs_t<NW, false, 4>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 9: e = launch_mrhs_t<NW, true, 4>(pl, s, btu, k, Y, ldy, part, st); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || pl.nslab == 1)

@@ -11,6 +11,9 @@
   row chunks     with WH_SERVE_CHUNK_VALUES small, every pass runs as many
                  row-chunk launches (the last one ragged): results still
                  within 1e-6 of the oracle, k = 1 and multi-RHS
+  cyclic scan    a request submitted during another's pass joins it at the
+                 next chunk launch (starts before that pass ends)
+  buffers        pageable host U or Y is refused at submit
 """
 import time
 
@@ -266,3 +269,58 @@ def test_load_shedding(monkeypatch):
         wait(ctx, [t])
     finally:
         wh.wh_destroy(ctx)
+
+
+def test_requests_join_a_pass_in_progress(monkeypatch):
+    """The scan over a matrix's row chunks takes new requests at the next
+    chunk launch: a request submitted while another's pass is under way
+    starts before that pass ends, and both results are right."""
+    monkeypatch.setenv("WH_SERVE_CHUNK_VALUES", str(8 * 1024))  # 8 rows a chunk: 256 chunks of 2048 x 1024
+    ctx = wh.wh_create(0, 256 << 20)
+    try:
+        sp = SPECS[1]
+        s = oracle.encode(synth.matrix(sp), 8)
+        d = torch.from_numpy(s).cuda()
+        mat = wh.wh_load_compressed(ctx, sp.rows, sp.cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, d)
+        ref_M = oracle.decode(s, sp.rows, sp.cols, 8).astype(np.float64)
+        # warm the slot (graphs built on the first request)
+        U0 = torch.from_numpy(synth.uniform(sp.cols, seed=800).reshape(1, -1)).cuda()
+        Y0 = torch.empty((1, sp.rows), device="cuda")
+        t0 = wh.wh_submit(ctx, make_request(mat, U0, Y0))
+        wait(ctx, [t0])
+        UA = torch.from_numpy(synth.uniform(2 * sp.cols, seed=801).reshape(2, -1)).cuda()
+        UB = torch.from_numpy(synth.uniform(3 * sp.cols, seed=802).reshape(3, -1)).cuda()
+        YA = torch.full((2, sp.rows), -7.0, device="cuda")
+        YB = torch.full((3, sp.rows), -7.0, device="cuda")
+        torch.cuda.synchronize()
+        ta = wh.wh_submit(ctx, make_request(mat, UA, YA))
+        time.sleep(0.0005)
+        tb = wh.wh_submit(ctx, make_request(mat, UB, YB))
+        res = wait(ctx, [ta, tb])
+        a, b = res[ta], res[tb]
+        assert a[0] == wh.WH_OK and b[0] == wh.WH_OK
+        print(f"A: start {(a[2] - a[1]) * 1e-6:.3f} ms done {(a[3] - a[1]) * 1e-6:.3f} ms; "
+              f"B: start {(b[2] - a[1]) * 1e-6:.3f} ms done {(b[3] - a[1]) * 1e-6:.3f} ms")
+        assert b[2] < a[3], "B waited for A's pass to end"
+        assert b[3] >= a[3]
+        torch.cuda.synchronize()
+        for U, Y in ((UA, YA), (UB, YB)):
+            r = U.cpu().numpy().astype(np.float64) @ ref_M.T
+            e = np.linalg.norm(Y.cpu().numpy() - r, axis=1) / np.linalg.norm(r, axis=1)
+            assert e.max() <= 1e-6
+    finally:
+        wh.wh_destroy(ctx)
+
+
+def test_pageable_host_buffers_are_refused(serving):
+    """Host buffers must be page-locked (their copies are then asynchronous
+    and the loop never waits on one); pageable ones are refused at submit."""
+    ctx, mats, _ = serving
+    U = torch.rand((1, SPECS[0].cols))       # pageable
+    Y = torch.zeros((1, SPECS[0].rows))
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_submit(ctx, make_request(mats[0], U, Y.pin_memory()))
+    assert ei.value.status == wh.WH_ERR_INVALID
+    with pytest.raises(wh.WhError) as ei:
+        wh.wh_submit(ctx, make_request(mats[0], U.pin_memory(), Y))
+    assert ei.value.status == wh.WH_ERR_INVALID
