@@ -122,8 +122,8 @@ const char *wh_status_str(wh_status st);
  * variables WH_GEMV_LANES (4, 8, ..., 512 lanes per block row),
  * WH_GEMV_ROWS (1, 2 or 4 block rows per lane group) and WH_GEMV_SLABS
  * (column slabs), read here, fix the compressed GEMV's launch shape instead
- * of the planner's choice (for launch-shape sweeps); invalid values are
- * ignored.  Results stay within the stated tolerances for every shape.
+ * of the planner's choice, and WH_MRHS_SLABS the multi-RHS kernel's column
+ * slabs (for launch-shape sweeps); invalid values are ignored.  Results stay within the stated tolerances for every shape.
  * WH_SERVE_CHUNK_VALUES (a positive integer, default 2^29) bounds the matrix
  * values one serving launch covers: the serving loop runs each pass over a
  * larger matrix as launches over consecutive row chunks, so that batches of

@@ -154,7 +154,8 @@ size_t slot_partials(const Matrix& m, const wh_ctx* ctx)
         if (gp.nslab > 1)
             n = std::max(n, (size_t)gp.nslab * gp.part_rows());
         for (uint32_t k = 16; k <= kMaxRhs; k += 16) { // the plan depends on k's group count
-            const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k);
+            const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k,
+                                              ctx->gemv_tune.mrhs_slabs);
             n = std::max(n, mrhs_workspace(mp, k, false).total);
         }
     }
@@ -242,7 +243,8 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
                 const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
                 e = whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, ms.U, ms.Y + c.first, ms.part, ms.stream);
             } else {
-                const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k);
+                const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k,
+                                                  ctx->gemv_tune.mrhs_slabs);
                 e = whz_mrhs(m.desc.rate, mp, false, m.dptr, ms.U, m.desc.cols, k, ms.Y + c.first, m.desc.rows,
                              ms.part, ms.stream);
             }

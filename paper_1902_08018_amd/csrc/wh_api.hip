@@ -36,8 +36,9 @@ wh_status device_error(wh_ctx* ctx, hipError_t e)
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
 // WH_GEMV_LANES / WH_GEMV_ROWS / WH_GEMV_SLABS fix the fused GEMV's lanes per
-// block row, block rows per lane group and column slabs (launch-shape sweeps
-// and tests); a value that is not valid is ignored.
+// block row, block rows per lane group and column slabs, WH_MRHS_SLABS the
+// multi-RHS kernel's column slabs (launch-shape sweeps and tests); a value
+// that is not valid is ignored.
 GemvTuning gemv_tuning_from_env()
 {
     auto get = [](const char* name) -> uint32_t {
@@ -55,6 +56,7 @@ GemvTuning gemv_tuning_from_env()
     if (rows == 1 || rows == 2 || rows == 4)
         t.rows = rows;
     t.slabs = get("WH_GEMV_SLABS");
+    t.mrhs_slabs = get("WH_MRHS_SLABS");
     return t;
 }
 
@@ -456,7 +458,8 @@ wh_status wh_gemv_batched(wh_ctx* ctx, wh_mat m, const void* d_U, int u_dtype, u
             return wh_gemv(ctx, m, static_cast<const float*>(d_U), d_Y, 0, mat.desc.rows, flags, stream);
         if (flags & WH_PAPER_MP)
             return WH_ERR_INVALID; // Fig. 7 per-product sums exist for one vector only
-        const MrhsPlan pl = whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus, k);
+        const MrhsPlan pl =
+            whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus, k, ctx->gemv_tune.mrhs_slabs);
         // slab partials and B^T U share the context's workspace
         wh_status s2 = ensure_partials(ctx, mrhs_workspace(pl, k, u_dtype == WH_U_BF16).total, st);
         if (s2 != WH_OK)

@@ -48,6 +48,7 @@ struct GemvTuning {
     uint32_t lanes = 0; // lanes per group: 4, 8, ..., 512
     uint32_t rows = 0;  // block rows per group and tile: 1 .. kGemvMaxRowsPerGroup
     uint32_t slabs = 0; // column slabs (at most one per group width of block columns)
+    uint32_t mrhs_slabs = 0; // column slabs of the multi-RHS kernel
 };
 
 // Launch geometry of the multi-RHS kernel: tiles of 4 block-rows per wave x
@@ -77,8 +78,9 @@ inline MrhsWorkspace mrhs_workspace(const MrhsPlan& pl, uint32_t k, bool bf16)
 }
 
 bool whz_rate_supported(uint32_t rate);
-// for k right-hand sides
-MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t k);
+// for k right-hand sides; slabs != 0 fixes the column slab count
+MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t k,
+                       uint32_t slabs = 0);
 // `ws`: mrhs_workspace(pl, k, bf16).total doubles of device memory
 hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu,
                     uint32_t k, float* Y, uint32_t ldy, double* part, hipStream_t st);

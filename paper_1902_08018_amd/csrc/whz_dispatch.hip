@@ -195,7 +195,8 @@ hipError_t whz_gemv(uint32_t rate, const GemvPlan& pl, AccMode mode, const void*
     }
 }
 
-MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t k)
+MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t k,
+                       uint32_t slabs)
 {
     (void)rows;
     MrhsPlan pl{};
@@ -208,12 +209,19 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
     const uint32_t tile_rows = 4u * (uint32_t)mrhs_waves((int)((k + 15) / 16));
     pl.ntiles = (nbr + tile_rows - 1) / tile_rows;
     // two workgroups are resident per CU: about two rounds of them (each
-    // column slab adds FP64 partials, slabs x k x rows)
+    // column slab adds FP64 partials, slabs x k x rows).  Workgroups go to
+    // the eight XCDs round-robin, so with a multiple of 8 slabs (slab =
+    // workgroup % slabs) each XCD's L2 holds the B^T U of 1/8 of the columns
+    // only
     const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 4;
     const uint32_t max_slabs = (pl.nbc + 15) / 16;
     uint32_t nslab = pl.ntiles ? (uint32_t)((want + pl.ntiles - 1) / pl.ntiles) : 1;
     if (nslab < 1)
         nslab = 1;
+    if (max_slabs >= 8)
+        nslab = (nslab + 7) / 8 * 8;
+    if (slabs)
+        nslab = slabs;
     if (nslab > max_slabs)
         nslab = max_slabs ? max_slabs : 1;
     uint32_t slab_bc = (pl.nbc + nslab - 1) / nslab;

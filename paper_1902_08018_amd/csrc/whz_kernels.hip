@@ -464,8 +464,9 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
 // coefficients, scaled by the block's 2^(emax - 30), in registers; then
 //   FP32 U   four quarters of 4 block columns: the quarter's lanes write their
 //            blocks to the wave's 16 x 16 LDS tile, which is contracted with
-//            v_mfma_f32_16x16x4f32 (K = 4: one block column), 4 MFMAs per
-//            quarter and 16 right-hand sides
+//            v_mfma_f32_16x16x4f32, K = the quarter's 4 block columns, one
+//            MFMA per coefficient column: 4 MFMAs per quarter and 16
+//            right-hand sides
 //   BF16 U   two halves of 8 block columns, written rounded to BF16 and
 //            contracted with v_mfma_f32_16x16x32_bf16 (K = 32), 1 MFMA per
 //            half and 16 right-hand sides
@@ -508,9 +509,10 @@ __device__ __forceinline__ void wave_sync_lds()
 // B^T U for NT groups of 16 right-hand sides (zero past k and past the last
 // column), over nbc16 block columns (a multiple of 16; zero past the
 // matrix), in the layout the MFMA B operands are loaded in:
-//   FP32  float[bc][n][m][16]:      B[m][j] of block column bc, right-hand
-//                                   side 16 n + j (64 consecutive floats per
-//                                   (bc, n): one coalesced load per MFMA)
+//   FP32  float[bc][n][16][4]:      for lane (j, kk) of a quarter's K = 4
+//                                   MFMAs (kk: block column), the four values
+//                                   m = 0..3 of right-hand side 16 n + j:
+//                                   one 16-byte load per quarter
 //   BF16  bf16[bc / 2][n][16][8]:   for lane (j, g) of a K = 32 MFMA, the
 //                                   eight values (bc & 1, m) of block
 //                                   columns 2p, 2p + 1: one 16-byte load
@@ -553,10 +555,10 @@ __global__ void __launch_bounds__(kThreads) mrhs_btu_kernel(const void* __restri
         for (int m = 0; m < 4; ++m)
             o[m] = to_bf16_rne(ut[m]);
     } else {
-        float* o = static_cast<float*>(out) + (((uint64_t)bc * nt + n) * 4) * 16 + jj;
+        float* o = static_cast<float*>(out) + (((uint64_t)bc * nt + n) * 16 + jj) * 4;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            o[16 * m] = ut[m];
+            o[m] = ut[m];
     }
 }
 
@@ -582,22 +584,21 @@ __device__ __forceinline__ void load_block_words(const uint32_t* __restrict__ g,
 }
 
 // FP32 U: the B operands of one quarter (4 block columns from bc) for this
-// lane: B[m][j] of each block column and group of 16 right-hand sides.
+// lane (j = lane % 16, block column bc + lane / 16): B^T U's four values
+// m = 0..3 of right-hand side 16 n + j, one MFMA each.
 template <int NT>
-__device__ __forceinline__ void mrhs_load_bq(const float* __restrict__ btf, uint32_t bc, int lane, float (&b)[4][NT])
+__device__ __forceinline__ void mrhs_load_bq(const float* __restrict__ btf, uint32_t bc, int lane, f32x4 (&b)[NT])
 {
-    const uint32_t mj = (uint32_t)lane; // m = lane / 16, j = lane % 16: offset 16 m + j
+    const uint32_t kk = (uint32_t)lane >> 4, j = (uint32_t)lane & 15u;
 #pragma unroll
-    for (int kq = 0; kq < 4; ++kq)
-#pragma unroll
-        for (int n = 0; n < NT; ++n)
-            b[kq][n] = btf[((uint64_t)(bc + kq) * NT + n) * 64 + mj];
+    for (int n = 0; n < NT; ++n)
+        b[n] = *reinterpret_cast<const f32x4*>(btf + (((uint64_t)(bc + kk) * NT + n) * 16 + j) * 4);
 }
 
-// Quarters of B operands loaded ahead (FP32 U): all four before the decode
-// when one group of right-hand sides leaves the registers for it, else two.
+// Quarters of B operands loaded ahead (FP32 U), as many as the registers for
+// six (one group of right-hand sides) or four waves per SIMD leave room for.
 template <int NT>
-constexpr int kMrhsAhead = NT == 1 ? 4 : 2;
+constexpr int kMrhsAhead = NT == 1 ? 3 : (NT == 2 ? 2 : 1);
 
 template <int NW, bool BF16U, int NT>
 __global__ void __launch_bounds__(64 * mrhs_waves(NT)) mrhs_kernel(const uint32_t* __restrict__ stream,
@@ -664,7 +665,7 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT)) mrhs_kernel(const uint32_
         // ---- B operands in flight during the decode (block columns cb ..
         // cb + 15 lie inside the workspace: it spans whole steps)
         constexpr int AH = kMrhsAhead<NT>;
-        float bq[BF16U ? 1 : AH][4][NT];
+        f32x4 bq[BF16U ? 1 : AH][NT];
         u32x4 bh[BF16U ? 2 : 1][NT];
         if constexpr (BF16U) {
             const uint32_t g = (uint32_t)lane >> 4, j = (uint32_t)lane & 15u;
@@ -709,14 +710,15 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT)) mrhs_kernel(const uint32_
                 }
                 wave_sync_lds();
                 const int slot = q % AH;
+                // MFMA m contracts coefficient column m of the quarter's four
+                // block columns (K = block column): lane l holds A[l % 16][l / 16],
+                // coefficient (r, m) = ((l % 16) % 4, m) of block column l / 16
+                const f32x4 a4 = *reinterpret_cast<const f32x4*>(at + (lane & 15) * kATileStride + 4 * (lane >> 4));
 #pragma unroll
-                for (int kq = 0; kq < 4; ++kq) {
-                    const int m = lane >> 4; // column 4 kb + m of the step, kb = 4 q + kq
-                    const float a = at[(lane & 15) * kATileStride + 4 * kq + m];
+                for (int m = 0; m < 4; ++m)
 #pragma unroll
                     for (int n = 0; n < NT; ++n)
-                        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq[slot][kq][n], acc[n], 0, 0, 0);
-                }
+                        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[m], bq[slot][n][m], acc[n], 0, 0, 0);
                 if (q + AH < 4) // the quarter after next into the slot just used
                     mrhs_load_bq<NT>(btf, cb + 4 * (q + AH), lane, bq[slot]);
             }
