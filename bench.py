@@ -50,8 +50,10 @@ def parse():
                     help="counter-pass mode, prints no JSON: 1 = 3 launches of the timed configuration, then 3 "
                          "plain 4 GiB device copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE) and 3 "
                          "read-only streams of the same 4 GiB; "
-                         "2 = 3 multi-RHS launches (k = 16, FP32 U) on the same matrix; 3 = 3 whole-matrix "
-                         "decodes into row-major FP32 (the separate path's first step)")
+                         "2 = 3 multi-RHS launches (k = --probe-k, FP32 or --probe-bf16 U) on the same matrix; "
+                         "3 = 3 whole-matrix decodes into row-major FP32 (the separate path's first step)")
+    ap.add_argument("--probe-k", type=int, default=16, help="right-hand sides of --probe 2")
+    ap.add_argument("--probe-bf16", type=int, default=0, help="--probe 2 with BF16 U")
     ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                                            "traffic.json"))
     return ap.parse_args()
@@ -663,7 +665,7 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
     outstanding = {}
     last_done = [None] * nm
     lat, miss, bsz, rejected = [], 0, [], 0
-    per = [{"lat": [], "miss": 0, "rejected": 0} for _ in range(nm)]
+    per = [{"lat": [], "miss": 0, "rejected": 0, "queue": [], "service": []} for _ in range(nm)]
     t0 = time.monotonic_ns() + 50_000_000
     i = 0
     done_count = 0
@@ -697,6 +699,8 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
                     pj = per[int(target[idx])]
                     pj["lat"].append(lat[-1])
                     pj["miss"] += r.missed
+                    pj["queue"].append((r.t_start_ns - r.t_arrive_ns) * 1e-6)   # waiting to join a launch
+                    pj["service"].append((r.t_done_ns - r.t_start_ns) * 1e-6)  # one pass of the scan
         if i < n:
             nxt = t0 + int(arrive[i] * 1e9) - time.monotonic_ns()
             if nxt > 200_000:
@@ -728,7 +732,12 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
                                                    "p50_ms": round(float(np.percentile(pj["lat"], 50)), 3),
                                                    "p99_ms": round(float(np.percentile(pj["lat"], 99)), 3),
                                                    "miss_rate": round(pj["miss"] / max(1, len(pj["lat"])), 4),
-                                                   "rejected": pj["rejected"]}
+                                                   "rejected": pj["rejected"],
+                                                   "queue_p50_ms": round(float(np.percentile(pj["queue"], 50)), 3),
+                                                   "service_p50_ms": round(float(np.percentile(pj["service"], 50)),
+                                                                          3),
+                                                   "service_p99_ms": round(float(np.percentile(pj["service"], 99)),
+                                                                          3)}
                            for sp, pj in zip(specs, per) if pj["lat"]}}
 
 
@@ -755,12 +764,16 @@ def main():
     us = [workload.u_device(spec, synth.STREAM_U, k * cols) for k in range(4)]
     y = torch.empty(rows, dtype=torch.float32, device="cuda")
     if args.probe == 2:
-        U = torch.from_numpy(synth.u_batch(spec, 16)).cuda()
-        Y = torch.empty((16, rows), dtype=torch.float32, device="cuda")
+        k = args.probe_k
+        U = torch.from_numpy(synth.u_batch(spec, k)).cuda()
+        if args.probe_bf16:
+            U = U.to(torch.bfloat16)
+        Y = torch.empty((k, rows), dtype=torch.float32, device="cuda")
         for _ in range(3):
             wh.wh_gemv_batched(ctx, mat, U, Y)
         torch.cuda.synchronize()
-        print(f"# probe done: 3 x wh_gemv_batched k=16 rate {rate} {rows}x{cols}", file=sys.stderr, flush=True)
+        print(f"# probe done: 3 x wh_gemv_batched k={k} {'BF16' if args.probe_bf16 else 'FP32'} U rate {rate} "
+              f"{rows}x{cols}", file=sys.stderr, flush=True)
         wh.wh_destroy(ctx)
         return
     if args.probe == 3:

@@ -207,13 +207,15 @@ wh_status wh_gemv_noalloc(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, u
                           uint32_t row_end, uint32_t flags, void *stream);
 
 /* The launch shape the fused compressed GEMV would use for rows
- * [row_begin, row_end) of a rows x cols matrix on a device with num_cus
- * CUs (diagnostics; no context, no GPU): out8 = {lanes per block row, block
- * rows per lane group, row tiles, column slabs, block columns per slab,
- * first block row, one past the last block row, rows of the first block row
- * before the range}.  The workgroups launched are row tiles x column slabs. */
+ * [row_begin, row_end) of a rows x cols matrix at `rate` bits/value on a
+ * device with num_cus CUs (diagnostics; no context, no GPU): out9 = {lanes
+ * per block row, block rows per lane group, row tiles, column slabs, block
+ * columns per slab, first block row, one past the last block row, rows of the
+ * first block row before the range, lanes per workgroup}.  The workgroups
+ * launched are row tiles x column slabs.  An unsupported rate ->
+ * WH_ERR_INVALID. */
 wh_status wh_gemv_plan_info(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
-                            uint32_t *out8);
+                            uint32_t rate, uint32_t *out9);
 
 /* Y = M U for k right-hand sides.  The paper's GEMV takes one vector
  * (Sec. 4.4); several at once is this library's addition, for the serving

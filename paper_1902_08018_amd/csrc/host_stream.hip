@@ -164,7 +164,7 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
                 (void)hipGetLastError();
                 return WH_ERR_INVALID;
             }
-            const GemvPlan pl = whz_gemv_plan(rows, cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
+            const GemvPlan pl = whz_gemv_plan(rate, rows, cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
             if (pl.nslab > 1) {
                 const wh_status s = ensure_partials(ctx, (size_t)pl.nslab * pl.part_rows(), st);
                 if (s != WH_OK)
@@ -190,7 +190,7 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
             const uint64_t b0 = bb + n * cb;
             const uint32_t b1 = (uint32_t)std::min<uint64_t>(b0 + cb, be);
             const Chunk c = chunk_at((uint32_t)b0, b1, rows, row_begin, row_end);
-            const GemvPlan pl = whz_gemv_plan(c.rows, cols, c.lo, c.hi, ctx->num_cus, &ctx->gemv_tune);
+            const GemvPlan pl = whz_gemv_plan(rate, c.rows, cols, c.lo, c.hi, ctx->num_cus, &ctx->gemv_tune);
             if (pl.nslab > 1)
                 part_need = std::max(part_need, (size_t)pl.nslab * pl.part_rows());
         }
@@ -224,7 +224,7 @@ extern "C" wh_status wh_gemv_host(wh_ctx* ctx, const void* h_code, uint32_t rows
             if (e != hipSuccess)
                 break;
             const Chunk c = chunk_at((uint32_t)b0, b1, rows, row_begin, row_end);
-            const GemvPlan pl = whz_gemv_plan(c.rows, cols, c.lo, c.hi, ctx->num_cus, &ctx->gemv_tune);
+            const GemvPlan pl = whz_gemv_plan(rate, c.rows, cols, c.lo, c.hi, ctx->num_cus, &ctx->gemv_tune);
             e = whz_gemv(rate, pl, mode, p->buf[k], d_u, d_y + (c.r0 + c.lo - row_begin),
                          pl.nslab > 1 ? ctx->part : nullptr, st);
             if (e == hipSuccess)

@@ -105,7 +105,7 @@ extern "C" wh_status wh_gemv_noalloc(wh_ctx* ctx, wh_mat m, const float* d_u, fl
                                                        : AccMode::Fp64;
         // the same launch plan as wh_gemv, so the two give the same y
         const GemvPlan pl =
-            whz_gemv_plan(mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
+            whz_gemv_plan(mat.desc.rate, mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
         double* part = nullptr;
         if (pl.nslab > 1) {
             if ((uint64_t)pl.nslab * pl.part_rows() > kScratchDoubles)

@@ -23,6 +23,12 @@
 //               last chunk).  So a request waits at most one chunk for the
 //               pass it joins, not for a whole pass to end, and requests that
 //               arrive while others run share the same launches
+//   holding     while another matrix's scan is running late (its requests
+//               cannot meet their deadlines any more), a matrix with no scan
+//               under way holds its queued requests back as long as the most
+//               urgent can still wait (its pass and a margin before the
+//               deadline), so that more requests share each of its passes
+//               and the late scan keeps more of the device
 //   order       each matrix has at most two chunk launches in flight, on its
 //               own stream; the streams of different matrices run side by
 //               side, so a small matrix's pass is never queued behind a long
@@ -66,7 +72,9 @@ uint64_t now_ns()
     return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
 
-constexpr uint32_t kBuckets[] = {1, 2, 4, 8, 16, 32, 64};
+// right-hand-side buckets of the launch graphs: the multi-RHS kernel's cost
+// steps with each group of 16
+constexpr uint32_t kBuckets[] = {1, 2, 4, 8, 16, 32, 48, 64};
 constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
 // chunk launches of one matrix in flight on the device (the second keeps
 // its stream busy while the worker notices the first one end)
@@ -86,7 +94,7 @@ struct Req {
     uint64_t t_arrive = 0, t_start = 0, t_done = 0;
     wh_status status = WH_PENDING;
     uint32_t batch_size = 0; // requests that joined the scan at the same launch
-    uint32_t col0 = 0;       // first of its k consecutive columns in the slot
+    uint64_t cols = 0;       // its k columns of the slot (bit c = column c), vector i in the i-th
     uint32_t left = 0;       // chunk launches still to issue for it
 };
 
@@ -150,10 +158,10 @@ size_t slot_partials(const Matrix& m, const wh_ctx* ctx)
 {
     size_t n = 0;
     for (const auto& c : serve_chunks(m, ctx->serve_chunk_values)) {
-        const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
+        const GemvPlan gp = whz_gemv_plan(m.desc.rate, m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
         if (gp.nslab > 1)
             n = std::max(n, (size_t)gp.nslab * gp.part_rows());
-        for (uint32_t k = 16; k <= kMaxRhs; k += 16) { // the plan depends on k's group count
+        for (uint32_t k = 16; k <= kMaxRhs; k += 16) { // the plan and workspace depend on k
             const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k,
                                               ctx->gemv_tune.mrhs_slabs);
             n = std::max(n, mrhs_workspace(mp, k, false).total);
@@ -240,7 +248,7 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
                 return WH_ERR_DEVICE;
             hipError_t e;
             if (k == 1) {
-                const GemvPlan gp = whz_gemv_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
+                const GemvPlan gp = whz_gemv_plan(m.desc.rate, m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
                 e = whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, ms.U, ms.Y + c.first, ms.part, ms.stream);
             } else {
                 const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k,
@@ -261,17 +269,42 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
     return WH_OK;
 }
 
-// The first of k consecutive free columns, or -1.
-int free_run(uint64_t used, uint32_t k)
+// The k lowest free columns (any, not necessarily consecutive: a request
+// never waits for a run of them to come free), or 0 if fewer are free.
+uint64_t take_cols(uint64_t used, uint32_t k)
 {
-    const uint64_t want = k >= 64 ? ~0ull : ((1ull << k) - 1);
-    for (uint32_t c = 0; c + k <= 64; ++c)
-        if (((used >> c) & want) == 0)
-            return (int)c;
-    return -1;
+    uint64_t free = ~used, out = 0;
+    for (uint32_t i = 0; i < k; ++i) {
+        if (!free)
+            return 0;
+        const uint64_t low = free & (0 - free);
+        out |= low;
+        free ^= low;
+    }
+    return out;
 }
 
-uint64_t run_mask(uint32_t c0, uint32_t k) { return (k >= 64 ? ~0ull : ((1ull << k) - 1)) << c0; }
+// Copies between a request's k contiguous vectors of n floats at `req` and
+// its columns of a slot buffer (column c at slot + c * n), one copy per run of
+// consecutive columns.  to_slot: request -> slot.
+hipError_t copy_cols(float* slot, const float* req_src, float* req_dst, uint64_t mask, size_t n, bool to_slot,
+                     hipMemcpyKind kind, hipStream_t st)
+{
+    size_t i = 0; // vectors of the request done
+    while (mask) {
+        const uint32_t c0 = (uint32_t)__builtin_ctzll(mask);
+        const uint64_t from = mask >> c0;
+        const uint32_t len = ~from ? (uint32_t)__builtin_ctzll(~from) : 64u - c0;
+        const size_t bytes = (size_t)len * n * sizeof(float);
+        const hipError_t e = to_slot ? hipMemcpyAsync(slot + (size_t)c0 * n, req_src + i * n, bytes, kind, st)
+                                     : hipMemcpyAsync(req_dst + i * n, slot + (size_t)c0 * n, bytes, kind, st);
+        if (e != hipSuccess)
+            return e;
+        i += len;
+        mask &= len >= 64 ? 0ull : ~(((1ull << len) - 1) << c0);
+    }
+    return hipSuccess;
+}
 
 // Called with sv->mu held.  Issues the next chunk launch of a matrix: queued
 // requests join (FIFO, while columns last), the chunk's graph runs over every
@@ -287,16 +320,15 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
     std::vector<uint64_t> joined;
     while (!ms.pending.empty()) {
         Req& r = sv->reqs[ms.pending.front()];
-        const int c0 = free_run(ms.used, r.r.k);
-        if (c0 < 0)
+        const uint64_t mask = take_cols(ms.used, r.r.k);
+        if (!mask)
             break;
-        r.col0 = (uint32_t)c0;
+        r.cols = mask;
         r.left = nchunks;
         r.t_start = t0;
-        ms.used |= run_mask(r.col0, r.r.k);
+        ms.used |= mask;
         const hipMemcpyKind kind = r.r.u_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-        if (hipMemcpyAsync(ms.U + (size_t)r.col0 * cols, r.r.U, (size_t)r.r.k * cols * sizeof(float), kind,
-                           ms.stream) != hipSuccess)
+        if (copy_cols(ms.U, r.r.U, nullptr, mask, cols, true, kind, ms.stream) != hipSuccess)
             return WH_ERR_DEVICE;
         joined.push_back(ms.pending.front());
         ms.active.push_back(ms.pending.front());
@@ -325,10 +357,9 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
             continue;
         }
         const hipMemcpyKind kind = r.r.y_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        if (hipMemcpyAsync(r.r.Y, ms.Y + (size_t)r.col0 * rows, (size_t)r.r.k * rows * sizeof(float), kind,
-                           ms.stream) != hipSuccess)
+        if (copy_cols(ms.Y, nullptr, r.r.Y, r.cols, rows, false, kind, ms.stream) != hipSuccess)
             return WH_ERR_DEVICE;
-        ms.used &= ~run_mask(r.col0, r.r.k); // later users of these columns come after this copy
+        ms.used &= ~r.cols; // later users of these columns come after this copy
         l.done.push_back(ms.active[i]);
     }
     ms.active.resize(keep);
@@ -338,14 +369,38 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
     return WH_OK;
 }
 
+// The hold: a matrix's queued requests start at the latest when its pass
+// (measured chunk times, `kHoldPasses` of them to allow for sharing the
+// device) and kHoldMarginNs remain before the most urgent one's deadline.
+constexpr double kHoldPasses = 2.0;
+constexpr double kHoldMarginNs = 5e5;
+
 // Called with sv->mu held.  How urgent a matrix's next chunk launch is: the
 // earliest deadline among its requests that can still meet theirs
 // (`feasible`), and the least remaining scan time of its other requests
-// (`late`, ns).  Returns false if it has nothing to launch.
-bool urgency(Server* sv, const MatServe& ms, uint64_t now, uint64_t& feasible, uint64_t& late)
+// (`late`, ns).  Returns false if it has nothing to launch now; then
+// `hold_until` is when its held requests must start (UINT64_MAX: nothing
+// held).  `hold`: another matrix's scan is running late.
+bool urgency(Server* sv, const MatServe& ms, uint64_t now, bool hold, uint64_t& feasible, uint64_t& late,
+             uint64_t& hold_until)
 {
-    feasible = late = UINT64_MAX;
+    feasible = late = hold_until = UINT64_MAX;
     const double chunk_ns = ms.chunk_ms * 1e6;
+    if (hold && ms.active.empty() && !ms.pending.empty()) {
+        const double pass_ns = chunk_ns * (double)ms.chunks.size();
+        double start_by = 1e300;
+        uint32_t k = 0;
+        for (uint64_t t : ms.pending) {
+            const Req& r = sv->reqs.at(t);
+            k += r.r.k;
+            const double due = r.r.deadline_ns ? (double)(r.t_arrive + r.r.deadline_ns) : 0.0;
+            start_by = std::min(start_by, due - kHoldPasses * pass_ns - kHoldMarginNs);
+        }
+        if (k < kMaxRhs && (double)now < start_by) {
+            hold_until = (uint64_t)start_by;
+            return false;
+        }
+    }
     auto consider = [&](const Req& r, uint32_t left) {
         const uint64_t due = r.r.deadline_ns ? r.t_arrive + r.r.deadline_ns : UINT64_MAX;
         const double rest = left * chunk_ns;
@@ -359,7 +414,7 @@ bool urgency(Server* sv, const MatServe& ms, uint64_t now, uint64_t& feasible, u
     bool joinable = false;
     if (!ms.pending.empty()) {
         const Req& head = sv->reqs.at(ms.pending.front());
-        if (free_run(ms.used, head.r.k) >= 0) {
+        if (take_cols(ms.used, head.r.k)) {
             joinable = true;
             consider(head, (uint32_t)ms.chunks.size());
         }
@@ -414,17 +469,35 @@ void worker_main(Server* sv)
         }
         // dispatch: earliest feasible deadline first, then late work with
         // the least scan left; each matrix up to kMaxInflight launches
+        uint64_t wake = UINT64_MAX; // the earliest end of a hold
         while (sv->sticky == WH_OK) {
             const uint64_t now = now_ns();
             MatServe* pick = nullptr;
             uint64_t best_f = UINT64_MAX, best_l = UINT64_MAX;
+            wake = UINT64_MAX;
+            // the scans running late: none of their requests can still meet
+            // its deadline
+            std::vector<const MatServe*> late_scans;
+            for (const auto& mv : sv->mats) {
+                const MatServe& o = mv.second;
+                if (!o.usable || o.active.empty())
+                    continue;
+                uint64_t f = UINT64_MAX, l, h;
+                (void)urgency(sv, o, now, false, f, l, h);
+                if (f == UINT64_MAX)
+                    late_scans.push_back(&o);
+            }
             for (auto& mv : sv->mats) {
                 MatServe& ms = mv.second;
                 if (!ms.usable || ms.inflight.size() >= kMaxInflight || ms.spare.empty())
                     continue;
-                uint64_t f, l;
-                if (!urgency(sv, ms, now, f, l))
+                const bool hold = std::any_of(late_scans.begin(), late_scans.end(),
+                                              [&](const MatServe* o) { return o != &ms; });
+                uint64_t f, l, h;
+                if (!urgency(sv, ms, now, hold, f, l, h)) {
+                    wake = std::min(wake, h);
                     continue;
+                }
                 if (!pick || f < best_f || (f == best_f && l < best_l)) {
                     pick = &ms;
                     best_f = f;
@@ -441,9 +514,13 @@ void worker_main(Server* sv)
             }
             ++inflight;
         }
-        // sleep briefly while launches run; block while idle
-        if (inflight)
+        // sleep briefly while launches run or a hold is about to end; block
+        // while idle
+        const uint64_t now = now_ns();
+        if (inflight || wake <= now + 20000)
             sv->cv.wait_for(lk, std::chrono::microseconds(20));
+        else if (wake != UINT64_MAX)
+            sv->cv.wait_for(lk, std::chrono::nanoseconds(std::min<uint64_t>(wake - now, 5000000)));
         else
             sv->cv.wait_for(lk, std::chrono::milliseconds(5));
     }

@@ -263,15 +263,16 @@ wh_status wh_destroy(wh_ctx* ctx)
 }
 
 wh_status wh_gemv_plan_info(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
-                            uint32_t* out8)
+                            uint32_t rate, uint32_t* out9)
 {
-    if (!out8 || rows == 0 || cols == 0 || row_begin > row_end || row_end > rows)
+    if (!out9 || rows == 0 || cols == 0 || row_begin > row_end || row_end > rows || !whz_rate_supported(rate))
         return WH_ERR_INVALID;
     GemvTuning none;
-    const GemvPlan pl = whz_gemv_plan(rows, cols, row_begin, row_end, num_cus, &none);
-    const uint32_t v[8] = {1u << pl.lg, pl.rpg, pl.ntiles, pl.nslab, pl.slab_bc, pl.bi_begin, pl.bi_end, pl.skip};
-    for (int i = 0; i < 8; ++i)
-        out8[i] = v[i];
+    const GemvPlan pl = whz_gemv_plan(rate, rows, cols, row_begin, row_end, num_cus, &none);
+    const uint32_t v[9] = {1u << pl.lg, pl.rpg, pl.ntiles,  pl.nslab, pl.slab_bc,
+                           pl.bi_begin, pl.bi_end, pl.skip, pl.lanes};
+    for (int i = 0; i < 9; ++i)
+        out9[i] = v[i];
     return WH_OK;
 }
 
@@ -415,7 +416,7 @@ wh_status wh_gemv(wh_ctx* ctx, wh_mat m, const float* d_u, float* d_y, uint32_t 
         }
         if (mat.desc.fmt == WH_FMT_ZFP_FIXED_RATE) {
             const GemvPlan pl =
-                whz_gemv_plan(mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
+                whz_gemv_plan(mat.desc.rate, mat.desc.rows, mat.desc.cols, row_begin, row_end, ctx->num_cus, &ctx->gemv_tune);
             double* part = nullptr;
             if (pl.nslab > 1) {
                 wh_status s2 = ensure_partials(ctx, (size_t)pl.nslab * pl.part_rows(), st);

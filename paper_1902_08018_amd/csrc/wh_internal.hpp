@@ -12,18 +12,23 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // Accumulation of the cross-block row sums.
 enum class AccMode { Fp64, TwoSum, PaperMp };
 
-// Workgroup size of the fused GEMV; the most block rows one lane group takes
-// per tile; and the LDS doubles that hold the groups' row sums (slots x 4 x
-// rows per group: one slot per wave, or per group of fewer than 64 lanes).
+// Workgroup size of the fused GEMV: 512 lanes, or 768 from 10 bits/value up,
+// where a lane stages 8 or more words of LDS and two 768-lane workgroups (24
+// waves) fit a CU where only two 512-lane ones did.  The most lanes a group
+// spans (the largest power of two dividing both sizes is 256 for 768); the
+// most block rows one lane group takes per tile.  The LDS doubles that hold
+// the groups' row sums (slots x 4 x rows per group: one slot per wave, or per
+// group of fewer than 64 lanes) are as many as the workgroup's lanes.
 constexpr uint32_t kGemvLanes = 512;
+constexpr uint32_t gemv_wg_lanes(uint32_t rate) { return rate >= 10 ? 768u : 512u; }
+constexpr uint32_t gemv_max_lg(uint32_t lanes) { return lanes == 768u ? 8u : 9u; }
 constexpr int kGemvMaxRowsPerGroup = 4;
-constexpr int kGemvRedDoubles = 512;
-constexpr uint32_t gemv_slots(uint32_t lg) { return lg >= 6 ? kGemvLanes / 64 : kGemvLanes >> lg; }
+constexpr uint32_t gemv_slots(uint32_t lg, uint32_t lanes) { return lg >= 6 ? lanes / 64 : lanes >> lg; }
 
 // Launch geometry of the fused GEMV over rows [row_begin, row_end), i.e.
-// block-rows [bi_begin, bi_end).  The lanes of a workgroup form groups of
-// 2^lg; each group sweeps one block row's slab of block columns, and a tile is
-// (512 >> lg) groups x rpg block rows.  A matrix whose sides are not multiples
+// block-rows [bi_begin, bi_end).  The `lanes` lanes of a workgroup form groups
+// of 2^lg; each group sweeps one block row's slab of block columns, and a tile
+// is (lanes >> lg) groups x rpg block rows.  A matrix whose sides are not multiples
 // of 4 ends in partial blocks: the stream codes them edge-padded, u is taken as
 // zero past the last column, and rows outside the range are not written.
 struct GemvPlan {
@@ -38,6 +43,7 @@ struct GemvPlan {
     uint32_t lg;       // log2 of the lanes per group (2 .. 9)
     uint32_t rpg;      // block rows per group and tile (1 .. kGemvMaxRowsPerGroup)
     uint32_t skip;     // row_begin % 4: rows of the first block row before the range
+    uint32_t lanes;    // workgroup lanes (gemv_wg_lanes of the rate)
     // FP64 partials per slab and right-hand side: the range's block-rows
     uint32_t part_rows() const { return (bi_end - bi_begin) * 4; }
 };
@@ -84,8 +90,8 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
 // `ws`: mrhs_workspace(pl, k, bf16).total doubles of device memory
 hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu,
                     uint32_t k, float* Y, uint32_t ldy, double* part, hipStream_t st);
-GemvPlan whz_gemv_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
-                       const GemvTuning* tune = nullptr);
+GemvPlan whz_gemv_plan(uint32_t rate, uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end,
+                       int num_cus, const GemvTuning* tune = nullptr);
 // Slabs of block columns for a kernel whose `lanes` lanes sweep each block row
 // of a tile of `tile_rows` block rows together (the block-scaled FP8 GEMV).
 GemvPlan block_slab_plan(uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t lanes,

@@ -121,37 +121,39 @@ uint32_t set_slabs(GemvPlan& pl, uint32_t nslab, uint32_t width)
 //    lane; past 2^27 blocks, about 8192 workgroups of up to 48 blocks per
 //    lane, which keeps the FP64 partial sums small (the times differ by under
 //    1 % there).
-GemvPlan whz_gemv_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus,
-                       const GemvTuning* tune)
+GemvPlan whz_gemv_plan(uint32_t rate, uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end,
+                       int num_cus, const GemvTuning* tune)
 {
     (void)rows;
     (void)num_cus;
     GemvPlan pl = range_plan(cols, row_begin, row_end);
+    const uint32_t lanes = gemv_wg_lanes(rate), max_lg = gemv_max_lg(lanes);
+    pl.lanes = lanes;
     const uint32_t nbr = pl.bi_end - pl.bi_begin;
     uint32_t lg = 3;
     while (lg > 2 && (1u << lg) > pl.nbc) // fewer block columns than lanes
         --lg;
     for (;;) { // the narrowest groups whose tiles are at least 90 % full
-        const uint64_t tile = kGemvLanes >> lg;
+        const uint64_t tile = lanes >> lg;
         const uint64_t span = (uint64_t)ceil_div(nbr, tile) * tile;
-        if (lg >= 9 || 10 * (uint64_t)nbr >= 9 * span)
+        if (lg >= max_lg || 10 * (uint64_t)nbr >= 9 * span)
             break;
         ++lg;
     }
     uint32_t rpg = 1;
     if (tune && tune->lanes) {
         lg = 2;
-        while ((1u << lg) < tune->lanes && lg < 9)
+        while ((1u << lg) < tune->lanes && lg < max_lg)
             ++lg;
     }
-    if (tune && tune->rows && gemv_slots(lg) * 4 * tune->rows <= (uint32_t)kGemvRedDoubles)
+    if (tune && tune->rows && gemv_slots(lg, lanes) * 4 * tune->rows <= lanes)
         rpg = tune->rows;
     pl.lg = lg;
     pl.rpg = rpg;
-    pl.ntiles = ceil_div(nbr, (uint64_t)(kGemvLanes >> lg) * rpg);
+    pl.ntiles = ceil_div(nbr, (uint64_t)(lanes >> lg) * rpg);
     const uint32_t G = 1u << lg;
     const uint64_t blocks = (uint64_t)nbr * pl.nbc;
-    const uint64_t per_wg = (uint64_t)kGemvLanes;
+    const uint64_t per_wg = (uint64_t)lanes;
     uint64_t iters = std::min<uint64_t>(16, std::max<uint64_t>(3, (blocks + per_wg * 1024) / (per_wg * 2048)));
     if (blocks > (1ull << 27))
         iters = std::min<uint64_t>(48, blocks / (per_wg * 8192));
@@ -167,6 +169,7 @@ GemvPlan block_slab_plan(uint32_t cols, uint32_t row_begin, uint32_t row_end, in
                          uint32_t tile_rows)
 {
     GemvPlan pl = range_plan(cols, row_begin, row_end);
+    pl.lanes = lanes;
     const uint32_t nbr = pl.bi_end - pl.bi_begin;
     pl.ntiles = ceil_div(nbr, tile_rows);
     // enough workgroups to fill the chip several times over
@@ -220,6 +223,11 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
         nslab = 1;
     if (max_slabs >= 8)
         nslab = (nslab + 7) / 8 * 8;
+    // the partials grow with k: at most 128 slab x right-hand-side rows
+    // (8 slabs up to 16 right-hand sides, 2 for 64)
+    const uint32_t cap = std::max<uint32_t>(1, 128 / std::max<uint32_t>(k, 1));
+    if (nslab > cap)
+        nslab = cap;
     if (slabs)
         nslab = slabs;
     if (nslab > max_slabs)

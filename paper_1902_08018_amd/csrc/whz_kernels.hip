@@ -236,7 +236,9 @@ struct TwoSumAcc {
     }
 };
 
-constexpr int kGemvThreads = (int)kGemvLanes;
+// workgroup lanes of the fused GEMV for NW words per block (2 NW bits/value)
+template <int NW>
+constexpr int kGemvThreads = (int)gemv_wg_lanes(2 * NW);
 
 // L = B^-1 = (1/16) [[4, 4, 4, 4], [5, 1, -1, -5], [-4, 4, 4, -4],
 // [-2, 6, -6, 2]] (the forward lift's linear part) on (a, b, c, d).
@@ -304,23 +306,24 @@ __device__ __forceinline__ void exact_block_coeffs(const uint32_t (&cf)[16], int
 // lane has blocks to decode.  Output row i of the range is matrix row
 // 4 * bi_begin + skip + i.
 template <int NW, typename Acc>
-__global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __restrict__ stream,
+__global__ void __launch_bounds__(kGemvThreads<NW>) gemv_kernel(const uint32_t* __restrict__ stream,
                                                         const float* __restrict__ u, float* __restrict__ y,
                                                         double* __restrict__ part, uint32_t nbc, uint32_t bi_begin,
                                                         uint32_t bi_end, uint32_t slab_bc, uint32_t nslab,
                                                         uint32_t cols, uint32_t nrows, uint32_t lg, uint32_t rpg,
                                                         uint32_t skip)
 {
-    __shared__ uint32_t lds[kGemvThreads * kStagedWords<NW>];
+    constexpr int THREADS = kGemvThreads<NW>;
+    __shared__ uint32_t lds[THREADS * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
     // a group's four row sums per tile row: one slot per wave when a group
     // spans whole waves, else one per group
-    __shared__ double red[kGemvRedDoubles];
+    __shared__ double red[THREADS];
     uint32_t* row = lds + threadIdx.x;
-    clear_pad<NW, kGemvThreads>(row);
-    load_section_table<kGemvThreads>(tab);
+    clear_pad<NW, THREADS>(row);
+    load_section_table<THREADS>(tab);
 
-    const uint32_t G = 1u << lg, groups = (uint32_t)kGemvThreads >> lg;
+    const uint32_t G = 1u << lg, groups = (uint32_t)THREADS >> lg;
     const uint32_t grp = threadIdx.x >> lg, gl = threadIdx.x & (G - 1);
     const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
     const uint32_t bi0 = bi_begin + tile * groups * rpg;
@@ -357,13 +360,13 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
                 uu.w = 0.0f;
             }
             uint32_t w[NW];
-            stage_block<NW, kGemvThreads>(row, srow + (uint64_t)bj * NW, w);
+            stage_block<NW, THREADS>(row, srow + (uint64_t)bj * NW, w);
             int emax;
             uint32_t iv[16];
             if constexpr (Acc::kPerProduct) {
                 // Fig. 7: each FP32 product of the decoded value and u is
                 // added to the FP64 sum on its own
-                decode_block_ints<NW, kGemvThreads>(row, tab, w[0], emax, iv);
+                decode_block_ints<NW, THREADS>(row, tab, w[0], emax, iv);
                 const int k = emax - 30;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -376,7 +379,7 @@ __global__ void __launch_bounds__(kGemvThreads) gemv_kernel(const uint32_t* __re
                 // coefficients against B^T u (FP32); B is applied once to the
                 // row group's sums below
                 bool cut;
-                decode_block_coeffs<NW, kGemvThreads>(row, tab, w[0], emax, iv, cut);
+                decode_block_coeffs<NW, THREADS>(row, tab, w[0], emax, iv, cut);
                 float ut[4];
                 lin_bt_u<float>(uu.x, uu.y, uu.z, uu.w, ut);
                 const int k = emax - 30;
@@ -867,8 +870,10 @@ template <int NW, typename Acc>
 hipError_t launch_gemv_t(const GemvPlan& pl, const uint32_t* s, const float* u, float* y, double* part,
                          hipStream_t st)
 {
-    hipLaunchKernelGGL((gemv_kernel<NW, Acc>), dim3(pl.ntiles * pl.nslab), dim3(kGemvThreads), 0, st, s, u, y, part,
-                       pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab, pl.cols, pl.nrows, pl.lg, pl.rpg,
+    if (pl.lanes != (uint32_t)kGemvThreads<NW>) // a plan made for another rate
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemv_kernel<NW, Acc>), dim3(pl.ntiles * pl.nslab), dim3(kGemvThreads<NW>), 0, st, s, u, y,
+                       part, pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab, pl.cols, pl.nrows, pl.lg, pl.rpg,
                        pl.skip);
     return hipGetLastError();
 }

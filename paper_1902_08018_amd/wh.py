@@ -74,7 +74,7 @@ _sig = {
     "wh_gemv_noalloc": ([_P, _U64, _P, _P, _U32, _U32, _U32, _P], _I32),
     "wh_gemv_batched": ([_P, _U64, _P, ctypes.c_int, _U32, _U32, _P, _U32, _U32, _P], _I32),
     "wh_gemv_host": ([_P, _P, _U32, _U32, _U32, _P, _P, _U32, _U32, _U32, _U32, _P], _I32),
-    "wh_gemv_plan_info": ([_U32, _U32, _U32, _U32, ctypes.c_int, ctypes.POINTER(_U32)], _I32),
+    "wh_gemv_plan_info": ([_U32, _U32, _U32, _U32, ctypes.c_int, _U32, ctypes.POINTER(_U32)], _I32),
     "wh_var_index_bytes": ([_U32, _U32], _U64),
     "wh_var_capacity_bytes": ([_U32, _U32], _U64),
     "wh_encode_var": ([_P, _U32, _U32, _I32, _U32, _P, _U64, ctypes.POINTER(_U64)], _I32),
@@ -259,11 +259,11 @@ def wh_encode_var(M, fmt: int, rate: int):
 
 
 def wh_gemv_plan_info(rows: int, cols: int, row_begin: int = 0, row_end: int | None = None,
-                      num_cus: int = 256) -> dict:
+                      num_cus: int = 256, rate: int = 8) -> dict:
     row_end = rows if row_end is None else row_end
-    out = (_U32 * 8)()
-    _check(_lib.wh_gemv_plan_info(rows, cols, row_begin, row_end, num_cus, out), "wh_gemv_plan_info")
-    keys = ("lanes", "rows_per_group", "ntiles", "nslab", "slab_bc", "bi_begin", "bi_end", "skip")
+    out = (_U32 * 9)()
+    _check(_lib.wh_gemv_plan_info(rows, cols, row_begin, row_end, num_cus, rate, out), "wh_gemv_plan_info")
+    keys = ("lanes", "rows_per_group", "ntiles", "nslab", "slab_bc", "bi_begin", "bi_end", "skip", "wg_lanes")
     return dict(zip(keys, [int(x) for x in out]))
 
 

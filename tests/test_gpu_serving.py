@@ -13,6 +13,7 @@
                  within 1e-6 of the oracle, k = 1 and multi-RHS
   cyclic scan    a request submitted during another's pass joins it at the
                  next chunk launch (starts before that pass ends)
+  columns        a request takes any free columns of its matrix's slot
   buffers        pageable host U or Y is refused at submit
 """
 import time
@@ -293,7 +294,7 @@ def test_requests_join_a_pass_in_progress(monkeypatch):
         YA = torch.full((2, sp.rows), -7.0, device="cuda")
         YB = torch.full((3, sp.rows), -7.0, device="cuda")
         torch.cuda.synchronize()
-        ta = wh.wh_submit(ctx, make_request(mat, UA, YA))
+        ta = wh.wh_submit(ctx, make_request(mat, UA, YA, deadline_ns=1))  # late at once: not held back
         time.sleep(0.0005)
         tb = wh.wh_submit(ctx, make_request(mat, UB, YB))
         res = wait(ctx, [ta, tb])
@@ -324,3 +325,42 @@ def test_pageable_host_buffers_are_refused(serving):
     with pytest.raises(wh.WhError) as ei:
         wh.wh_submit(ctx, make_request(mats[0], U.pin_memory(), Y))
     assert ei.value.status == wh.WH_ERR_INVALID
+
+
+def test_requests_take_scattered_columns(monkeypatch):
+    """A request takes any free right-hand-side columns of the matrix's slot,
+    not only a consecutive run: C joins while B still holds columns in the
+    middle of those A freed, and every result is right."""
+    monkeypatch.setenv("WH_SERVE_CHUNK_VALUES", str(8 * 1024))  # 256 chunks of 2048 x 1024
+    ctx = wh.wh_create(0, 256 << 20)
+    try:
+        sp = SPECS[1]
+        s = oracle.encode(synth.matrix(sp), 8)
+        d = torch.from_numpy(s).cuda()
+        mat = wh.wh_load_compressed(ctx, sp.rows, sp.cols, wh.WH_FMT_ZFP_FIXED_RATE, 8, d)
+        ref_M = oracle.decode(s, sp.rows, sp.cols, 8).astype(np.float64)
+        U0 = torch.from_numpy(synth.uniform(sp.cols, seed=900).reshape(1, -1)).cuda()
+        Y0 = torch.empty((1, sp.rows), device="cuda")
+        wait(ctx, [wh.wh_submit(ctx, make_request(mat, U0, Y0, deadline_ns=1))])  # slot built, pass timed
+        bufs = {}
+        for name, k, seed in (("A", 3, 901), ("B", 2, 902), ("C", 5, 903)):
+            bufs[name] = (torch.from_numpy(synth.uniform(k * sp.cols, seed=seed).reshape(k, -1)).cuda(),
+                          torch.full((k, sp.rows), -7.0, device="cuda"))
+        torch.cuda.synchronize()
+        ta = wh.wh_submit(ctx, make_request(mat, *bufs["A"], deadline_ns=1))
+        time.sleep(0.004)  # B joins part of the way through A's pass
+        tb = wh.wh_submit(ctx, make_request(mat, *bufs["B"], deadline_ns=1))
+        ra = wait(ctx, [ta])[ta]
+        tc = wh.wh_submit(ctx, make_request(mat, *bufs["C"], deadline_ns=1))
+        res = wait(ctx, [tb, tc])
+        rb, rc = res[tb], res[tc]
+        print(f"A done {(ra[3] - ra[1]) * 1e-6:.2f} ms, B start {(rb[2] - ra[1]) * 1e-6:.2f} done "
+              f"{(rb[3] - ra[1]) * 1e-6:.2f}, C start {(rc[2] - ra[1]) * 1e-6:.2f}")
+        assert rc[2] < rb[3], "C did not join while B was under way"
+        torch.cuda.synchronize()
+        for U, Y in bufs.values():
+            r = U.cpu().numpy().astype(np.float64) @ ref_M.T
+            e = np.linalg.norm(Y.cpu().numpy() - r, axis=1) / np.linalg.norm(r, axis=1)
+            assert e.max() <= 1e-6
+    finally:
+        wh.wh_destroy(ctx)

@@ -30,8 +30,8 @@ def rel_l2(y, ref):
     return float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
 
 
-def scratch_doubles(rows, cols, r0, r1):
-    p = wh.wh_gemv_plan_info(rows, cols, r0, r1, torch.cuda.get_device_properties(0).multi_processor_count)
+def scratch_doubles(rows, cols, r0, r1, rate):
+    p = wh.wh_gemv_plan_info(rows, cols, r0, r1, torch.cuda.get_device_properties(0).multi_processor_count, rate)
     return p["nslab"] * (p["bi_end"] - p["bi_begin"]) * 4 if p["nslab"] > 1 else 0, p
 
 
@@ -50,7 +50,7 @@ def test_noalloc_two_calls_match_gemv(gpu_ctx, flags):
     cases = [(synth.MatrixSpec(1024, 8192, 64, 8.0), 8, 3, 1021),
              (synth.MatrixSpec(256, 2048, 32, 8.0), 16, 0, 256)]
     for spec, rate, r0, r1 in cases:
-        need, plan = scratch_doubles(spec.rows, spec.cols, r0, r1)
+        need, plan = scratch_doubles(spec.rows, spec.cols, r0, r1, rate)
         print(f"case {spec.rows}x{spec.cols} rate {rate} rows [{r0},{r1}) plan {plan} scratch doubles {need}",
               flush=True)
         assert 0 < need * 8 <= wh.WH_NOALLOC_SCRATCH_BYTES
@@ -103,7 +103,7 @@ def test_noalloc_rejects_a_plan_beyond_the_array():
 def test_noalloc_captured_in_a_graph(gpu_ctx):
     spec = synth.MatrixSpec(512, 8192, 64, 8.0)
     rate = 8
-    need, plan = scratch_doubles(spec.rows, spec.cols, 0, spec.rows)
+    need, plan = scratch_doubles(spec.rows, spec.cols, 0, spec.rows, rate)
     assert need > 0, plan
     mat, s = load(gpu_ctx, spec, rate)
     rng = np.random.default_rng(7)
