@@ -626,7 +626,7 @@ SERVING_SPECS = {
 
 
 def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measured=20000, warmup_s=1.0,
-                  rate_hz=2000.0, deadline_ms=5.0, budget_mb=160, seed=0, shed=0):
+                  rate_hz=2000.0, deadline_ms=5.0, budget_mb=512, seed=0, shed=0):
     """Open-loop Poisson load against resident rate-8 matrices (target
     uniform over `names`); k ~ U{1..8} dose vectors in pinned host memory;
     latency measured from the scheduled arrival time."""

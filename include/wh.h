@@ -124,7 +124,7 @@ const char *wh_status_str(wh_status st);
  * (column slabs), read here, fix the compressed GEMV's launch shape instead
  * of the planner's choice, and WH_MRHS_SLABS the multi-RHS kernel's column
  * slabs (for launch-shape sweeps); invalid values are ignored.  Results stay within the stated tolerances for every shape.
- * WH_SERVE_CHUNK_VALUES (a positive integer, default 2^29) bounds the matrix
+ * WH_SERVE_CHUNK_VALUES (a positive integer, default 2^28) bounds the matrix
  * values one serving launch covers: the serving loop runs each pass over a
  * larger matrix as launches over consecutive row chunks, so that batches of
  * other matrices get the device between chunks.  WH_SERVE_SHED=F (an integer

@@ -9,41 +9,45 @@
 //   submit      any thread; the request is validated (host buffers must be
 //               page-locked), stamped and queued.  The first request for a
 //               matrix sets up its slot outside the loop's lock
-//   slot        per matrix, carved out of the context's HBM budget: U and Y
-//               for 64 right-hand-side columns, the FP64 slab partials of its
-//               plans, and one pre-instantiated hipGraph per (row chunk,
-//               k-bucket 1, 2, 4, ..., 64).  A request that can never fit is
-//               rejected at submit
+//   slot        per matrix, carved out of the context's HBM budget: U, Y and
+//               a staging copy of Y for 64 right-hand-side columns, the FP64
+//               slab partials of its plans, and one pre-instantiated hipGraph
+//               per (row chunk, k-bucket 1, 2, 4, ..., 64).  A request that
+//               can never fit is rejected at submit
 //   cyclic scan each matrix's rows are split into chunks of at most
 //               ctx->serve_chunk_values values.  The loop launches one chunk
 //               at a time, cycling through them, over every column held by a
 //               request.  A queued request joins at the next chunk launch: its
 //               U is copied into free columns, and it is complete once the
-//               scan has gone round once from there (Y copied back after its
-//               last chunk).  So a request waits at most one chunk for the
-//               pass it joins, not for a whole pass to end, and requests that
-//               arrive while others run share the same launches
+//               scan has gone round once from there.  So a request waits at
+//               most one chunk for the pass it joins, not for a whole pass to
+//               end, and requests that arrive while others run share the same
+//               launches
 //   holding     while another matrix's scan is running late (its requests
 //               cannot meet their deadlines any more), a matrix with no scan
 //               under way holds its queued requests back as long as the most
-//               urgent can still wait (its pass and a margin before the
+//               urgent can still wait (its pass, the launches that may be
+//               ahead of it and between its chunks, and a margin before the
 //               deadline), so that more requests share each of its passes
-//               and the late scan keeps more of the device
-//   order       each matrix has at most two chunk launches in flight, on its
-//               own stream; the streams of different matrices run side by
-//               side, so a small matrix's pass is never queued behind a long
-//               scan of a big one.  Launches are issued in order of urgency:
-//               the earliest deadline among requests that can still meet
-//               theirs (estimated from the measured chunk time), then late
-//               work, least remaining scan first
-//   completion  the worker polls each launch's event; the requests whose last
-//               chunk it was are stamped done
+//   order       every launch goes to one stream of the loop's, at most two in
+//               flight, so each runs alone on the device: the loop, not the
+//               hardware, decides how the device is shared, and a launch's
+//               measured time is what the next one of its chunk and bucket
+//               will take.  Requests that can still meet their deadlines go
+//               by the latest time their next chunk may start (the earliest
+//               first).  A scan running late is paced at one chunk per
+//               kLatePace of its chunk times while that work waits (about
+//               half the device), and takes what is left over
+//   copies      vectors in and results out travel on two copy streams, so
+//               the transfers overlap the launches: a launch waits only for
+//               the copies of the requests that join at it, and results bound
+//               for host memory are staged on the device and copied out after
+//   completion  the worker polls each launch's events; the requests whose
+//               last chunk it was are stamped done once their results are out
 //   poll        never blocks: WH_PENDING, or the result once (then retired)
 //
-// Every launch of a matrix goes to that matrix's stream, so a column freed by
-// one request (its Y copy queued) is reused by the next only after that copy,
-// and the slab partials are shared by the chunks in order.  All streams keep
-// the default priority.
+// A matrix's slab partials are shared by its chunks in launch order.  Every
+// stream keeps the default priority.
 #include <hip/hip_runtime.h>
 
 #include <time.h>
@@ -76,9 +80,12 @@ uint64_t now_ns()
 // steps with each group of 16
 constexpr uint32_t kBuckets[] = {1, 2, 4, 8, 16, 32, 48, 64};
 constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
-// chunk launches of one matrix in flight on the device (the second keeps
-// its stream busy while the worker notices the first one end)
+// chunk launches in flight on the device (the second keeps the stream busy
+// while the worker notices the first one end)
 constexpr size_t kMaxInflight = 2;
+// event sets per matrix: launches whose results are still being copied out
+// keep theirs a little longer
+constexpr size_t kEventSets = kMaxInflight + 4;
 static_assert(kMaxRhs == 64, "a slot's columns are the bits of a uint64_t");
 
 int bucket_index(uint32_t k)
@@ -98,26 +105,39 @@ struct Req {
     uint32_t left = 0;       // chunk launches still to issue for it
 };
 
+// The events of one chunk launch: t0 and t1 around its graph and the copies
+// of its results to the slot's staging columns (launch stream), ty after the
+// copies of those results to host memory (copy-out stream), tu after the
+// copies in of the requests that joined (copy-in stream).
+struct LaunchEvents {
+    hipEvent_t t0 = nullptr, t1 = nullptr, ty = nullptr, tu = nullptr;
+};
+
 struct Launch {
-    hipEvent_t t0 = nullptr, t1 = nullptr;
+    LaunchEvents ev;
+    bool computed = false;      // t1 has been seen
+    bool to_host = false;       // ty was recorded
+    uint64_t free = 0;          // columns of the requests it completes, freed when it does
     std::vector<uint64_t> done; // requests whose last chunk this launch is
 };
 
 struct MatServe {
     Matrix m{};
-    hipStream_t stream = nullptr;
     std::vector<std::pair<uint32_t, uint32_t>> chunks;
     float* U = nullptr;      // kMaxRhs x cols
     float* Y = nullptr;      // kMaxRhs x rows
+    float* S = nullptr;      // kMaxRhs x rows: results staged for their copy to host
     double* part = nullptr;  // slab partials of the chunk plans
     std::vector<hipGraphExec_t> exec; // [chunk * kNumBuckets + bucket]
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> spare; // event pairs not in use
+    std::vector<LaunchEvents> spare; // event sets not in use
     std::deque<Launch> inflight;
     std::deque<uint64_t> pending; // queued, not yet in the scan
     std::vector<uint64_t> active; // in the scan, chunks left to launch
     uint64_t used = 0;            // columns held by active requests
     uint32_t next_chunk = 0;
     double chunk_ms = 0.0;        // running estimate of one chunk launch
+    double chunk_ms_max = 0.0;    // the longest recent one (decays)
+    double pace_ns = 0.0;         // while its scan runs late: when its next chunk is due
     size_t bytes = 0;             // charged to the budget
     bool building = false, usable = false;
     wh_status build_status = WH_OK;
@@ -127,6 +147,9 @@ struct MatServe {
 
 struct Server {
     wh_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;   // every launch of the loop
+    hipStream_t copy_in = nullptr;  // requests' vectors into their columns
+    hipStream_t copy_out = nullptr; // staged results to host memory
     std::mutex mu;
     std::condition_variable cv;
     std::unordered_map<uint64_t, Req> reqs;
@@ -173,7 +196,7 @@ size_t slot_partials(const Matrix& m, const wh_ctx* ctx)
 // What a matrix's slot charges against the context's HBM budget.
 size_t slot_bytes(const Matrix& m, const wh_ctx* ctx)
 {
-    return (size_t)kMaxRhs * ((size_t)m.desc.cols + m.desc.rows) * sizeof(float) +
+    return (size_t)kMaxRhs * ((size_t)m.desc.cols + 2 * (size_t)m.desc.rows) * sizeof(float) +
            slot_partials(m, ctx) * sizeof(double);
 }
 
@@ -190,38 +213,50 @@ void free_slot(MatServe& ms)
         if (g)
             (void)hipGraphExecDestroy(g);
     ms.exec.clear();
-    for (auto& e : ms.spare) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
-    }
+    auto destroy = [](LaunchEvents& e) {
+        for (hipEvent_t x : {e.t0, e.t1, e.ty, e.tu})
+            if (x)
+                (void)hipEventDestroy(x);
+        e = LaunchEvents{};
+    };
+    for (auto& e : ms.spare)
+        destroy(e);
     ms.spare.clear();
-    for (Launch& l : ms.inflight) {
-        (void)hipEventDestroy(l.t0);
-        (void)hipEventDestroy(l.t1);
-    }
+    for (Launch& l : ms.inflight)
+        destroy(l.ev);
     ms.inflight.clear();
     if (ms.U)
         (void)hipFree(ms.U);
     if (ms.Y)
         (void)hipFree(ms.Y);
+    if (ms.S)
+        (void)hipFree(ms.S);
     if (ms.part)
         (void)hipFree(ms.part);
-    ms.U = ms.Y = nullptr;
+    ms.U = ms.Y = ms.S = nullptr;
     ms.part = nullptr;
-    if (ms.stream)
-        (void)hipStreamDestroy(ms.stream);
-    ms.stream = nullptr;
 }
 
-// Device memory, streams, events and graphs of a matrix's slot.  Runs
-// without the server lock (the worker does not touch a slot being built).
+// Device memory, events and graphs of a matrix's slot (captured on a stream
+// of its own, then launched on the loop's).  Runs without the server lock
+// (the worker does not touch a slot being built).
 wh_status build_slot(wh_ctx* ctx, MatServe& ms)
 {
+    struct CaptureStream {
+        hipStream_t s = nullptr;
+        ~CaptureStream()
+        {
+            if (s)
+                (void)hipStreamDestroy(s);
+        }
+    } cap;
     const Matrix& m = ms.m;
-    if (hipStreamCreateWithFlags(&ms.stream, hipStreamNonBlocking) != hipSuccess)
+    if (hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking) != hipSuccess)
         return WH_ERR_DEVICE;
+    hipStream_t st = cap.s;
     if (hipMalloc(&ms.U, (size_t)kMaxRhs * m.desc.cols * sizeof(float)) != hipSuccess ||
-        hipMalloc(&ms.Y, (size_t)kMaxRhs * m.desc.rows * sizeof(float)) != hipSuccess)
+        hipMalloc(&ms.Y, (size_t)kMaxRhs * m.desc.rows * sizeof(float)) != hipSuccess ||
+        hipMalloc(&ms.S, (size_t)kMaxRhs * m.desc.rows * sizeof(float)) != hipSuccess)
         return WH_ERR_NOMEM;
     // columns the graphs read before a request writes them must be finite
     if (hipMemset(ms.U, 0, (size_t)kMaxRhs * m.desc.cols * sizeof(float)) != hipSuccess)
@@ -230,11 +265,13 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
     if (part_n && hipMalloc(&ms.part, part_n * sizeof(double)) != hipSuccess)
         return WH_ERR_NOMEM;
     ms.chunks = serve_chunks(m, ctx->serve_chunk_values);
-    for (size_t i = 0; i < kMaxInflight + 1; ++i) {
-        hipEvent_t a = nullptr, b = nullptr;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    for (size_t i = 0; i < kEventSets; ++i) {
+        ms.spare.emplace_back();
+        LaunchEvents& e = ms.spare.back();
+        if (hipEventCreate(&e.t0) != hipSuccess || hipEventCreate(&e.t1) != hipSuccess ||
+            hipEventCreateWithFlags(&e.ty, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&e.tu, hipEventDisableTiming) != hipSuccess)
             return WH_ERR_DEVICE;
-        ms.spare.emplace_back(a, b);
     }
     ms.exec.assign(ms.chunks.size() * kNumBuckets, nullptr);
     double model = 0.0;
@@ -244,19 +281,19 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
         for (int b = 0; b < kNumBuckets; ++b) {
             const uint32_t k = kBuckets[b];
             hipGraph_t g = nullptr;
-            if (hipStreamBeginCapture(ms.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return WH_ERR_DEVICE;
             hipError_t e;
             if (k == 1) {
                 const GemvPlan gp = whz_gemv_plan(m.desc.rate, m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
-                e = whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, ms.U, ms.Y + c.first, ms.part, ms.stream);
+                e = whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, ms.U, ms.Y + c.first, ms.part, st);
             } else {
                 const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k,
                                                   ctx->gemv_tune.mrhs_slabs);
                 e = whz_mrhs(m.desc.rate, mp, false, m.dptr, ms.U, m.desc.cols, k, ms.Y + c.first, m.desc.rows,
-                             ms.part, ms.stream);
+                             ms.part, st);
             }
-            const hipError_t e2 = hipStreamEndCapture(ms.stream, &g);
+            const hipError_t e2 = hipStreamEndCapture(st, &g);
             if (e != hipSuccess || e2 != hipSuccess || !g)
                 return WH_ERR_DEVICE;
             e = hipGraphInstantiate(&ms.exec[ci * kNumBuckets + b], g, nullptr, nullptr, 0);
@@ -265,7 +302,7 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
                 return WH_ERR_DEVICE;
         }
     }
-    ms.chunk_ms = model;
+    ms.chunk_ms = ms.chunk_ms_max = model;
     return WH_OK;
 }
 
@@ -306,11 +343,35 @@ hipError_t copy_cols(float* slot, const float* req_src, float* req_dst, uint64_t
     return hipSuccess;
 }
 
+// The columns `mask` of one slot buffer copied to the same columns of another.
+hipError_t stage_cols(float* dst, const float* src, uint64_t mask, size_t n, hipStream_t st)
+{
+    while (mask) {
+        const uint32_t c0 = (uint32_t)__builtin_ctzll(mask);
+        const uint64_t from = mask >> c0;
+        const uint32_t len = ~from ? (uint32_t)__builtin_ctzll(~from) : 64u - c0;
+        const hipError_t e = hipMemcpyAsync(dst + (size_t)c0 * n, src + (size_t)c0 * n,
+                                            (size_t)len * n * sizeof(float), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess)
+            return e;
+        mask &= len >= 64 ? 0ull : ~(((1ull << len) - 1) << c0);
+    }
+    return hipSuccess;
+}
+
 // Called with sv->mu held.  Issues the next chunk launch of a matrix: queued
-// requests join (FIFO, while columns last), the chunk's graph runs over every
-// held column, and the requests whose last chunk this was get their Y copied
-// back.  The HIP calls are asynchronous: copies from and to page-locked or
-// device memory only.
+// requests join (FIFO, while columns last) and their vectors are copied into
+// their columns on the copy-in stream, which the launch waits for; the
+// chunk's graph runs over every held column; the results of the requests
+// whose last chunk this was are copied to their device buffers, or staged and
+// then copied to host memory on the copy-out stream, so that neither kind of
+// host copy holds up the launches.  A column is freed only once the launch
+// that completes its request has finished, results copied, so a request that
+// takes it over writes its vectors over nothing a launch still needs.  The
+// launches issued meanwhile compute the freed column with whatever it holds,
+// and the new request's own pass, which begins after its copy in, rewrites
+// every row of it.  The HIP calls are asynchronous: copies from and to
+// page-locked or device memory only.
 wh_status issue_chunk(Server* sv, MatServe& ms)
 {
     const Matrix& m = ms.m;
@@ -328,7 +389,7 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
         r.t_start = t0;
         ms.used |= mask;
         const hipMemcpyKind kind = r.r.u_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-        if (copy_cols(ms.U, r.r.U, nullptr, mask, cols, true, kind, ms.stream) != hipSuccess)
+        if (copy_cols(ms.U, r.r.U, nullptr, mask, cols, true, kind, sv->copy_in) != hipSuccess)
             return WH_ERR_DEVICE;
         joined.push_back(ms.pending.front());
         ms.active.push_back(ms.pending.front());
@@ -342,72 +403,105 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
     const int b = bucket_index(kmax);
     const uint32_t c = ms.next_chunk;
     Launch l;
-    l.t0 = ms.spare.back().first;
-    l.t1 = ms.spare.back().second;
+    l.ev = ms.spare.back();
     ms.spare.pop_back();
-    if (hipEventRecord(l.t0, ms.stream) != hipSuccess ||
-        hipGraphLaunch(ms.exec[(size_t)c * kNumBuckets + b], ms.stream) != hipSuccess)
+    if (!joined.empty() && (hipEventRecord(l.ev.tu, sv->copy_in) != hipSuccess ||
+                            hipStreamWaitEvent(sv->stream, l.ev.tu, 0) != hipSuccess))
+        return WH_ERR_DEVICE;
+    if (hipEventRecord(l.ev.t0, sv->stream) != hipSuccess ||
+        hipGraphLaunch(ms.exec[(size_t)c * kNumBuckets + b], sv->stream) != hipSuccess)
         return WH_ERR_DEVICE;
     ms.next_chunk = (c + 1) % nchunks;
     size_t keep = 0;
+    std::vector<const Req*> to_host;
     for (size_t i = 0; i < ms.active.size(); ++i) {
         Req& r = sv->reqs[ms.active[i]];
         if (--r.left > 0) {
             ms.active[keep++] = ms.active[i];
             continue;
         }
-        const hipMemcpyKind kind = r.r.y_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        if (copy_cols(ms.Y, nullptr, r.r.Y, r.cols, rows, false, kind, ms.stream) != hipSuccess)
+        const hipError_t e = r.r.y_on_device
+                                 ? copy_cols(ms.Y, nullptr, r.r.Y, r.cols, rows, false, hipMemcpyDeviceToDevice,
+                                             sv->stream)
+                                 : stage_cols(ms.S, ms.Y, r.cols, rows, sv->stream);
+        if (e != hipSuccess)
             return WH_ERR_DEVICE;
-        ms.used &= ~r.cols; // later users of these columns come after this copy
+        if (!r.r.y_on_device)
+            to_host.push_back(&r);
+        l.free |= r.cols;
         l.done.push_back(ms.active[i]);
     }
     ms.active.resize(keep);
-    if (hipEventRecord(l.t1, ms.stream) != hipSuccess)
+    if (hipEventRecord(l.ev.t1, sv->stream) != hipSuccess)
         return WH_ERR_DEVICE;
+    if (!to_host.empty()) {
+        if (hipStreamWaitEvent(sv->copy_out, l.ev.t1, 0) != hipSuccess)
+            return WH_ERR_DEVICE;
+        for (const Req* r : to_host)
+            if (copy_cols(ms.S, nullptr, r->r.Y, r->cols, rows, false, hipMemcpyDeviceToHost, sv->copy_out) !=
+                hipSuccess)
+                return WH_ERR_DEVICE;
+        if (hipEventRecord(l.ev.ty, sv->copy_out) != hipSuccess)
+            return WH_ERR_DEVICE;
+        l.to_host = true;
+    }
     ms.inflight.push_back(std::move(l));
     return WH_OK;
 }
 
 // The hold: a matrix's queued requests start at the latest when its pass
-// (measured chunk times, `kHoldPasses` of them to allow for sharing the
-// device) and kHoldMarginNs remain before the most urgent one's deadline.
-constexpr double kHoldPasses = 2.0;
+// (measured chunk times), the launches that may be ahead of it (`ahead_ns`)
+// and kHoldMarginNs remain before the most urgent one's deadline.
 constexpr double kHoldMarginNs = 5e5;
+// A scan running late gets one chunk launch per kLatePace of its measured
+// chunk times while other work competes, so its pass takes about kLatePace
+// times as long as it would alone and the rest of the device is left to
+// requests that can still meet their deadlines.
+constexpr double kLatePace = 2.0;
 
-// Called with sv->mu held.  How urgent a matrix's next chunk launch is: the
-// earliest deadline among its requests that can still meet theirs
-// (`feasible`), and the least remaining scan time of its other requests
-// (`late`, ns).  Returns false if it has nothing to launch now; then
+// Called with sv->mu held.  When a matrix's next chunk launch should start:
+// the latest start of its requests that can still meet their deadlines
+// (deadline less the chunks they have left, with `between_ns` for another
+// launch between two of them; `late` false), else the pace of a scan running
+// late (`late` true).  Returns false if it has nothing to launch now; then
 // `hold_until` is when its held requests must start (UINT64_MAX: nothing
-// held).  `hold`: another matrix's scan is running late.
-bool urgency(Server* sv, const MatServe& ms, uint64_t now, bool hold, uint64_t& feasible, uint64_t& late,
-             uint64_t& hold_until)
+// held).  `hold`: another matrix's scan is running late; `ahead_ns`: what
+// may run before the first chunk of a pass.
+bool urgency(Server* sv, const MatServe& ms, uint64_t now, bool hold, double ahead_ns, double between_ns,
+             double& key, bool& late, uint64_t& hold_until)
 {
-    feasible = late = hold_until = UINT64_MAX;
+    hold_until = UINT64_MAX;
+    key = 1e300;
+    late = false;
     const double chunk_ns = ms.chunk_ms * 1e6;
     if (hold && ms.active.empty() && !ms.pending.empty()) {
-        const double pass_ns = chunk_ns * (double)ms.chunks.size();
+        const double nc = (double)ms.chunks.size();
+        const double pass_ns = ms.chunk_ms_max * 1e6 * nc + between_ns * (nc - 1.0) + ahead_ns;
         double start_by = 1e300;
         uint32_t k = 0;
         for (uint64_t t : ms.pending) {
             const Req& r = sv->reqs.at(t);
             k += r.r.k;
             const double due = r.r.deadline_ns ? (double)(r.t_arrive + r.r.deadline_ns) : 0.0;
-            start_by = std::min(start_by, due - kHoldPasses * pass_ns - kHoldMarginNs);
+            start_by = std::min(start_by, due - pass_ns - kHoldMarginNs);
         }
         if (k < kMaxRhs && (double)now < start_by) {
             hold_until = (uint64_t)start_by;
             return false;
         }
     }
+    bool any_late = false;
     auto consider = [&](const Req& r, uint32_t left) {
-        const uint64_t due = r.r.deadline_ns ? r.t_arrive + r.r.deadline_ns : UINT64_MAX;
-        const double rest = left * chunk_ns;
-        if ((double)now + rest <= (double)due)
-            feasible = std::min(feasible, due);
+        if (!r.r.deadline_ns) {
+            any_late = true;
+            return;
+        }
+        const double due = (double)(r.t_arrive + r.r.deadline_ns);
+        const double rest = left * chunk_ns + (left > 1 ? (left - 1) * between_ns : 0.0);
+        if ((double)now + rest + ahead_ns <= due)
+            key = std::min(key, due - rest);
         else
-            late = std::min(late, (uint64_t)rest);
+            any_late = true;
     };
     for (uint64_t t : ms.active)
         consider(sv->reqs.at(t), sv->reqs.at(t).left);
@@ -418,6 +512,10 @@ bool urgency(Server* sv, const MatServe& ms, uint64_t now, bool hold, uint64_t& 
             joinable = true;
             consider(head, (uint32_t)ms.chunks.size());
         }
+    }
+    if (key == 1e300 && any_late) {
+        late = true;
+        key = ms.pace_ns > 0.0 ? ms.pace_ns : (double)now;
     }
     return !ms.active.empty() || joinable;
 }
@@ -439,41 +537,75 @@ void worker_main(Server* sv)
     (void)hipSetDevice(sv->ctx->device);
     std::unique_lock<std::mutex> lk(sv->mu);
     while (!sv->stop) {
-        // completion, in launch order per matrix
-        size_t inflight = 0;
+        // completion, in launch order per matrix: a launch's compute (t1),
+        // then the copies of its results to host memory (ty)
+        size_t inflight = 0; // launches whose compute has not ended
+        wh_status failed = WH_OK;
         for (auto& mv : sv->mats) {
             MatServe& ms = mv.second;
-            while (!ms.inflight.empty()) {
-                Launch& l = ms.inflight.front();
-                const hipError_t q = hipEventQuery(l.t1);
-                if (q == hipErrorNotReady)
+            for (Launch& l : ms.inflight) {
+                if (l.computed)
+                    continue;
+                const hipError_t q = hipEventQuery(l.ev.t1);
+                if (q == hipErrorNotReady) {
+                    ++inflight;
+                    continue;
+                }
+                if (q != hipSuccess) {
+                    failed = WH_ERR_DEVICE;
                     break;
+                }
+                l.computed = true;
+                float ms_el = 0.f;
+                if (hipEventElapsedTime(&ms_el, l.ev.t0, l.ev.t1) == hipSuccess && ms_el > 0.f) {
+                    ms.chunk_ms = 0.8 * ms.chunk_ms + 0.2 * (double)ms_el;
+                    ms.chunk_ms_max = std::max(0.98 * ms.chunk_ms_max, (double)ms_el);
+                }
+            }
+            while (failed == WH_OK && !ms.inflight.empty() && ms.inflight.front().computed) {
+                Launch& l = ms.inflight.front();
+                if (l.to_host) {
+                    const hipError_t q = hipEventQuery(l.ev.ty);
+                    if (q == hipErrorNotReady)
+                        break;
+                    if (q != hipSuccess) {
+                        failed = WH_ERR_DEVICE;
+                        break;
+                    }
+                }
                 const uint64_t t = now_ns();
-                const wh_status st = q == hipSuccess ? WH_OK : WH_ERR_DEVICE;
                 for (uint64_t tk : l.done) {
                     Req& r = sv->reqs[tk];
                     r.t_done = t;
-                    r.status = st;
+                    r.status = WH_OK;
                 }
-                float ms_el = 0.f;
-                if (st == WH_OK && hipEventElapsedTime(&ms_el, l.t0, l.t1) == hipSuccess && ms_el > 0.f)
-                    ms.chunk_ms = 0.8 * ms.chunk_ms + 0.2 * (double)ms_el;
-                ms.spare.emplace_back(l.t0, l.t1);
+                ms.used &= ~l.free;
+                ms.spare.push_back(l.ev);
                 ms.inflight.pop_front();
-                if (st != WH_OK) {
-                    sv->ctx->failed.store(true);
-                    fail_all(sv, st);
-                }
             }
-            inflight += ms.inflight.size();
+            if (failed != WH_OK)
+                break;
         }
-        // dispatch: earliest feasible deadline first, then late work with
-        // the least scan left; each matrix up to kMaxInflight launches
+        if (failed != WH_OK) {
+            sv->ctx->failed.store(true);
+            fail_all(sv, failed);
+            for (auto& mv : sv->mats) { // nothing more is launched: take back their events
+                for (Launch& l : mv.second.inflight)
+                    mv.second.spare.push_back(l.ev);
+                mv.second.inflight.clear();
+            }
+            inflight = 0;
+        }
+        // dispatch: the earliest latest start among requests that can still
+        // meet their deadlines, and the paced chunks of late scans between
+        // them; kMaxInflight launches in flight at most
         uint64_t wake = UINT64_MAX; // the earliest end of a hold
-        while (sv->sticky == WH_OK) {
+        while (sv->sticky == WH_OK && inflight < kMaxInflight) {
             const uint64_t now = now_ns();
-            MatServe* pick = nullptr;
-            uint64_t best_f = UINT64_MAX, best_l = UINT64_MAX;
+            // candidates: the feasible one with the earliest latest start, the
+            // late scan whose paced start is earliest
+            MatServe *feas = nullptr, *late_pick = nullptr;
+            double feas_key = 0.0, late_key = 0.0;
             wake = UINT64_MAX;
             // the scans running late: none of their requests can still meet
             // its deadline
@@ -482,30 +614,56 @@ void worker_main(Server* sv)
                 const MatServe& o = mv.second;
                 if (!o.usable || o.active.empty())
                     continue;
-                uint64_t f = UINT64_MAX, l, h;
-                (void)urgency(sv, o, now, false, f, l, h);
-                if (f == UINT64_MAX)
+                double key;
+                bool late;
+                uint64_t h;
+                if (urgency(sv, o, now, false, 0.0, 0.0, key, late, h) && late)
                     late_scans.push_back(&o);
             }
             for (auto& mv : sv->mats) {
                 MatServe& ms = mv.second;
-                if (!ms.usable || ms.inflight.size() >= kMaxInflight || ms.spare.empty())
+                if (!ms.usable || ms.spare.empty())
                     continue;
                 const bool hold = std::any_of(late_scans.begin(), late_scans.end(),
                                               [&](const MatServe* o) { return o != &ms; });
-                uint64_t f, l, h;
-                if (!urgency(sv, ms, now, hold, f, l, h)) {
+                // a launch of this matrix may wait for kMaxInflight of the
+                // longest recent launches of the others, and each further
+                // chunk of its pass for one more
+                double between_ns = 0.0;
+                for (const auto& o : sv->mats)
+                    if (&o.second != &ms && o.second.usable)
+                        between_ns = std::max(between_ns, o.second.chunk_ms_max * 1e6);
+                const double ahead_ns = between_ns * kMaxInflight;
+                double key;
+                bool late;
+                uint64_t h;
+                if (!urgency(sv, ms, now, hold, ahead_ns, between_ns, key, late, h)) {
                     wake = std::min(wake, h);
                     continue;
                 }
-                if (!pick || f < best_f || (f == best_f && l < best_l)) {
-                    pick = &ms;
-                    best_f = f;
-                    best_l = l;
+                if (late && (!late_pick || key < late_key)) {
+                    late_pick = &ms;
+                    late_key = key;
+                } else if (!late && (!feas || key < feas_key)) {
+                    feas = &ms;
+                    feas_key = key;
                 }
             }
+            // a late scan's paced chunk goes first when its start has come,
+            // the most urgent feasible work can still start after it and the
+            // launch in flight, and that work is not a pass under way (whose
+            // chunks run back to back); feasible work next; a late scan ahead
+            // of its pace only when nothing else is waiting
+            MatServe* pick = feas;
+            if (late_pick && (!feas || ((double)now >= late_key && feas->active.empty() &&
+                                        feas_key - (double)now >= late_pick->chunk_ms_max * 1e6 * kMaxInflight)))
+                pick = late_pick;
             if (!pick)
                 break;
+            if (pick == late_pick) { // the next paced start, at most one step either side of now
+                const double step = kLatePace * pick->chunk_ms * 1e6;
+                pick->pace_ns = std::min((double)now + step, std::max((double)now - step, late_key) + step);
+            }
             const wh_status st = issue_chunk(sv, *pick);
             if (st != WH_OK) {
                 sv->ctx->failed.store(true);
@@ -514,10 +672,14 @@ void worker_main(Server* sv)
             }
             ++inflight;
         }
-        // sleep briefly while launches run or a hold is about to end; block
-        // while idle
+        // sleep briefly while launches or copies run or a hold is about to
+        // end; block while idle
         const uint64_t now = now_ns();
-        if (inflight || wake <= now + 20000)
+        const bool busy = std::any_of(sv->mats.begin(), sv->mats.end(),
+                                      [](const std::pair<const wh_mat, MatServe>& mv) {
+                                          return !mv.second.inflight.empty();
+                                      });
+        if (busy || wake <= now + 20000)
             sv->cv.wait_for(lk, std::chrono::microseconds(20));
         else if (wake != UINT64_MAX)
             sv->cv.wait_for(lk, std::chrono::nanoseconds(std::min<uint64_t>(wake - now, 5000000)));
@@ -526,13 +688,34 @@ void worker_main(Server* sv)
     }
 }
 
+// Every launch and copy the loop has issued ends.
+void sync_streams(Server* sv)
+{
+    for (hipStream_t s : {sv->stream, sv->copy_in, sv->copy_out})
+        if (s)
+            (void)hipStreamSynchronize(s);
+}
+
+// The context's serving state, created with its streams and worker on first
+// use (nullptr if the stream cannot be created).
 Server* ensure_server(wh_ctx* ctx)
 {
     static std::mutex create_mu;
     std::lock_guard<std::mutex> g(create_mu);
     if (!ctx->server) {
+        hipStream_t st[3] = {nullptr, nullptr, nullptr};
+        for (hipStream_t& s : st)
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+                for (hipStream_t x : st)
+                    if (x)
+                        (void)hipStreamDestroy(x);
+                return nullptr;
+            }
         Server* sv = new Server();
         sv->ctx = ctx;
+        sv->stream = st[0];
+        sv->copy_in = st[1];
+        sv->copy_out = st[2];
         sv->worker = std::thread(worker_main, sv);
         ctx->server = sv;
     }
@@ -568,12 +751,12 @@ void serve_shutdown(wh_ctx* ctx)
     sv->cv.notify_all();
     if (sv->worker.joinable())
         sv->worker.join();
-    for (auto& mv : sv->mats) {
-        MatServe& ms = mv.second;
-        if (ms.stream)
-            (void)hipStreamSynchronize(ms.stream);
-        free_slot(ms);
-    }
+    sync_streams(sv);
+    for (auto& mv : sv->mats)
+        free_slot(mv.second);
+    for (hipStream_t s : {sv->stream, sv->copy_in, sv->copy_out})
+        if (s)
+            (void)hipStreamDestroy(s);
     delete sv;
     ctx->server = nullptr;
 }
@@ -593,8 +776,7 @@ void serve_forget(wh_ctx* ctx, wh_mat m)
     if (it == sv->mats.end())
         return;
     MatServe& ms = it->second;
-    if (ms.stream)
-        (void)hipStreamSynchronize(ms.stream); // launches in flight finish
+    sync_streams(sv); // launches in flight and their copies finish
     for (Launch& l : ms.inflight)
         for (uint64_t tk : l.done) { // their last chunk ran: deliver
             Req& r = sv->reqs[tk];
@@ -631,6 +813,8 @@ extern "C" wh_status wh_submit(wh_ctx* ctx, const wh_request* req, uint64_t* tic
         if (!buffer_ok(req->U, req->u_on_device, ctx->device) || !buffer_ok(req->Y, req->y_on_device, ctx->device))
             return WH_ERR_INVALID;
         Server* sv = ensure_server(ctx);
+        if (!sv)
+            return WH_ERR_DEVICE;
         std::unique_lock<std::mutex> lk(sv->mu);
         if (sv->sticky != WH_OK)
             return sv->sticky;
@@ -662,14 +846,15 @@ extern "C" wh_status wh_submit(wh_ctx* ctx, const wh_request* req, uint64_t* tic
             lk.lock();
             MatServe& ms2 = sv->mats[req->mat];
             if (bst == WH_OK) {
-                ms2.stream = tmp.stream;
                 ms2.chunks = std::move(tmp.chunks);
                 ms2.U = tmp.U;
                 ms2.Y = tmp.Y;
+                ms2.S = tmp.S;
                 ms2.part = tmp.part;
                 ms2.exec = std::move(tmp.exec);
                 ms2.spare = std::move(tmp.spare);
                 ms2.chunk_ms = tmp.chunk_ms;
+                ms2.chunk_ms_max = tmp.chunk_ms_max;
                 ms2.usable = true;
             } else {
                 free_slot(tmp);

@@ -61,15 +61,15 @@ GemvTuning gemv_tuning_from_env()
 }
 
 // WH_SERVE_CHUNK_VALUES: the most matrix values one serving launch covers
-// (a served pass runs as row chunks of about this size); default 2^29.
+// (a served pass runs as row chunks of about this size); default 2^28.
 uint64_t serve_chunk_from_env()
 {
     const char* v = std::getenv("WH_SERVE_CHUNK_VALUES");
     if (!v || !*v)
-        return 1ull << 29;
+        return 1ull << 28;
     char* end = nullptr;
     const unsigned long long x = std::strtoull(v, &end, 10);
-    return (*end == 0 && x > 0) ? (uint64_t)x : (1ull << 29);
+    return (*end == 0 && x > 0) ? (uint64_t)x : (1ull << 28);
 }
 
 wh_status storage_bytes(const wh_matrix_desc& d, uint64_t& nbytes)

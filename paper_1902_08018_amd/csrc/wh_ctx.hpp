@@ -71,7 +71,7 @@ struct wh_ctx {
     int device = 0;
     int num_cus = 256;
     wh::GemvTuning gemv_tune; // launch-shape overrides read at wh_create
-    uint64_t serve_chunk_values = 1ull << 29; // values per serving launch (WH_SERVE_CHUNK_VALUES)
+    uint64_t serve_chunk_values = 1ull << 28; // values per serving launch (WH_SERVE_CHUNK_VALUES)
     uint32_t serve_shed = 0; // shed when the queue head waited this many deadlines (WH_SERVE_SHED; 0 = never)
     uint64_t budget = 0;
     std::mutex mu; // guards mats / next_id

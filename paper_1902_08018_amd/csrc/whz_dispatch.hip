@@ -223,9 +223,11 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
         nslab = 1;
     if (max_slabs >= 8)
         nslab = (nslab + 7) / 8 * 8;
-    // the partials grow with k: at most 128 slab x right-hand-side rows
-    // (8 slabs up to 16 right-hand sides, 2 for 64)
-    const uint32_t cap = std::max<uint32_t>(1, 128 / std::max<uint32_t>(k, 1));
+    // the FP64 partials (slabs x k x rows) stay within 64 MiB: 8 slabs of 16
+    // right-hand sides over 65536 rows, 2 of 64; short row ranges (few tiles,
+    // which need the slabs to fill the device) keep theirs
+    const uint64_t per_slab = (uint64_t)std::max<uint32_t>(k, 1) * nbr * 4;
+    const uint32_t cap = (uint32_t)std::max<uint64_t>(1, (8ull << 20) / std::max<uint64_t>(per_slab, 1));
     if (nslab > cap)
         nslab = cap;
     if (slabs)
