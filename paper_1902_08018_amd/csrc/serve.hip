@@ -649,13 +649,12 @@ void worker_main(Server* sv)
                     feas_key = key;
                 }
             }
-            // a late scan's paced chunk goes first when its start has come,
-            // the most urgent feasible work can still start after it and the
-            // launch in flight, and that work is not a pass under way (whose
-            // chunks run back to back); feasible work next; a late scan ahead
-            // of its pace only when nothing else is waiting
+            // a late scan's paced chunk goes first when its start has come
+            // and the most urgent feasible work can still start after it and
+            // the launch in flight; feasible work next; a late scan ahead of
+            // its pace only when nothing else is waiting
             MatServe* pick = feas;
-            if (late_pick && (!feas || ((double)now >= late_key && feas->active.empty() &&
+            if (late_pick && (!feas || ((double)now >= late_key &&
                                         feas_key - (double)now >= late_pick->chunk_ms_max * 1e6 * kMaxInflight)))
                 pick = late_pick;
             if (!pick)
