@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--serving", type=int, default=1, help="also run the Poisson serving load")
     ap.add_argument("--serving-requests", type=int, default=20000)
-    ap.add_argument("--leg", default="", help="internal: 'host-pipeline' runs only that leg and prints its JSON")
+    ap.add_argument("--leg", default="", help="'host-pipeline' (internal) or 'serving' (the three-matrix load of "
+                                              "--serving-requests requests) runs only that leg and prints its JSON")
     ap.add_argument("--probe", type=int, default=0,
                     help="counter-pass mode, prints no JSON: 1 = 3 launches of the timed configuration, then 3 "
                          "plain 4 GiB device copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE) and 3 "
@@ -753,6 +754,9 @@ def main():
     size, rate = args.size, args.rate
     spec = synth.LARGE if size == 65536 else synth.MatrixSpec(size, size, int(round(size ** 0.5)), 32.0)
     rows, cols = spec.rows, spec.cols
+    if args.leg == "serving":
+        print(json.dumps(bench_serving(n_measured=args.serving_requests)), flush=True)
+        return
     ctx = wh.wh_create(0, 0)
     if args.leg == "host-pipeline":
         print(json.dumps(bench_host_pipeline(ctx, rate, args.steps)), flush=True)

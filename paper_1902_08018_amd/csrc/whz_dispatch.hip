@@ -211,11 +211,13 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
     const uint32_t nbr = pl.bi_end - pl.bi_begin;
     const uint32_t tile_rows = 4u * (uint32_t)mrhs_waves((int)((k + 15) / 16));
     pl.ntiles = (nbr + tile_rows - 1) / tile_rows;
-    // two workgroups are resident per CU: about two rounds of them (each
-    // column slab adds FP64 partials, slabs x k x rows).  Workgroups go to
-    // the eight XCDs round-robin, so with a multiple of 8 slabs (slab =
-    // workgroup % slabs) each XCD's L2 holds the B^T U of 1/8 of the columns
-    // only
+    // two workgroups are resident per CU; about two rounds of them, then the
+    // slab count rounded up to a multiple of 8: on 65536^2 with up to 16
+    // right-hand sides, 8 to 12 slabs (5 to 8 rounds) run 5.4 ms where 3
+    // slabs (two rounds and two workgroups) take 6.2 ms and 5 to 7 take
+    // 5.65 ms.  The L2 miss count is the same for 3 and 8 slabs (34.5 M and
+    // 34.1 M): the gain is the shorter last round, not where B^T U is
+    // cached.  Each column slab adds FP64 partials, slabs x k x rows
     const uint64_t want = (uint64_t)(num_cus > 0 ? num_cus : 256) * 4;
     const uint32_t max_slabs = (pl.nbc + 15) / 16;
     uint32_t nslab = pl.ntiles ? (uint32_t)((want + pl.ntiles - 1) / pl.ntiles) : 1;
