@@ -124,6 +124,16 @@ const char *wh_status_str(wh_status st);
  * (column slabs), read here, fix the compressed GEMV's launch shape instead
  * of the planner's choice, and WH_MRHS_SLABS the multi-RHS kernel's column
  * slabs (for launch-shape sweeps); invalid values are ignored.  Results stay within the stated tolerances for every shape.
+ * WH_MRHS_FP32=1 keeps FP32 right-hand sides on the FP32 matrix cores for
+ * every k (by default, from 17 right-hand sides up, the FP32 operands are
+ * each split into three BF16 parts and their six significant products run
+ * on the BF16 matrix cores; the result stays within the FP32 tolerance).
+ * WH_SERVE_PACE (a number from 1 to 16, default 4) paces a served matrix
+ * whose requests can no longer meet their deadlines: while other work waits,
+ * it gets one launch per that many of its launch times (one per launch time
+ * while its own queued requests wait for free columns).
+ * WH_SERVE_MARGIN_US (default 500) is the margin, in microseconds, that a
+ * held request keeps before its deadline beyond its estimated pass.
  * WH_SERVE_CHUNK_VALUES (a positive integer, default 2^28) bounds the matrix
  * values one serving launch covers: the serving loop runs each pass over a
  * larger matrix as launches over consecutive row chunks, so that batches of

@@ -36,8 +36,9 @@
 //               will take.  Requests that can still meet their deadlines go
 //               by the latest time their next chunk may start (the earliest
 //               first).  A scan running late is paced at one chunk per
-//               kLatePace of its chunk times while that work waits (about
-//               half the device), and takes what is left over
+//               ctx->serve_pace of its chunk times while that work waits
+//               (full speed while its own requests wait for columns), and
+//               takes what is left over
 //   copies      vectors in and results out travel on two copy streams, so
 //               the transfers overlap the launches: a launch waits only for
 //               the copies of the requests that join at it, and results bound
@@ -164,9 +165,14 @@ struct Server {
 namespace {
 
 // The row chunks of one served pass: consecutive ranges of whole block rows
-// holding at most `values` matrix values each (at least one block row).
+// holding at most `values` matrix values each (at least one block row).  A
+// matrix of at most twice that is one chunk: cutting its pass in two would
+// only let other launches in between two halves of a pass short enough to
+// meet a deadline.
 std::vector<std::pair<uint32_t, uint32_t>> serve_chunks(const Matrix& m, uint64_t values)
 {
+    if ((uint64_t)m.desc.rows * m.desc.cols <= 2 * values)
+        return {{0u, m.desc.rows}};
     const uint64_t per = std::max<uint64_t>(4, values / std::max<uint32_t>(1, m.desc.cols) / 4 * 4);
     std::vector<std::pair<uint32_t, uint32_t>> out;
     for (uint64_t r0 = 0; r0 < m.desc.rows; r0 += per)
@@ -185,9 +191,9 @@ size_t slot_partials(const Matrix& m, const wh_ctx* ctx)
         if (gp.nslab > 1)
             n = std::max(n, (size_t)gp.nslab * gp.part_rows());
         for (uint32_t k = 16; k <= kMaxRhs; k += 16) { // the plan and workspace depend on k
-            const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k,
-                                              ctx->gemv_tune.mrhs_slabs);
-            n = std::max(n, mrhs_workspace(mp, k, false).total);
+            const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k, false,
+                                              &ctx->gemv_tune);
+            n = std::max(n, mrhs_workspace(mp, k).total);
         }
     }
     return n;
@@ -288,9 +294,9 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
                 const GemvPlan gp = whz_gemv_plan(m.desc.rate, m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus);
                 e = whz_gemv(m.desc.rate, gp, AccMode::Fp64, m.dptr, ms.U, ms.Y + c.first, ms.part, st);
             } else {
-                const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k,
-                                                  ctx->gemv_tune.mrhs_slabs);
-                e = whz_mrhs(m.desc.rate, mp, false, m.dptr, ms.U, m.desc.cols, k, ms.Y + c.first, m.desc.rows,
+                const MrhsPlan mp = whz_mrhs_plan(m.desc.rows, m.desc.cols, c.first, c.second, ctx->num_cus, k, false,
+                                                  &ctx->gemv_tune);
+                e = whz_mrhs(m.desc.rate, mp, m.dptr, ms.U, m.desc.cols, k, ms.Y + c.first, m.desc.rows,
                              ms.part, st);
             }
             const hipError_t e2 = hipStreamEndCapture(st, &g);
@@ -451,13 +457,12 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
 
 // The hold: a matrix's queued requests start at the latest when its pass
 // (measured chunk times), the launches that may be ahead of it (`ahead_ns`)
-// and kHoldMarginNs remain before the most urgent one's deadline.
-constexpr double kHoldMarginNs = 5e5;
-// A scan running late gets one chunk launch per kLatePace of its measured
-// chunk times while other work competes, so its pass takes about kLatePace
+// and ctx->serve_margin_ns remain before the most urgent one's deadline.
+// A scan running late gets one chunk launch per ctx->serve_pace of its
+// measured chunk times while other work competes (one per chunk time while
+// its queued requests wait for columns), so its pass takes about that many
 // times as long as it would alone and the rest of the device is left to
 // requests that can still meet their deadlines.
-constexpr double kLatePace = 2.0;
 
 // Called with sv->mu held.  When a matrix's next chunk launch should start:
 // the latest start of its requests that can still meet their deadlines
@@ -483,7 +488,7 @@ bool urgency(Server* sv, const MatServe& ms, uint64_t now, bool hold, double ahe
             const Req& r = sv->reqs.at(t);
             k += r.r.k;
             const double due = r.r.deadline_ns ? (double)(r.t_arrive + r.r.deadline_ns) : 0.0;
-            start_by = std::min(start_by, due - pass_ns - kHoldMarginNs);
+            start_by = std::min(start_by, due - pass_ns - sv->ctx->serve_margin_ns);
         }
         if (k < kMaxRhs && (double)now < start_by) {
             hold_until = (uint64_t)start_by;
@@ -660,7 +665,10 @@ void worker_main(Server* sv)
             if (!pick)
                 break;
             if (pick == late_pick) { // the next paced start, at most one step either side of now
-                const double step = kLatePace * pick->chunk_ms * 1e6;
+                // at full speed while its queued requests wait for columns
+                const bool backlog = !pick->pending.empty() &&
+                                     !take_cols(pick->used, sv->reqs.at(pick->pending.front()).r.k);
+                const double step = (backlog ? 1.0 : sv->ctx->serve_pace) * pick->chunk_ms * 1e6;
                 pick->pace_ns = std::min((double)now + step, std::max((double)now - step, late_key) + step);
             }
             const wh_status st = issue_chunk(sv, *pick);

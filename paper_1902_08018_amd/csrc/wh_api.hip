@@ -57,6 +57,7 @@ GemvTuning gemv_tuning_from_env()
         t.rows = rows;
     t.slabs = get("WH_GEMV_SLABS");
     t.mrhs_slabs = get("WH_MRHS_SLABS");
+    t.mrhs_fp32 = get("WH_MRHS_FP32") ? 1u : 0u;
     return t;
 }
 
@@ -217,6 +218,18 @@ wh_status wh_create(int hip_device, uint64_t hbm_budget_bytes, wh_ctx** out)
         ctx->num_cus = prop.multiProcessorCount;
         ctx->gemv_tune = gemv_tuning_from_env();
         ctx->serve_chunk_values = serve_chunk_from_env();
+        if (const char* v = std::getenv("WH_SERVE_PACE")) {
+            char* end = nullptr;
+            const double f = std::strtod(v, &end);
+            if (*v && *end == 0 && f >= 1.0 && f <= 16.0)
+                ctx->serve_pace = f;
+        }
+        if (const char* v = std::getenv("WH_SERVE_MARGIN_US")) {
+            char* end = nullptr;
+            const double f = std::strtod(v, &end);
+            if (*v && *end == 0 && f >= 0.0 && f <= 1e6)
+                ctx->serve_margin_ns = f * 1e3;
+        }
         if (const char* v = std::getenv("WH_SERVE_SHED")) {
             char* end = nullptr;
             const unsigned long f = std::strtoul(v, &end, 10);
@@ -459,14 +472,13 @@ wh_status wh_gemv_batched(wh_ctx* ctx, wh_mat m, const void* d_U, int u_dtype, u
             return wh_gemv(ctx, m, static_cast<const float*>(d_U), d_Y, 0, mat.desc.rows, flags, stream);
         if (flags & WH_PAPER_MP)
             return WH_ERR_INVALID; // Fig. 7 per-product sums exist for one vector only
-        const MrhsPlan pl =
-            whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus, k, ctx->gemv_tune.mrhs_slabs);
+        const MrhsPlan pl = whz_mrhs_plan(mat.desc.rows, mat.desc.cols, 0, mat.desc.rows, ctx->num_cus, k,
+                                          u_dtype == WH_U_BF16, &ctx->gemv_tune);
         // slab partials and B^T U share the context's workspace
-        wh_status s2 = ensure_partials(ctx, mrhs_workspace(pl, k, u_dtype == WH_U_BF16).total, st);
+        wh_status s2 = ensure_partials(ctx, mrhs_workspace(pl, k).total, st);
         if (s2 != WH_OK)
             return s2;
-        hipError_t e =
-            whz_mrhs(mat.desc.rate, pl, u_dtype == WH_U_BF16, mat.dptr, d_U, ldu, k, d_Y, ldy, ctx->part, st);
+        hipError_t e = whz_mrhs(mat.desc.rate, pl, mat.dptr, d_U, ldu, k, d_Y, ldy, ctx->part, st);
         return device_error(ctx, partials_release(ctx, st, e));
     } catch (...) {
         return WH_ERR_INVALID;

@@ -44,6 +44,7 @@ struct GemvPlan {
     uint32_t rpg;      // block rows per group and tile (1 .. kGemvMaxRowsPerGroup)
     uint32_t skip;     // row_begin % 4: rows of the first block row before the range
     uint32_t lanes;    // workgroup lanes (gemv_wg_lanes of the rate)
+    uint32_t math;     // multi-RHS plans: the contraction (MrhsMath)
     // FP64 partials per slab and right-hand side: the range's block-rows
     uint32_t part_rows() const { return (bi_end - bi_begin) * 4; }
 };
@@ -55,41 +56,56 @@ struct GemvTuning {
     uint32_t rows = 0;  // block rows per group and tile: 1 .. kGemvMaxRowsPerGroup
     uint32_t slabs = 0; // column slabs (at most one per group width of block columns)
     uint32_t mrhs_slabs = 0; // column slabs of the multi-RHS kernel
+    uint32_t mrhs_fp32 = 0;  // 1: FP32 U always on the FP32 MFMA (no three-part split)
 };
 
 // Launch geometry of the multi-RHS kernel: tiles of 4 block-rows per wave x
-// slabs of block-columns (multiples of 16).  Waves per workgroup for NT
-// groups of 16 right-hand sides.
+// slabs of block-columns (multiples of 16).
 typedef GemvPlan MrhsPlan;
-constexpr int mrhs_waves(int nt) { return nt == 1 ? 12 : 8; }
+// How it contracts: FP32 U on the FP32 MFMA; BF16 U on the BF16 MFMA; or FP32
+// U and the FP32 coefficients each split into three BF16 parts, whose six
+// significant products go to the BF16 MFMA (X6: from 17 right-hand sides up,
+// where the FP32 MFMA's time, which does not overlap the decoder's VALU work,
+// exceeds the split's VALU cost).
+enum class MrhsMath : uint32_t { F32 = 0, Bf16 = 1, X6 = 2 };
+inline MrhsMath mrhs_math(uint32_t k, bool bf16, bool force_fp32)
+{
+    return bf16 ? MrhsMath::Bf16 : (k > 16 && !force_fp32 ? MrhsMath::X6 : MrhsMath::F32);
+}
+// Waves per workgroup for NT groups of 16 right-hand sides.
+constexpr int mrhs_waves(int nt, MrhsMath m) { return m == MrhsMath::X6 ? 8 : (nt == 1 ? 12 : 8); }
 constexpr uint32_t kMrhsMaxTileBlockRows = 48;
 constexpr uint32_t kMaxRhs = 64;
 
 // The multi-RHS workspace, in doubles: FP64 slab partials [nslab][k][rows]
 // (only when the plan splits the columns), then, from btu_offset (a whole
 // number of 256-byte lines in), B^T U for every block column rounded up to
-// 16 and every group of 16 right-hand sides (FP32, or BF16 with BF16 U).
+// 16 and every group of 16 right-hand sides (FP32, BF16, or three BF16
+// parts: 4, 2 or 6 bytes per value).
 struct MrhsWorkspace {
     size_t btu_offset;
     size_t total;
 };
-inline MrhsWorkspace mrhs_workspace(const MrhsPlan& pl, uint32_t k, bool bf16)
+inline MrhsWorkspace mrhs_workspace(const MrhsPlan& pl, uint32_t k)
 {
     const size_t part = pl.nslab > 1 ? (size_t)pl.nslab * k * pl.part_rows() : 0;
     const size_t off = (part + 31) / 32 * 32;
     const size_t nbc16 = ((size_t)pl.nbc + 15) / 16 * 16;
     const size_t nt = (k + 15) / 16;
-    const size_t btu_bytes = nbc16 * nt * 64 * (bf16 ? 2 : 4);
+    const MrhsMath m = (MrhsMath)pl.math;
+    const size_t btu_bytes = nbc16 * nt * 64 * (m == MrhsMath::Bf16 ? 2 : m == MrhsMath::X6 ? 6 : 4);
     return MrhsWorkspace{off, off + (btu_bytes + 7) / 8};
 }
 
 bool whz_rate_supported(uint32_t rate);
-// for k right-hand sides; slabs != 0 fixes the column slab count
+// for k right-hand sides, FP32 or BF16 U; `tune` (may be null) can fix the
+// column slab count and keep FP32 U on the FP32 MFMA
 MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t k,
-                       uint32_t slabs = 0);
-// `ws`: mrhs_workspace(pl, k, bf16).total doubles of device memory
-hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu,
-                    uint32_t k, float* Y, uint32_t ldy, double* part, hipStream_t st);
+                       bool bf16, const GemvTuning* tune = nullptr);
+// `ws`: mrhs_workspace(pl, k).total doubles of device memory; U is BF16 when
+// the plan's math is MrhsMath::Bf16, else FP32
+hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, const void* stream, const void* U, uint32_t ldu, uint32_t k,
+                    float* Y, uint32_t ldy, double* part, hipStream_t st);
 GemvPlan whz_gemv_plan(uint32_t rate, uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end,
                        int num_cus, const GemvTuning* tune = nullptr);
 // Slabs of block columns for a kernel whose `lanes` lanes sweep each block row

@@ -16,7 +16,7 @@ namespace wh {
     hipError_t decode_matrix(const void*, uint32_t, uint32_t, float*, hipStream_t);                                  \
     hipError_t encode(const float*, uint32_t, uint32_t, void*, uint32_t*, hipStream_t);                              \
     hipError_t gemv(const GemvPlan&, AccMode, const void*, const float*, float*, double*, hipStream_t);              \
-    hipError_t mrhs(const MrhsPlan&, bool, const void*, const void*, uint32_t, uint32_t, float*, uint32_t, double*,     \
+    hipError_t mrhs(const MrhsPlan&, const void*, const void*, uint32_t, uint32_t, float*, uint32_t, double*,           \
                     hipStream_t);                                                                                      \
     }
 WH_FOR_EACH_NW(X)
@@ -199,17 +199,20 @@ hipError_t whz_gemv(uint32_t rate, const GemvPlan& pl, AccMode mode, const void*
 }
 
 MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_t row_end, int num_cus, uint32_t k,
-                       uint32_t slabs)
+                       bool bf16, const GemvTuning* tune)
 {
     (void)rows;
+    const uint32_t slabs = tune ? tune->mrhs_slabs : 0;
     MrhsPlan pl{};
+    const MrhsMath math = mrhs_math(k, bf16, tune && tune->mrhs_fp32);
+    pl.math = (uint32_t)math;
     pl.nbc = (cols + 3) / 4;
     pl.bi_begin = row_begin / 4;
     pl.bi_end = (row_end + 3) / 4;
     pl.cols = cols;
     pl.nrows = row_end - row_begin;
     const uint32_t nbr = pl.bi_end - pl.bi_begin;
-    const uint32_t tile_rows = 4u * (uint32_t)mrhs_waves((int)((k + 15) / 16));
+    const uint32_t tile_rows = 4u * (uint32_t)mrhs_waves((int)((k + 15) / 16), math);
     pl.ntiles = (nbr + tile_rows - 1) / tile_rows;
     // two workgroups are resident per CU; about two rounds of them, then the
     // slab count rounded up to a multiple of 8: on 65536^2 with up to 16
@@ -225,11 +228,12 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
         nslab = 1;
     if (max_slabs >= 8)
         nslab = (nslab + 7) / 8 * 8;
-    // the FP64 partials (slabs x k x rows) stay within 64 MiB: 8 slabs of 16
-    // right-hand sides over 65536 rows, 2 of 64; short row ranges (few tiles,
-    // which need the slabs to fill the device) keep theirs
+    // the FP64 partials (slabs x k x rows) stay within 256 MiB: 8 slabs of up
+    // to 64 right-hand sides over 65536 rows (at k = 64, 8 slabs take 7.27 ms
+    // where 2 took 7.60); short row ranges (few tiles, which need the slabs to
+    // fill the device) keep theirs
     const uint64_t per_slab = (uint64_t)std::max<uint32_t>(k, 1) * nbr * 4;
-    const uint32_t cap = (uint32_t)std::max<uint64_t>(1, (8ull << 20) / std::max<uint64_t>(per_slab, 1));
+    const uint32_t cap = (uint32_t)std::max<uint64_t>(1, (32ull << 20) / std::max<uint64_t>(per_slab, 1));
     if (nslab > cap)
         nslab = cap;
     if (slabs)
@@ -245,15 +249,15 @@ MrhsPlan whz_mrhs_plan(uint32_t rows, uint32_t cols, uint32_t row_begin, uint32_
     return pl;
 }
 
-hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu,
-                    uint32_t k, float* Y, uint32_t ldy, double* part, hipStream_t st)
+hipError_t whz_mrhs(uint32_t rate, const MrhsPlan& pl, const void* stream, const void* U, uint32_t ldu, uint32_t k,
+                    float* Y, uint32_t ldy, double* part, hipStream_t st)
 {
     if (pl.ntiles == 0)
         return hipSuccess;
     switch (rate / 2) {
 #define X(kw)                                                                                                        \
     case kw:                                                                                                         \
-        return nw##kw::mrhs(pl, bf16, stream, U, ldu, k, Y, ldy, part, st);
+        return nw##kw::mrhs(pl, stream, U, ldu, k, Y, ldy, part, st);
         WH_FOR_EACH_NW(X)
 #undef X
     default:

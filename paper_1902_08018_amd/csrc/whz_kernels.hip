@@ -473,6 +473,18 @@ __global__ void __launch_bounds__(kGemvThreads<NW>) gemv_kernel(const uint32_t* 
 //   BF16 U   two halves of 8 block columns, written rounded to BF16 and
 //            contracted with v_mfma_f32_16x16x32_bf16 (K = 32), 1 MFMA per
 //            half and 16 right-hand sides
+//   X6       FP32 U from 17 right-hand sides up: the halves of the BF16
+//            path, with every FP32 coefficient and every FP32 value of B^T U
+//            split into three BF16 parts by truncation (x = x1 + x2 + x3
+//            exactly: 8 significant bits each).  Of the nine products of
+//            parts, the six whose order is at most 2^-16 of the whole (1.1,
+//            1.2, 2.1, 1.3, 2.2, 3.1) are accumulated: 6 MFMAs per half and
+//            16 right-hand sides.  Every BF16 product is exact in FP32, and
+//            the three dropped ones are below 2^-21 of the product (the
+//            split of Henry, Tang and Heinecke, "Leveraging the bfloat16
+//            artificial intelligence datatype for higher-precision
+//            computations", ARITH 2019).  BF16 MFMAs run beside the
+//            decoder's VALU work, where FP32 ones do not
 // Operand layouts (16x16 output tile D[i][j], lane l):
 //   A[i][kk]  lane = i + 16*(kk/g), element kk % g   (g = 1 FP32, 8 BF16)
 //   B[kk][j]  lane = j + 16*(kk/g), element kk % g
@@ -480,8 +492,11 @@ __global__ void __launch_bounds__(kGemvThreads<NW>) gemv_kernel(const uint32_t* 
 // so each lane's four accumulators are the four coefficient rows of one
 // block row.  The FP32 MFMA accumulators cover one step (K = 64); after
 // every step they are added into FP64 sums.
-static_assert(4 * mrhs_waves(1) <= (int)kMrhsMaxTileBlockRows && 4 * mrhs_waves(4) <= (int)kMrhsMaxTileBlockRows,
+static_assert(4 * mrhs_waves(1, MrhsMath::F32) <= (int)kMrhsMaxTileBlockRows &&
+                  4 * mrhs_waves(4, MrhsMath::F32) <= (int)kMrhsMaxTileBlockRows &&
+                  4 * mrhs_waves(2, MrhsMath::X6) <= (int)kMrhsMaxTileBlockRows,
               "block rows per multi-RHS workgroup");
+constexpr int kMathF32 = (int)MrhsMath::F32, kMathBf16 = (int)MrhsMath::Bf16, kMathX6 = (int)MrhsMath::X6;
 constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's quarter tile
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
@@ -498,6 +513,23 @@ __device__ __forceinline__ uint16_t to_bf16_rne(float f)
 }
 
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// x = x1 + x2 + x3 exactly, each part a BF16 value (8 significant bits, cut
+// by truncation), returned as FP32 bit patterns whose low halves are zero.
+__device__ __forceinline__ void split3_bf16(float x, uint32_t& x1, uint32_t& x2, uint32_t& x3)
+{
+    x1 = __float_as_uint(x) & 0xFFFF0000u;
+    const float r = x - __uint_as_float(x1); // exact: the low 16 bits of x's significand
+    x2 = __float_as_uint(r) & 0xFFFF0000u;
+    x3 = __float_as_uint(r - __uint_as_float(x2)); // exact, at most 8 significant bits
+}
+
+// Two BF16 values (the high halves of two FP32 bit patterns) in one word,
+// the first in the low half.
+__device__ __forceinline__ uint32_t pack_hi16(uint32_t lo_src, uint32_t hi_src)
+{
+    return (lo_src >> 16) | (hi_src & 0xFFFF0000u);
+}
 
 // Orders the LDS accesses of the lanes of one wave: writes before it are
 // visible to reads after it in every lane of the wave, and no access moves
@@ -519,13 +551,16 @@ __device__ __forceinline__ void wave_sync_lds()
 //   BF16  bf16[bc / 2][n][16][8]:   for lane (j, g) of a K = 32 MFMA, the
 //                                   eight values (bc & 1, m) of block
 //                                   columns 2p, 2p + 1: one 16-byte load
+//   X6    bf16[bc / 2][n][3][16][8]: the BF16 layout for each of the three
+//                                   parts of the FP32 values
 // One thread per (right-hand side, block column), block columns fastest so
 // that the loads of U are contiguous.
-template <bool BF16U>
+template <int MATH>
 __global__ void __launch_bounds__(kThreads) mrhs_btu_kernel(const void* __restrict__ Uv, uint32_t ldu, uint32_t k,
                                                             uint32_t nt, uint32_t cols, uint32_t nbc16,
                                                             void* __restrict__ out)
 {
+    constexpr bool BF16U = MATH == kMathBf16;
     const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= (uint64_t)nbc16 * 16 * nt)
         return;
@@ -557,6 +592,16 @@ __global__ void __launch_bounds__(kThreads) mrhs_btu_kernel(const void* __restri
 #pragma unroll
         for (int m = 0; m < 4; ++m)
             o[m] = to_bf16_rne(ut[m]);
+    } else if constexpr (MATH == kMathX6) {
+        uint16_t* o = static_cast<uint16_t*>(out) + ((((uint64_t)(bc >> 1) * nt + n) * 3 * 16 + jj) * 8 + (bc & 1u) * 4);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            uint32_t p1, p2, p3;
+            split3_bf16(ut[m], p1, p2, p3);
+            o[m] = (uint16_t)(p1 >> 16);
+            o[16 * 8 + m] = (uint16_t)(p2 >> 16);
+            o[2 * 16 * 8 + m] = (uint16_t)(p3 >> 16);
+        }
     } else {
         float* o = static_cast<float*>(out) + (((uint64_t)bc * nt + n) * 16 + jj) * 4;
 #pragma unroll
@@ -603,18 +648,32 @@ __device__ __forceinline__ void mrhs_load_bq(const float* __restrict__ btf, uint
 template <int NT>
 constexpr int kMrhsAhead = NT == 1 ? 3 : (NT == 2 ? 2 : 1);
 
-template <int NW, bool BF16U, int NT>
-__global__ void __launch_bounds__(64 * mrhs_waves(NT)) mrhs_kernel(const uint32_t* __restrict__ stream,
-                                                                   const void* __restrict__ btu, uint32_t k,
-                                                                   float* __restrict__ Y, uint32_t ldy,
-                                                                   double* __restrict__ part, uint32_t nbc,
-                                                                   uint32_t bi_begin, uint32_t bi_end,
-                                                                   uint32_t slab_bc, uint32_t nslab, uint32_t nrows_out)
+// X6: the B operand words (three parts, 16 bytes each) of one half and one
+// group of 16 right-hand sides for this lane.
+template <int NT>
+__device__ __forceinline__ void mrhs_load_bx(const uint16_t* __restrict__ btb, uint32_t cb, int h, int n, int lane,
+                                             u32x4 (&b)[3])
 {
-    constexpr int W = mrhs_waves(NT), T = 64 * W;
+    const uint32_t g = (uint32_t)lane >> 4, j = (uint32_t)lane & 15u;
+    const uint16_t* p = btb + ((((uint64_t)(cb / 2 + 4 * h + g) * NT + n) * 3 * 16 + j) * 8);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        b[q] = *reinterpret_cast<const u32x4*>(p + q * 16 * 8);
+}
+
+template <int NW, int MATH, int NT>
+__global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH))
+    mrhs_kernel(const uint32_t* __restrict__ stream, const void* __restrict__ btu, uint32_t k, float* __restrict__ Y,
+                uint32_t ldy, double* __restrict__ part, uint32_t nbc, uint32_t bi_begin, uint32_t bi_end,
+                uint32_t slab_bc, uint32_t nslab, uint32_t nrows_out)
+{
+    constexpr bool BF16U = MATH == kMathBf16, X6 = MATH == kMathX6;
+    constexpr int W = mrhs_waves(NT, (MrhsMath)MATH), T = 64 * W;
     __shared__ uint32_t lds[T * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
-    __shared__ __align__(16) float atile[W][16 * kATileStride];
+    // the wave's A tile: FP32 quarters, or BF16 halves (three of them, one per
+    // part, for X6)
+    __shared__ __align__(16) float atile[W][(X6 ? 3 : 1) * 16 * kATileStride];
     uint32_t* row = lds + threadIdx.x;
     clear_pad<NW, T>(row);
     load_section_table<T>(tab); // the last workgroup barrier
@@ -668,9 +727,12 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT)) mrhs_kernel(const uint32_
         // ---- B operands in flight during the decode (block columns cb ..
         // cb + 15 lie inside the workspace: it spans whole steps)
         constexpr int AH = kMrhsAhead<NT>;
-        f32x4 bq[BF16U ? 1 : AH][NT];
+        f32x4 bq[MATH == kMathF32 ? AH : 1][NT];
         u32x4 bh[BF16U ? 2 : 1][NT];
-        if constexpr (BF16U) {
+        u32x4 bx[X6 ? 2 : 1][3]; // X6: the B parts of the next (half, group), and the one after
+        if constexpr (X6) {
+            mrhs_load_bx<NT>(btb, cb, 0, 0, lane, bx[0]);
+        } else if constexpr (BF16U) {
             const uint32_t g = (uint32_t)lane >> 4, j = (uint32_t)lane & 15u;
 #pragma unroll
             for (int h = 0; h < 2; ++h)
@@ -697,7 +759,7 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT)) mrhs_kernel(const uint32_
 #pragma unroll
         for (int n = 0; n < NT; ++n)
             acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
-        if constexpr (!BF16U) {
+        if constexpr (MATH == kMathF32) {
             // ---- four quarters of 4 block columns: write, then contract
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -725,6 +787,65 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT)) mrhs_kernel(const uint32_
                 if (q + AH < 4) // the quarter after next into the slot just used
                     mrhs_load_bq<NT>(btf, cb + 4 * (q + AH), lane, bq[slot]);
             }
+        } else if constexpr (X6) {
+            // ---- the coefficients' three BF16 parts, packed in pairs; both
+            // halves' A operands are read before any MFMA, so that the packed
+            // words die first (the tile is then written twice)
+            uint32_t pk[3][8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                uint32_t a1, a2, a3, b1, b2, b3;
+                split3_bf16(sc[2 * v], a1, a2, a3);
+                split3_bf16(sc[2 * v + 1], b1, b2, b3);
+                pk[0][v] = pack_hi16(a1, b1);
+                pk[1][v] = pack_hi16(a2, b2);
+                pk[2][v] = pack_hi16(a3, b3);
+            }
+            uint16_t* at16 = reinterpret_cast<uint16_t*>(at);
+            constexpr int kPart = 16 * kATile16Stride; // BF16 elements per part's tile
+            u32x4 av[2][3];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                wave_sync_lds();
+                if ((c >> 3) == h) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            *reinterpret_cast<u32x2*>(at16 + q * kPart + (4 * t + r) * kATile16Stride + 4 * (c & 7)) =
+                                u32x2{pk[q][2 * r], pk[q][2 * r + 1]};
+                }
+                wave_sync_lds();
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    av[h][q] = *reinterpret_cast<const u32x4*>(at16 + q * kPart + (lane & 15) * kATile16Stride +
+                                                               8 * (lane >> 4));
+            }
+            // ---- per half and group of 16 right-hand sides, six MFMAs; the
+            // B parts of the next (half, group) load meanwhile
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const int cur = (h * NT + n) & 1;
+                    if (h * NT + n + 1 < 2 * NT) {
+                        const int h2 = (h * NT + n + 1) / NT, n2 = (h * NT + n + 1) % NT;
+                        mrhs_load_bx<NT>(btb, cb, h2, n2, lane, bx[cur ^ 1]);
+                    }
+                    const mbf16x8 a1 = __builtin_bit_cast(mbf16x8, av[h][0]);
+                    const mbf16x8 a2 = __builtin_bit_cast(mbf16x8, av[h][1]);
+                    const mbf16x8 a3 = __builtin_bit_cast(mbf16x8, av[h][2]);
+                    const mbf16x8 b1 = __builtin_bit_cast(mbf16x8, bx[cur][0]);
+                    const mbf16x8 b2 = __builtin_bit_cast(mbf16x8, bx[cur][1]);
+                    const mbf16x8 b3 = __builtin_bit_cast(mbf16x8, bx[cur][2]);
+                    // smallest products first
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b1, acc[n], 0, 0, 0);
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2, acc[n], 0, 0, 0);
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b3, acc[n], 0, 0, 0);
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b1, acc[n], 0, 0, 0);
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b2, acc[n], 0, 0, 0);
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[n], 0, 0, 0);
+                }
         } else {
             // ---- two halves of 8 block columns (K = 32): the lanes of a half
             // write their blocks' coefficients, rounded to BF16, to the tile
@@ -900,43 +1021,54 @@ hipError_t launch_gemv(const GemvPlan& pl, AccMode mode, const uint32_t* s, cons
     return hipGetLastError();
 }
 
-template <int NW, bool BF, int NT>
+template <int NW, int MATH, int NT>
 hipError_t launch_mrhs_t(const MrhsPlan& pl, const uint32_t* s, const void* btu, uint32_t k, float* Y, uint32_t ldy,
                          double* part, hipStream_t st)
 {
-    hipLaunchKernelGGL((mrhs_kernel<NW, BF, NT>), dim3(pl.ntiles * pl.nslab), dim3(64 * mrhs_waves(NT)), 0, st, s,
-                       btu, k, Y, ldy, part, pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab, pl.nrows);
+    hipLaunchKernelGGL((mrhs_kernel<NW, MATH, NT>), dim3(pl.ntiles * pl.nslab),
+                       dim3(64 * mrhs_waves(NT, (MrhsMath)MATH)), 0, st, s, btu, k, Y, ldy, part, pl.nbc, pl.bi_begin,
+                       pl.bi_end, pl.slab_bc, pl.nslab, pl.nrows);
     return hipGetLastError();
 }
 
 template <int NW>
-hipError_t launch_mrhs(const MrhsPlan& pl, bool bf16, const uint32_t* s, const void* U, uint32_t ldu, uint32_t k,
-                       float* Y, uint32_t ldy, double* ws, hipStream_t st)
+hipError_t launch_mrhs(const MrhsPlan& pl, const uint32_t* s, const void* U, uint32_t ldu, uint32_t k, float* Y,
+                       uint32_t ldy, double* ws, hipStream_t st)
 {
     const int nt = (int)((k + 15) / 16);
-    const MrhsWorkspace w = mrhs_workspace(pl, k, bf16);
+    const MrhsMath math = (MrhsMath)pl.math;
+    if (math == MrhsMath::X6 && nt < 2)
+        return hipErrorInvalidValue; // the planner gives X6 only from 17 right-hand sides up
+    const MrhsWorkspace w = mrhs_workspace(pl, k);
     double* part = pl.nslab > 1 ? ws : nullptr;
     void* btu = ws + w.btu_offset;
     const uint32_t nbc16 = (pl.nbc + 15) / 16 * 16;
     const uint64_t items = (uint64_t)nbc16 * 16 * nt;
-    if (bf16)
-        hipLaunchKernelGGL(mrhs_btu_kernel<true>, dim3((unsigned)((items + kThreads - 1) / kThreads)), dim3(kThreads),
-                           0, st, U, ldu, k, (uint32_t)nt, pl.cols, nbc16, btu);
+    const dim3 bgrid((unsigned)((items + kThreads - 1) / kThreads));
+    if (math == MrhsMath::Bf16)
+        hipLaunchKernelGGL(mrhs_btu_kernel<kMathBf16>, bgrid, dim3(kThreads), 0, st, U, ldu, k, (uint32_t)nt, pl.cols,
+                           nbc16, btu);
+    else if (math == MrhsMath::X6)
+        hipLaunchKernelGGL(mrhs_btu_kernel<kMathX6>, bgrid, dim3(kThreads), 0, st, U, ldu, k, (uint32_t)nt, pl.cols,
+                           nbc16, btu);
     else
-        hipLaunchKernelGGL(mrhs_btu_kernel<false>, dim3((unsigned)((items + kThreads - 1) / kThreads)),
-                           dim3(kThreads), 0, st, U, ldu, k, (uint32_t)nt, pl.cols, nbc16, btu);
+        hipLaunchKernelGGL(mrhs_btu_kernel<kMathF32>, bgrid, dim3(kThreads), 0, st, U, ldu, k, (uint32_t)nt, pl.cols,
+                           nbc16, btu);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    switch (nt * 2 + (bf16 ? 1 : 0)) {
-    case 2: e = launch_mrhs_t<NW, false, 1>(pl, s, btu, k, Y, ldy, part, st); break;
-    case 3: e = launch_mrhs_t<NW, true, 1>(pl, s, btu, k, Y, ldy, part, st); break;
-    case 4: e = launch_mrhs_t<NW, false, 2>(pl, s, btu, k, Y, ldy, part, st); break;
-    case 5: e = launch_mrhs_t<NW, true, 2>(pl, s, btu, k, Y, ldy, part, st); break;
-    case 6: e = launch_mrhs_t<NW, false, 3>(pl, s, btu, k, Y, ldy, part, st); break;
-    case 7: e = launch_mrhs_t<NW, true, 3>(pl, s, btu, k, Y, ldy, part, st); break;
-    case 8: e = launch_mrhs_t<NW, false, 4>(pl, s, btu, k, Y, ldy, part, st); break;
-    case 9: e = launch_mrhs_t<NW, true, 4>(pl, s, btu, k, Y, ldy, part, st); break;
+    switch (nt * 3 + (int)math) {
+    case 3: e = launch_mrhs_t<NW, kMathF32, 1>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 4: e = launch_mrhs_t<NW, kMathBf16, 1>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 6: e = launch_mrhs_t<NW, kMathF32, 2>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 7: e = launch_mrhs_t<NW, kMathBf16, 2>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 8: e = launch_mrhs_t<NW, kMathX6, 2>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 9: e = launch_mrhs_t<NW, kMathF32, 3>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 10: e = launch_mrhs_t<NW, kMathBf16, 3>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 11: e = launch_mrhs_t<NW, kMathX6, 3>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 12: e = launch_mrhs_t<NW, kMathF32, 4>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 13: e = launch_mrhs_t<NW, kMathBf16, 4>(pl, s, btu, k, Y, ldy, part, st); break;
+    case 14: e = launch_mrhs_t<NW, kMathX6, 4>(pl, s, btu, k, Y, ldy, part, st); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || pl.nslab == 1)
@@ -982,10 +1114,10 @@ hipError_t gemv(const GemvPlan& pl, AccMode mode, const void* stream, const floa
     return launch_gemv<WH_NW>(pl, mode, static_cast<const uint32_t*>(stream), u, y, part, st);
 }
 
-hipError_t mrhs(const MrhsPlan& pl, bool bf16, const void* stream, const void* U, uint32_t ldu, uint32_t k, float* Y,
+hipError_t mrhs(const MrhsPlan& pl, const void* stream, const void* U, uint32_t ldu, uint32_t k, float* Y,
                 uint32_t ldy, double* part, hipStream_t st)
 {
-    return launch_mrhs<WH_NW>(pl, bf16, static_cast<const uint32_t*>(stream), U, ldu, k, Y, ldy, part, st);
+    return launch_mrhs<WH_NW>(pl, static_cast<const uint32_t*>(stream), U, ldu, k, Y, ldy, part, st);
 }
 
 } // namespace nwN

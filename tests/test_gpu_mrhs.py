@@ -1,10 +1,14 @@
 """GPU parity of the multi-right-hand-side path (decode -> LDS -> MFMA).
 
 Reference: the oracle-decoded matrix in FP64 times the k vectors (a plain
-FP64 matrix product of the oracle's decode).  Bounds: FP32 vectors on the
-FP32 matrix cores, relative L2 1e-6 per right-hand side; BF16 vectors (the
-decoded values rounded to BF16 for the contraction), 2e-3.
+FP64 matrix product of the oracle's decode).  Bounds: FP32 vectors, relative
+L2 1e-6 per right-hand side, whether they run on the FP32 matrix cores (up
+to 16 right-hand sides, or always with WH_MRHS_FP32=1) or split into three
+BF16 parts on the BF16 matrix cores (from 17 up); BF16 vectors (the decoded
+values rounded to BF16 for the contraction), 2e-3.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -63,13 +67,13 @@ def test_mrhs_bf16(gpu_ctx, small_mrhs, k):
 
 @pytest.mark.parametrize("shape", [(4, 4), (68, 260), (260, 68), (1028, 1092)])
 @pytest.mark.parametrize("rate", [8, 16])
-def test_mrhs_ragged(gpu_ctx, shape, rate):
+@pytest.mark.parametrize("k", [5, 40])
+def test_mrhs_ragged(gpu_ctx, shape, rate, k):
     rows, cols = shape
     spec = synth.MatrixSpec(rows, cols, 32, 8.0, seed=13)
     M = synth.matrix(spec)
     s = oracle.encode(M, rate)
     Mhat = oracle.decode(s, rows, cols, rate).astype(np.float64)
-    k = 5
     ldu, ldy = cols + 12, rows + 8  # padded leading dimensions
     Upad = np.zeros((k, ldu), dtype=np.float32)
     Upad[:, :cols] = synth.uniform(k * cols, seed=13).reshape(k, cols)
@@ -117,7 +121,7 @@ def test_mrhs_argument_errors(gpu_ctx, small_mrhs):
 
 
 @pytest.mark.parametrize("rate", [2, 4, 6])
-@pytest.mark.parametrize("k", [3, 16])
+@pytest.mark.parametrize("k", [3, 16, 40])
 def test_mrhs_low_rates_wide_range(gpu_ctx, rate, k):
     """Rates where the bit budget cuts coefficients to their top planes,
     on wide-range data (rows scaled by 2^-30 .. 2^10, signs mixed): blocks
@@ -134,3 +138,35 @@ def test_mrhs_low_rates_wide_range(gpu_ctx, rate, k):
     torch.cuda.synchronize()
     assert per_rhs_rel_l2(Y.cpu().numpy(), ref).max() <= 1e-6
     wh.wh_unload(gpu_ctx, mat)
+
+
+@pytest.mark.parametrize("k", [17, 33, 64])
+def test_mrhs_split_bf16_against_fp32_cores(small_mrhs, k):
+    """From 17 right-hand sides up FP32 vectors run as three BF16 parts on
+    the BF16 matrix cores; a context made with WH_MRHS_FP32=1 keeps them on
+    the FP32 cores.  Both are within 1e-6 of the oracle, and within 1e-6 of
+    each other."""
+    s, Mhat = small_mrhs
+    U = synth.u_batch(synth.SMALL, k)
+    ref = U.astype(np.float64) @ Mhat.T
+    out = {}
+    for force in (0, 1):
+        old = os.environ.pop("WH_MRHS_FP32", None)
+        if force:
+            os.environ["WH_MRHS_FP32"] = "1"  # read by wh_create
+        try:
+            ctx = wh.wh_create(0, 0)
+        finally:
+            os.environ.pop("WH_MRHS_FP32", None)
+            if old is not None:
+                os.environ["WH_MRHS_FP32"] = old
+        mat = wh.wh_load_compressed(ctx, 4096, 4096, wh.WH_FMT_ZFP_FIXED_RATE, 8, torch.from_numpy(s).cuda())
+        Y = torch.empty((k, 4096), dtype=torch.float32, device="cuda")
+        wh.wh_gemv_batched(ctx, mat, torch.from_numpy(U).cuda(), Y)
+        torch.cuda.synchronize()
+        out[force] = Y.cpu().numpy()
+        wh.wh_destroy(ctx)
+        err = per_rhs_rel_l2(out[force], ref)
+        print(f"k={k} {'FP32 cores' if force else 'BF16 parts'}: worst per-RHS rel-L2 {err.max():.3e}")
+        assert err.max() <= 1e-6
+    assert per_rhs_rel_l2(out[0], out[1].astype(np.float64)).max() <= 1e-6
