@@ -132,7 +132,7 @@ const char *wh_status_str(wh_status st);
  * whose requests can no longer meet their deadlines: while other work waits,
  * it gets one launch per that many of its launch times (one per launch time
  * while its own queued requests wait for free columns).
- * WH_SERVE_MARGIN_US (default 500) is the margin, in microseconds, that a
+ * WH_SERVE_MARGIN_US (default 1000) is the margin, in microseconds, that a
  * held request keeps before its deadline beyond its estimated pass.
  * WH_SERVE_CHUNK_VALUES (a positive integer, default 2^28) bounds the matrix
  * values one serving launch covers: the serving loop runs each pass over a

@@ -74,7 +74,7 @@ struct wh_ctx {
     uint64_t serve_chunk_values = 1ull << 28; // values per serving launch (WH_SERVE_CHUNK_VALUES)
     uint32_t serve_shed = 0; // shed when the queue head waited this many deadlines (WH_SERVE_SHED; 0 = never)
     double serve_pace = 4.0; // a late scan's chunk times per launch while other work waits (WH_SERVE_PACE)
-    double serve_margin_ns = 5e5; // a held request's margin before its deadline (WH_SERVE_MARGIN_US)
+    double serve_margin_ns = 1e6; // a held request's margin before its deadline (WH_SERVE_MARGIN_US)
     uint64_t budget = 0;
     std::mutex mu; // guards mats / next_id
     std::unordered_map<wh_mat, wh::Matrix> mats;
