@@ -51,6 +51,7 @@
 // stream keeps the default priority.
 #include <hip/hip_runtime.h>
 
+#include <sys/prctl.h>
 #include <time.h>
 
 #include <algorithm>
@@ -540,6 +541,10 @@ void fail_all(Server* sv, wh_status st)
 void worker_main(Server* sv)
 {
     (void)hipSetDevice(sv->ctx->device);
+    // the loop's short sleeps (20 us while launches run, until a hold ends)
+    // should end when due: the default 50 us timer slack would let them run
+    // on, so this thread asks for 1 us
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(sv->mu);
     while (!sv->stop) {
         // completion, in launch order per matrix: a launch's compute (t1),
