@@ -667,6 +667,13 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
     last_done = [None] * nm
     lat, miss, bsz, rejected = [], 0, [], 0
     per = [{"lat": [], "miss": 0, "rejected": 0, "queue": [], "service": []} for _ in range(nm)]
+    # the client must not pause: a garbage collection of the lists below
+    # took 25-60 ms once per run, during which no request was submitted and
+    # every one due meanwhile was late (latency counts from the scheduled
+    # arrival)
+    import gc
+    gc_was_on = gc.isenabled()
+    gc.disable()
     t0 = time.monotonic_ns() + 50_000_000
     i = 0
     done_count = 0
@@ -707,6 +714,8 @@ def bench_serving(names=("16384x16384", "32768x16384", "65536x65536"), n_measure
             if nxt > 200_000:
                 time.sleep(min(nxt, 1_000_000) * 1e-9 * 0.5)
     t_total = (time.monotonic_ns() - t0) * 1e-9
+    if gc_was_on:
+        gc.enable()
     wh.wh_destroy(ctx)
     # the last request each matrix completed, against the oracle on sampled
     # rows (its Y buffer is not reused after it: nothing else is in flight)

@@ -130,8 +130,7 @@ const char *wh_status_str(wh_status st);
  * on the BF16 matrix cores; the result stays within the FP32 tolerance).
  * WH_SERVE_PACE (a number from 1 to 16, default 4) paces a served matrix
  * whose requests can no longer meet their deadlines: while other work waits,
- * it gets one launch per that many of its launch times (one per launch time
- * while its own queued requests wait for free columns).
+ * it gets one launch per that many of its launch times.
  * WH_SERVE_MARGIN_US (default 1000) is the margin, in microseconds, that a
  * held request keeps before its deadline beyond its estimated pass.
  * WH_SERVE_CHUNK_VALUES (a positive integer, default 2^28) bounds the matrix

@@ -36,9 +36,8 @@
 //               will take.  Requests that can still meet their deadlines go
 //               by the latest time their next chunk may start (the earliest
 //               first).  A scan running late is paced at one chunk per
-//               ctx->serve_pace of its chunk times while that work waits
-//               (full speed while its own requests wait for columns), and
-//               takes what is left over
+//               ctx->serve_pace of its chunk times while that work waits,
+//               and takes what is left over
 //   copies      vectors in and results out travel on two copy streams, so
 //               the transfers overlap the launches: a launch waits only for
 //               the copies of the requests that join at it, and results bound
@@ -305,10 +304,18 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
                 return WH_ERR_DEVICE;
             e = hipGraphInstantiate(&ms.exec[ci * kNumBuckets + b], g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
-            if (e != hipSuccess)
+            if (e != hipSuccess || hipGraphUpload(ms.exec[ci * kNumBuckets + b], st) != hipSuccess)
                 return WH_ERR_DEVICE;
         }
     }
+    // every bucket's graph runs once here (over the zeroed columns), so that
+    // the first launch of each in the loop does not set anything up
+    for (int b = 0; b < kNumBuckets; ++b)
+        for (size_t ci = 0; ci < ms.chunks.size(); ++ci)
+            if (hipGraphLaunch(ms.exec[ci * kNumBuckets + b], st) != hipSuccess)
+                return WH_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return WH_ERR_DEVICE;
     ms.chunk_ms = ms.chunk_ms_max = model;
     return WH_OK;
 }
@@ -460,10 +467,9 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
 // (measured chunk times), the launches that may be ahead of it (`ahead_ns`)
 // and ctx->serve_margin_ns remain before the most urgent one's deadline.
 // A scan running late gets one chunk launch per ctx->serve_pace of its
-// measured chunk times while other work competes (one per chunk time while
-// its queued requests wait for columns), so its pass takes about that many
-// times as long as it would alone and the rest of the device is left to
-// requests that can still meet their deadlines.
+// measured chunk times while other work competes, so that the rest of the
+// device is left to requests that can still meet their deadlines; it takes
+// whatever time they leave over.
 
 // Called with sv->mu held.  When a matrix's next chunk launch should start:
 // the latest start of its requests that can still meet their deadlines
@@ -670,10 +676,7 @@ void worker_main(Server* sv)
             if (!pick)
                 break;
             if (pick == late_pick) { // the next paced start, at most one step either side of now
-                // at full speed while its queued requests wait for columns
-                const bool backlog = !pick->pending.empty() &&
-                                     !take_cols(pick->used, sv->reqs.at(pick->pending.front()).r.k);
-                const double step = (backlog ? 1.0 : sv->ctx->serve_pace) * pick->chunk_ms * 1e6;
+                const double step = sv->ctx->serve_pace * pick->chunk_ms * 1e6;
                 pick->pace_ns = std::min((double)now + step, std::max((double)now - step, late_key) + step);
             }
             const wh_status st = issue_chunk(sv, *pick);
