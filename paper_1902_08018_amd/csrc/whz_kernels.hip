@@ -661,6 +661,11 @@ __device__ __forceinline__ void mrhs_load_bx(const uint16_t* __restrict__ btb, u
         b[q] = *reinterpret_cast<const u32x4*>(p + q * 16 * 8);
 }
 
+// X6: (half, group) B parts loaded ahead of their MFMAs, the first of them
+// before the decode (one, two or three ahead time the same at 65536^2, k = 64:
+// 7.29 / 7.27 / 7.28 ms; two take the fewest registers).
+constexpr int kX6Ahead = 2;
+
 template <int NW, int MATH, int NT>
 __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH))
     mrhs_kernel(const uint32_t* __restrict__ stream, const void* __restrict__ btu, uint32_t k, float* __restrict__ Y,
@@ -729,9 +734,12 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH))
         constexpr int AH = kMrhsAhead<NT>;
         f32x4 bq[MATH == kMathF32 ? AH : 1][NT];
         u32x4 bh[BF16U ? 2 : 1][NT];
-        u32x4 bx[X6 ? 2 : 1][3]; // X6: the B parts of the next (half, group), and the one after
+        // X6: the B parts of the (half, group) in use and the kX6Ahead after it
+        u32x4 bx[X6 ? kX6Ahead + 1 : 1][3];
         if constexpr (X6) {
-            mrhs_load_bx<NT>(btb, cb, 0, 0, lane, bx[0]);
+#pragma unroll
+            for (int i = 0; i < kX6Ahead; ++i)
+                mrhs_load_bx<NT>(btb, cb, i / NT, i % NT, lane, bx[i]);
         } else if constexpr (BF16U) {
             const uint32_t g = (uint32_t)lane >> 4, j = (uint32_t)lane & 15u;
 #pragma unroll
@@ -827,11 +835,10 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH))
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
-                    const int cur = (h * NT + n) & 1;
-                    if (h * NT + n + 1 < 2 * NT) {
-                        const int h2 = (h * NT + n + 1) / NT, n2 = (h * NT + n + 1) % NT;
-                        mrhs_load_bx<NT>(btb, cb, h2, n2, lane, bx[cur ^ 1]);
-                    }
+                    const int i = h * NT + n, cur = i % (kX6Ahead + 1);
+                    if (i + kX6Ahead < 2 * NT)
+                        mrhs_load_bx<NT>(btb, cb, (i + kX6Ahead) / NT, (i + kX6Ahead) % NT, lane,
+                                         bx[(i + kX6Ahead) % (kX6Ahead + 1)]);
                     const mbf16x8 a1 = __builtin_bit_cast(mbf16x8, av[h][0]);
                     const mbf16x8 a2 = __builtin_bit_cast(mbf16x8, av[h][1]);
                     const mbf16x8 a3 = __builtin_bit_cast(mbf16x8, av[h][2]);
