@@ -46,8 +46,10 @@
 //               last chunk it was are stamped done once their results are out
 //   poll        never blocks: WH_PENDING, or the result once (then retired)
 //
-// A matrix's slab partials are shared by its chunks in launch order.  Every
-// stream keeps the default priority.
+// The decisions (columns, chunks, holding, order, pacing, a launch's
+// bookkeeping) are serve_policy.hpp's, which makes no device calls; this file
+// runs them with HIP.  A matrix's slab partials are shared by its chunks in
+// launch order.  Every stream keeps the default priority.
 #include <hip/hip_runtime.h>
 
 #include <sys/prctl.h>
@@ -63,6 +65,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "serve_policy.hpp"
 #include "wh_ctx.hpp"
 #include "wh_internal.hpp"
 
@@ -77,33 +80,19 @@ uint64_t now_ns()
     return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
 
-// right-hand-side buckets of the launch graphs: the multi-RHS kernel's cost
-// steps with each group of 16
-constexpr uint32_t kBuckets[] = {1, 2, 4, 8, 16, 32, 48, 64};
-constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
-// chunk launches in flight on the device (the second keeps the stream busy
-// while the worker notices the first one end)
-constexpr size_t kMaxInflight = 2;
+using policy::kBuckets;
+using policy::kMaxInflight;
+using policy::kNumBuckets;
 // event sets per matrix: launches whose results are still being copied out
 // keep theirs a little longer
 constexpr size_t kEventSets = kMaxInflight + 4;
-static_assert(kMaxRhs == 64, "a slot's columns are the bits of a uint64_t");
-
-int bucket_index(uint32_t k)
-{
-    for (int i = 0; i < kNumBuckets; ++i)
-        if (k <= kBuckets[i])
-            return i;
-    return -1;
-}
+static_assert(kMaxRhs == policy::kSlotCols, "a slot's columns are the bits of a uint64_t");
 
 struct Req {
     wh_request r;
-    uint64_t t_arrive = 0, t_start = 0, t_done = 0;
+    policy::ReqState ps; // arrival, deadline, k; in the scan: its columns (vector i in the i-th) and chunks left
+    uint64_t t_done = 0;
     wh_status status = WH_PENDING;
-    uint32_t batch_size = 0; // requests that joined the scan at the same launch
-    uint64_t cols = 0;       // its k columns of the slot (bit c = column c), vector i in the i-th
-    uint32_t left = 0;       // chunk launches still to issue for it
 };
 
 // The events of one chunk launch: t0 and t1 around its graph and the copies
@@ -132,13 +121,7 @@ struct MatServe {
     std::vector<hipGraphExec_t> exec; // [chunk * kNumBuckets + bucket]
     std::vector<LaunchEvents> spare; // event sets not in use
     std::deque<Launch> inflight;
-    std::deque<uint64_t> pending; // queued, not yet in the scan
-    std::vector<uint64_t> active; // in the scan, chunks left to launch
-    uint64_t used = 0;            // columns held by active requests
-    uint32_t next_chunk = 0;
-    double chunk_ms = 0.0;        // running estimate of one chunk launch
-    double chunk_ms_max = 0.0;    // the longest recent one (decays)
-    double pace_ns = 0.0;         // while its scan runs late: when its next chunk is due
+    policy::ScanState st;         // queue, scan, held columns, chunk times, pace
     size_t bytes = 0;             // charged to the budget
     bool building = false, usable = false;
     wh_status build_status = WH_OK;
@@ -164,20 +147,10 @@ struct Server {
 
 namespace {
 
-// The row chunks of one served pass: consecutive ranges of whole block rows
-// holding at most `values` matrix values each (at least one block row).  A
-// matrix of at most twice that is one chunk: cutting its pass in two would
-// only let other launches in between two halves of a pass short enough to
-// meet a deadline.
+// The row chunks of one served pass (policy::chunk_rows).
 std::vector<std::pair<uint32_t, uint32_t>> serve_chunks(const Matrix& m, uint64_t values)
 {
-    if ((uint64_t)m.desc.rows * m.desc.cols <= 2 * values)
-        return {{0u, m.desc.rows}};
-    const uint64_t per = std::max<uint64_t>(4, values / std::max<uint32_t>(1, m.desc.cols) / 4 * 4);
-    std::vector<std::pair<uint32_t, uint32_t>> out;
-    for (uint64_t r0 = 0; r0 < m.desc.rows; r0 += per)
-        out.emplace_back((uint32_t)r0, (uint32_t)std::min<uint64_t>(r0 + per, m.desc.rows));
-    return out;
+    return policy::chunk_rows(m.desc.rows, m.desc.cols, values);
 }
 
 // Workspace (doubles) the k = 1 or multi-RHS plans of the chunks need: FP64
@@ -316,23 +289,9 @@ wh_status build_slot(wh_ctx* ctx, MatServe& ms)
                 return WH_ERR_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess)
         return WH_ERR_DEVICE;
-    ms.chunk_ms = ms.chunk_ms_max = model;
+    ms.st.nchunks = (uint32_t)ms.chunks.size();
+    ms.st.chunk_ms = ms.st.chunk_ms_max = model;
     return WH_OK;
-}
-
-// The k lowest free columns (any, not necessarily consecutive: a request
-// never waits for a run of them to come free), or 0 if fewer are free.
-uint64_t take_cols(uint64_t used, uint32_t k)
-{
-    uint64_t free = ~used, out = 0;
-    for (uint32_t i = 0; i < k; ++i) {
-        if (!free)
-            return 0;
-        const uint64_t low = free & (0 - free);
-        out |= low;
-        free ^= low;
-    }
-    return out;
 }
 
 // Copies between a request's k contiguous vectors of n floats at `req` and
@@ -390,69 +349,46 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
 {
     const Matrix& m = ms.m;
     const size_t cols = m.desc.cols, rows = m.desc.rows;
-    const uint32_t nchunks = (uint32_t)ms.chunks.size();
-    const uint64_t t0 = now_ns();
-    std::vector<uint64_t> joined;
-    while (!ms.pending.empty()) {
-        Req& r = sv->reqs[ms.pending.front()];
-        const uint64_t mask = take_cols(ms.used, r.r.k);
-        if (!mask)
-            break;
-        r.cols = mask;
-        r.left = nchunks;
-        r.t_start = t0;
-        ms.used |= mask;
+    const policy::LaunchPlan p =
+        policy::plan_launch(ms.st, [sv](uint64_t t) -> policy::ReqState& { return sv->reqs.at(t).ps; }, now_ns());
+    for (uint64_t t : p.joined) {
+        const Req& r = sv->reqs.at(t);
         const hipMemcpyKind kind = r.r.u_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-        if (copy_cols(ms.U, r.r.U, nullptr, mask, cols, true, kind, sv->copy_in) != hipSuccess)
+        if (copy_cols(ms.U, r.r.U, nullptr, r.ps.cols, cols, true, kind, sv->copy_in) != hipSuccess)
             return WH_ERR_DEVICE;
-        joined.push_back(ms.pending.front());
-        ms.active.push_back(ms.pending.front());
-        ms.pending.pop_front();
     }
-    for (uint64_t t : joined)
-        sv->reqs[t].batch_size = (uint32_t)joined.size();
-    if (ms.active.empty())
+    if (!p.launch)
         return WH_OK;
-    const uint32_t kmax = 64u - (uint32_t)__builtin_clzll(ms.used);
-    const int b = bucket_index(kmax);
-    const uint32_t c = ms.next_chunk;
     Launch l;
     l.ev = ms.spare.back();
     ms.spare.pop_back();
-    if (!joined.empty() && (hipEventRecord(l.ev.tu, sv->copy_in) != hipSuccess ||
-                            hipStreamWaitEvent(sv->stream, l.ev.tu, 0) != hipSuccess))
+    if (!p.joined.empty() && (hipEventRecord(l.ev.tu, sv->copy_in) != hipSuccess ||
+                              hipStreamWaitEvent(sv->stream, l.ev.tu, 0) != hipSuccess))
         return WH_ERR_DEVICE;
     if (hipEventRecord(l.ev.t0, sv->stream) != hipSuccess ||
-        hipGraphLaunch(ms.exec[(size_t)c * kNumBuckets + b], sv->stream) != hipSuccess)
+        hipGraphLaunch(ms.exec[(size_t)p.chunk * kNumBuckets + p.bucket], sv->stream) != hipSuccess)
         return WH_ERR_DEVICE;
-    ms.next_chunk = (c + 1) % nchunks;
-    size_t keep = 0;
     std::vector<const Req*> to_host;
-    for (size_t i = 0; i < ms.active.size(); ++i) {
-        Req& r = sv->reqs[ms.active[i]];
-        if (--r.left > 0) {
-            ms.active[keep++] = ms.active[i];
-            continue;
-        }
+    for (uint64_t t : p.done) {
+        const Req& r = sv->reqs.at(t);
         const hipError_t e = r.r.y_on_device
-                                 ? copy_cols(ms.Y, nullptr, r.r.Y, r.cols, rows, false, hipMemcpyDeviceToDevice,
+                                 ? copy_cols(ms.Y, nullptr, r.r.Y, r.ps.cols, rows, false, hipMemcpyDeviceToDevice,
                                              sv->stream)
-                                 : stage_cols(ms.S, ms.Y, r.cols, rows, sv->stream);
+                                 : stage_cols(ms.S, ms.Y, r.ps.cols, rows, sv->stream);
         if (e != hipSuccess)
             return WH_ERR_DEVICE;
         if (!r.r.y_on_device)
             to_host.push_back(&r);
-        l.free |= r.cols;
-        l.done.push_back(ms.active[i]);
     }
-    ms.active.resize(keep);
+    l.free = p.free;
+    l.done = p.done;
     if (hipEventRecord(l.ev.t1, sv->stream) != hipSuccess)
         return WH_ERR_DEVICE;
     if (!to_host.empty()) {
         if (hipStreamWaitEvent(sv->copy_out, l.ev.t1, 0) != hipSuccess)
             return WH_ERR_DEVICE;
         for (const Req* r : to_host)
-            if (copy_cols(ms.S, nullptr, r->r.Y, r->cols, rows, false, hipMemcpyDeviceToHost, sv->copy_out) !=
+            if (copy_cols(ms.S, nullptr, r->r.Y, r->ps.cols, rows, false, hipMemcpyDeviceToHost, sv->copy_out) !=
                 hipSuccess)
                 return WH_ERR_DEVICE;
         if (hipEventRecord(l.ev.ty, sv->copy_out) != hipSuccess)
@@ -463,75 +399,6 @@ wh_status issue_chunk(Server* sv, MatServe& ms)
     return WH_OK;
 }
 
-// The hold: a matrix's queued requests start at the latest when its pass
-// (measured chunk times), the launches that may be ahead of it (`ahead_ns`)
-// and ctx->serve_margin_ns remain before the most urgent one's deadline.
-// A scan running late gets one chunk launch per ctx->serve_pace of its
-// measured chunk times while other work competes, so that the rest of the
-// device is left to requests that can still meet their deadlines; it takes
-// whatever time they leave over.
-
-// Called with sv->mu held.  When a matrix's next chunk launch should start:
-// the latest start of its requests that can still meet their deadlines
-// (deadline less the chunks they have left, with `between_ns` for another
-// launch between two of them; `late` false), else the pace of a scan running
-// late (`late` true).  Returns false if it has nothing to launch now; then
-// `hold_until` is when its held requests must start (UINT64_MAX: nothing
-// held).  `hold`: another matrix's scan is running late; `ahead_ns`: what
-// may run before the first chunk of a pass.
-bool urgency(Server* sv, const MatServe& ms, uint64_t now, bool hold, double ahead_ns, double between_ns,
-             double& key, bool& late, uint64_t& hold_until)
-{
-    hold_until = UINT64_MAX;
-    key = 1e300;
-    late = false;
-    const double chunk_ns = ms.chunk_ms * 1e6;
-    if (hold && ms.active.empty() && !ms.pending.empty()) {
-        const double nc = (double)ms.chunks.size();
-        const double pass_ns = ms.chunk_ms_max * 1e6 * nc + between_ns * (nc - 1.0) + ahead_ns;
-        double start_by = 1e300;
-        uint32_t k = 0;
-        for (uint64_t t : ms.pending) {
-            const Req& r = sv->reqs.at(t);
-            k += r.r.k;
-            const double due = r.r.deadline_ns ? (double)(r.t_arrive + r.r.deadline_ns) : 0.0;
-            start_by = std::min(start_by, due - pass_ns - sv->ctx->serve_margin_ns);
-        }
-        if (k < kMaxRhs && (double)now < start_by) {
-            hold_until = (uint64_t)start_by;
-            return false;
-        }
-    }
-    bool any_late = false;
-    auto consider = [&](const Req& r, uint32_t left) {
-        if (!r.r.deadline_ns) {
-            any_late = true;
-            return;
-        }
-        const double due = (double)(r.t_arrive + r.r.deadline_ns);
-        const double rest = left * chunk_ns + (left > 1 ? (left - 1) * between_ns : 0.0);
-        if ((double)now + rest + ahead_ns <= due)
-            key = std::min(key, due - rest);
-        else
-            any_late = true;
-    };
-    for (uint64_t t : ms.active)
-        consider(sv->reqs.at(t), sv->reqs.at(t).left);
-    bool joinable = false;
-    if (!ms.pending.empty()) {
-        const Req& head = sv->reqs.at(ms.pending.front());
-        if (take_cols(ms.used, head.r.k)) {
-            joinable = true;
-            consider(head, (uint32_t)ms.chunks.size());
-        }
-    }
-    if (key == 1e300 && any_late) {
-        late = true;
-        key = ms.pace_ns > 0.0 ? ms.pace_ns : (double)now;
-    }
-    return !ms.active.empty() || joinable;
-}
-
 void fail_all(Server* sv, wh_status st)
 {
     sv->sticky = st;
@@ -539,8 +406,8 @@ void fail_all(Server* sv, wh_status st)
         if (kv.second.status == WH_PENDING)
             kv.second.status = st;
     for (auto& mv : sv->mats) {
-        mv.second.pending.clear();
-        mv.second.active.clear();
+        mv.second.st.pending.clear();
+        mv.second.st.active.clear();
     }
 }
 
@@ -573,10 +440,8 @@ void worker_main(Server* sv)
                 }
                 l.computed = true;
                 float ms_el = 0.f;
-                if (hipEventElapsedTime(&ms_el, l.ev.t0, l.ev.t1) == hipSuccess && ms_el > 0.f) {
-                    ms.chunk_ms = 0.8 * ms.chunk_ms + 0.2 * (double)ms_el;
-                    ms.chunk_ms_max = std::max(0.98 * ms.chunk_ms_max, (double)ms_el);
-                }
+                if (hipEventElapsedTime(&ms_el, l.ev.t0, l.ev.t1) == hipSuccess && ms_el > 0.f)
+                    policy::observe_chunk(ms.st, (double)ms_el);
             }
             while (failed == WH_OK && !ms.inflight.empty() && ms.inflight.front().computed) {
                 Launch& l = ms.inflight.front();
@@ -595,7 +460,7 @@ void worker_main(Server* sv)
                     r.t_done = t;
                     r.status = WH_OK;
                 }
-                ms.used &= ~l.free;
+                policy::release(ms.st, l.free);
                 ms.spare.push_back(l.ev);
                 ms.inflight.pop_front();
             }
@@ -612,73 +477,26 @@ void worker_main(Server* sv)
             }
             inflight = 0;
         }
-        // dispatch: the earliest latest start among requests that can still
-        // meet their deadlines, and the paced chunks of late scans between
-        // them; kMaxInflight launches in flight at most
+        // dispatch (policy::pick): the earliest latest start among requests
+        // that can still meet their deadlines, and the paced chunks of late
+        // scans between them; kMaxInflight launches in flight at most
         uint64_t wake = UINT64_MAX; // the earliest end of a hold
+        const policy::Tuning tune{sv->ctx->serve_pace, sv->ctx->serve_margin_ns};
+        auto get = [sv](uint64_t t) -> const policy::ReqState& { return sv->reqs.at(t).ps; };
         while (sv->sticky == WH_OK && inflight < kMaxInflight) {
-            const uint64_t now = now_ns();
-            // candidates: the feasible one with the earliest latest start, the
-            // late scan whose paced start is earliest
-            MatServe *feas = nullptr, *late_pick = nullptr;
-            double feas_key = 0.0, late_key = 0.0;
-            wake = UINT64_MAX;
-            // the scans running late: none of their requests can still meet
-            // its deadline
-            std::vector<const MatServe*> late_scans;
-            for (const auto& mv : sv->mats) {
-                const MatServe& o = mv.second;
-                if (!o.usable || o.active.empty())
-                    continue;
-                double key;
-                bool late;
-                uint64_t h;
-                if (urgency(sv, o, now, false, 0.0, 0.0, key, late, h) && late)
-                    late_scans.push_back(&o);
-            }
+            std::vector<policy::ScanState*> scans;
+            std::vector<MatServe*> owners;
             for (auto& mv : sv->mats) {
                 MatServe& ms = mv.second;
-                if (!ms.usable || ms.spare.empty())
-                    continue;
-                const bool hold = std::any_of(late_scans.begin(), late_scans.end(),
-                                              [&](const MatServe* o) { return o != &ms; });
-                // a launch of this matrix may wait for kMaxInflight of the
-                // longest recent launches of the others, and each further
-                // chunk of its pass for one more
-                double between_ns = 0.0;
-                for (const auto& o : sv->mats)
-                    if (&o.second != &ms && o.second.usable)
-                        between_ns = std::max(between_ns, o.second.chunk_ms_max * 1e6);
-                const double ahead_ns = between_ns * kMaxInflight;
-                double key;
-                bool late;
-                uint64_t h;
-                if (!urgency(sv, ms, now, hold, ahead_ns, between_ns, key, late, h)) {
-                    wake = std::min(wake, h);
-                    continue;
-                }
-                if (late && (!late_pick || key < late_key)) {
-                    late_pick = &ms;
-                    late_key = key;
-                } else if (!late && (!feas || key < feas_key)) {
-                    feas = &ms;
-                    feas_key = key;
-                }
+                ms.st.usable = ms.usable;
+                ms.st.can_launch = ms.usable && !ms.spare.empty();
+                scans.push_back(&ms.st);
+                owners.push_back(&ms);
             }
-            // a late scan's paced chunk goes first when its start has come
-            // and the most urgent feasible work can still start after it and
-            // the launch in flight; feasible work next; a late scan ahead of
-            // its pace only when nothing else is waiting
-            MatServe* pick = feas;
-            if (late_pick && (!feas || ((double)now >= late_key &&
-                                        feas_key - (double)now >= late_pick->chunk_ms_max * 1e6 * kMaxInflight)))
-                pick = late_pick;
-            if (!pick)
+            const int i = policy::pick(scans, get, now_ns(), tune, wake);
+            if (i < 0)
                 break;
-            if (pick == late_pick) { // the next paced start, at most one step either side of now
-                const double step = sv->ctx->serve_pace * pick->chunk_ms * 1e6;
-                pick->pace_ns = std::min((double)now + step, std::max((double)now - step, late_key) + step);
-            }
+            MatServe* pick = owners[(size_t)i];
             const wh_status st = issue_chunk(sv, *pick);
             if (st != WH_OK) {
                 sv->ctx->failed.store(true);
@@ -798,9 +616,9 @@ void serve_forget(wh_ctx* ctx, wh_mat m)
             r.t_done = now_ns();
             r.status = WH_OK;
         }
-    for (uint64_t tk : ms.active) // part of the way round the scan
+    for (uint64_t tk : ms.st.active) // part of the way round the scan
         sv->reqs[tk].status = WH_ERR_NOT_FOUND;
-    for (uint64_t tk : ms.pending) // never started
+    for (uint64_t tk : ms.st.pending) // never started
         sv->reqs[tk].status = WH_ERR_NOT_FOUND;
     if (ms.usable)
         sv->arena_used -= ms.bytes;
@@ -868,16 +686,17 @@ extern "C" wh_status wh_submit(wh_ctx* ctx, const wh_request* req, uint64_t* tic
                 ms2.part = tmp.part;
                 ms2.exec = std::move(tmp.exec);
                 ms2.spare = std::move(tmp.spare);
-                ms2.chunk_ms = tmp.chunk_ms;
-                ms2.chunk_ms_max = tmp.chunk_ms_max;
+                ms2.st.nchunks = tmp.st.nchunks;
+                ms2.st.chunk_ms = tmp.st.chunk_ms;
+                ms2.st.chunk_ms_max = tmp.st.chunk_ms_max;
                 ms2.usable = true;
             } else {
                 free_slot(tmp);
                 ms2.build_status = bst;
                 sv->arena_used -= ms2.bytes;
-                for (uint64_t tk : ms2.pending) // requests queued meanwhile
+                for (uint64_t tk : ms2.st.pending) // requests queued meanwhile
                     sv->reqs[tk].status = bst;
-                ms2.pending.clear();
+                ms2.st.pending.clear();
             }
             ms2.building = false;
             sv->cv.notify_all();
@@ -893,18 +712,20 @@ extern "C" wh_status wh_submit(wh_ctx* ctx, const wh_request* req, uint64_t* tic
         // load shedding (off unless WH_SERVE_SHED is set): the matrix's oldest
         // queued request has already waited longer than `serve_shed` of its
         // deadlines, so a new one would wait longer still
-        if (ctx->serve_shed && !ms.pending.empty()) {
-            const Req& head = sv->reqs[ms.pending.front()];
+        if (ctx->serve_shed && !ms.st.pending.empty()) {
+            const Req& head = sv->reqs[ms.st.pending.front()];
             const uint64_t now = now_ns();
-            if (head.r.deadline_ns && now > head.t_arrive &&
-                now - head.t_arrive > (uint64_t)ctx->serve_shed * head.r.deadline_ns)
+            if (head.r.deadline_ns && now > head.ps.t_arrive &&
+                now - head.ps.t_arrive > (uint64_t)ctx->serve_shed * head.r.deadline_ns)
                 return WH_ERR_BUDGET;
         }
         const uint64_t tk = sv->next_ticket++;
         Req& r = sv->reqs[tk];
         r.r = *req;
-        r.t_arrive = t;
-        ms.pending.push_back(tk);
+        r.ps.t_arrive = t;
+        r.ps.deadline_ns = req->deadline_ns;
+        r.ps.k = req->k;
+        ms.st.pending.push_back(tk);
         *ticket = tk;
         sv->cv.notify_all();
         return WH_OK;
@@ -932,11 +753,11 @@ extern "C" wh_status wh_poll(wh_ctx* ctx, uint64_t ticket, wh_result* out)
         if (r.status == WH_PENDING)
             return WH_PENDING;
         out->status = r.status;
-        out->t_arrive_ns = r.t_arrive;
-        out->t_start_ns = r.t_start;
+        out->t_arrive_ns = r.ps.t_arrive;
+        out->t_start_ns = r.ps.t_start;
         out->t_done_ns = r.t_done;
-        out->missed = r.t_done > r.t_arrive + r.r.deadline_ns ? 1 : 0;
-        out->batch_size = r.batch_size;
+        out->missed = r.t_done > r.ps.t_arrive + r.r.deadline_ns ? 1 : 0;
+        out->batch_size = r.ps.batch_size;
         const wh_status st = r.status;
         sv->reqs.erase(it);
         return st == WH_OK ? WH_OK : st;
