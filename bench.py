@@ -45,8 +45,9 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--serving", type=int, default=1, help="also run the Poisson serving load")
     ap.add_argument("--serving-requests", type=int, default=20000)
-    ap.add_argument("--leg", default="", help="'host-pipeline' (internal) or 'serving' (the three-matrix load of "
-                                              "--serving-requests requests) runs only that leg and prints its JSON")
+    ap.add_argument("--leg", default="", help="'host-pipeline' (internal), 'serving' (the three-matrix load of "
+                                              "--serving-requests requests) or 'thermal' (the thermal step) runs "
+                                              "only that leg and prints its JSON")
     ap.add_argument("--probe", type=int, default=0,
                     help="counter-pass mode, prints no JSON: 1 = 3 launches of the timed configuration, then 3 "
                          "plain 4 GiB device copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE) and 3 "
@@ -767,6 +768,10 @@ def main():
         print(json.dumps(bench_serving(n_measured=args.serving_requests)), flush=True)
         return
     ctx = wh.wh_create(0, 0)
+    if args.leg == "thermal":
+        print(json.dumps(bench_thermal(ctx, args.steps)), flush=True)
+        wh.wh_destroy(ctx)
+        return
     if args.leg == "host-pipeline":
         print(json.dumps(bench_host_pipeline(ctx, rate, args.steps)), flush=True)
         wh.wh_destroy(ctx)
