@@ -232,8 +232,12 @@ wh_status wh_gemv_plan_info(uint32_t rows, uint32_t cols, uint32_t row_begin, ui
  * cols values, vector r at d_U + r*ldu (ldu >= cols), dtype 0 = FP32,
  * 1 = BF16.  d_Y: k vectors of rows FP32 at d_Y + r*ldy (ldy >= rows).
  * 1 <= k <= 64.  zfp format only; WH_PAPER_MP only with k = 1.  The matrix
- * cores contract the scaled coefficients against B^T U (as wh_gemv, FP32;
- * with BF16 U both operands are rounded to BF16), FP64 across columns. */
+ * cores contract the scaled coefficients against B^T U (as wh_gemv), FP64
+ * across columns.  FP32 U: on the FP32 matrix cores up to 16 right-hand
+ * sides; from 17 up each FP32 operand is split into three BF16 parts and the
+ * six significant part products run on the BF16 matrix cores (within the
+ * FP32 tolerance; WH_MRHS_FP32=1 at wh_create keeps the FP32 cores).  BF16 U:
+ * both operands rounded to BF16. */
 #define WH_U_F32 0
 #define WH_U_BF16 1
 wh_status wh_gemv_batched(wh_ctx *ctx, wh_mat m, const void *d_U, int u_dtype, uint32_t k, uint32_t ldu,
