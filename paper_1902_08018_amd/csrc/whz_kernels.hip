@@ -497,7 +497,8 @@ static_assert(4 * mrhs_waves(1, MrhsMath::F32) <= (int)kMrhsMaxTileBlockRows &&
                   4 * mrhs_waves(2, MrhsMath::X6) <= (int)kMrhsMaxTileBlockRows,
               "block rows per multi-RHS workgroup");
 constexpr int kMathF32 = (int)MrhsMath::F32, kMathBf16 = (int)MrhsMath::Bf16, kMathX6 = (int)MrhsMath::X6;
-constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's quarter tile
+constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's BF16 half tile (40 BF16)
+constexpr int kATile32Stride = 32;    // floats per LDS row of a wave's FP32 half tile (swizzled)
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -666,8 +667,10 @@ __device__ __forceinline__ void mrhs_load_bx(const uint16_t* __restrict__ btb, u
 // 7.29 / 7.27 / 7.28 ms; two take the fewest registers).
 constexpr int kX6Ahead = 2;
 
+// two workgroups per CU, i.e. W / 2 waves per SIMD: the register budget the
+// compiler must meet (80 VGPRs at 12 waves, 128 at 8)
 template <int NW, int MATH, int NT>
-__global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH))
+__global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_waves(NT, (MrhsMath)MATH) / 2)
     mrhs_kernel(const uint32_t* __restrict__ stream, const void* __restrict__ btu, uint32_t k, float* __restrict__ Y,
                 uint32_t ldy, double* __restrict__ part, uint32_t nbc, uint32_t bi_begin, uint32_t bi_end,
                 uint32_t slab_bc, uint32_t nslab, uint32_t nrows_out)
@@ -676,9 +679,10 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH))
     constexpr int W = mrhs_waves(NT, (MrhsMath)MATH), T = 64 * W;
     __shared__ uint32_t lds[T * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
-    // the wave's A tile: FP32 quarters, or BF16 halves (three of them, one per
-    // part, for X6)
-    __shared__ __align__(16) float atile[W][(X6 ? 3 : 1) * 16 * kATileStride];
+    // the wave's A tile: FP32 halves (16 x 32, swizzled), BF16 halves, or
+    // three BF16 halves (one per part) for X6
+    __shared__ __align__(16) float atile[W][X6 ? 3 * 16 * kATileStride
+                                              : (MATH == kMathF32 ? 16 * kATile32Stride : 16 * kATileStride)];
     uint32_t* row = lds + threadIdx.x;
     clear_pad<NW, T>(row);
     load_section_table<T>(tab); // the last workgroup barrier
@@ -768,32 +772,45 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH))
         for (int n = 0; n < NT; ++n)
             acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
         if constexpr (MATH == kMathF32) {
-            // ---- four quarters of 4 block columns: write, then contract
+            // ---- two halves of 8 block columns: the half's lanes write their
+            // blocks to the wave's 16 x 32 tile (row 4t + r, a 4-float group
+            // per block column, the group index XORed with the row's low
+            // three bits so that the column reads below spread over the
+            // banks), then every lane reads its A operands for the half's two
+            // quarters
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int h = 0; h < 2; ++h) {
                 // the tile is the wave's own: lanes read what other lanes of
                 // the wave wrote, so each hand-over is a wave-scope
                 // release/acquire (no workgroup barrier is needed)
                 wave_sync_lds();
-                if ((c >> 2) == q) {
+                if ((c >> 3) == h) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        *reinterpret_cast<f32x4*>(at + (4 * t + r) * kATileStride + 4 * (c & 3)) =
+                    for (int r = 0; r < 4; ++r) {
+                        const int tr = 4 * t + r;
+                        *reinterpret_cast<f32x4*>(at + tr * kATile32Stride + 4 * ((c & 7) ^ (tr & 7))) =
                             f32x4{sc[4 * r], sc[4 * r + 1], sc[4 * r + 2], sc[4 * r + 3]};
+                    }
                 }
                 wave_sync_lds();
-                const int slot = q % AH;
-                // MFMA m contracts coefficient column m of the quarter's four
-                // block columns (K = block column): lane l holds A[l % 16][l / 16],
-                // coefficient (r, m) = ((l % 16) % 4, m) of block column l / 16
-                const f32x4 a4 = *reinterpret_cast<const f32x4*>(at + (lane & 15) * kATileStride + 4 * (lane >> 4));
+                const int ar = lane & 15;
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
+                for (int qq = 0; qq < 2; ++qq) {
+                    const int q = 2 * h + qq, slot = q % AH;
+                    // MFMA m contracts coefficient column m of the quarter's
+                    // four block columns (K = block column): lane l holds
+                    // A[l % 16][l / 16], coefficient (r, m) = ((l % 16) % 4, m)
+                    // of the quarter's block column l / 16
+                    const f32x4 a4 = *reinterpret_cast<const f32x4*>(
+                        at + ar * kATile32Stride + 4 * (((lane >> 4) + 4 * qq) ^ (ar & 7)));
 #pragma unroll
-                    for (int n = 0; n < NT; ++n)
-                        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[m], bq[slot][n][m], acc[n], 0, 0, 0);
-                if (q + AH < 4) // the quarter after next into the slot just used
-                    mrhs_load_bq<NT>(btf, cb + 4 * (q + AH), lane, bq[slot]);
+                    for (int m = 0; m < 4; ++m)
+#pragma unroll
+                        for (int n = 0; n < NT; ++n)
+                            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[m], bq[slot][n][m], acc[n], 0, 0, 0);
+                    if (q + AH < 4) // the quarter after next into the slot just used
+                        mrhs_load_bq<NT>(btf, cb + 4 * (q + AH), lane, bq[slot]);
+                }
             }
         } else if constexpr (X6) {
             // ---- the coefficients' three BF16 parts, packed in pairs; both
