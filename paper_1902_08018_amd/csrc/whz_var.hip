@@ -253,13 +253,28 @@ __global__ void __launch_bounds__(kVarThreads) var_decode_kernel(const uint64_t*
         var_next_block(g, lim, row, tab, mode, param, live, pos, emax, iv);
         inv_xform(iv);
         if (live) {
+            // a block row of 4 values is one 16-byte non-temporal store when
+            // the matrix's rows are whole blocks (then every such run is
+            // aligned); edge blocks of other shapes go value by value
+            const bool whole = (cols & 3u) == 0u;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 4; ++r) {
+                if (4 * bi + r >= rows)
+                    continue;
+                float v[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    if (4 * bi + r < rows && 4 * bj + c < cols)
-                        out[(uint64_t)(4 * bi + r) * cols + 4 * bj + c] =
-                            __builtin_ldexpf((float)(int32_t)iv[4 * r + c], emax - 30);
+                    v[c] = __builtin_ldexpf((float)(int32_t)iv[4 * r + c], emax - 30);
+                float* o = out + (uint64_t)(4 * bi + r) * cols + 4 * bj;
+                if (whole) {
+                    __builtin_nontemporal_store(f32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<f32x4*>(o));
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (4 * bj + c < cols)
+                            o[c] = v[c];
+                }
+            }
         }
     }
 }
