@@ -69,9 +69,11 @@ __device__ __forceinline__ uint32_t vwindow(const uint32_t* __restrict__ g, uint
 // 16 verbatim bits a plane after the first, one ending group bit a plane,
 // and across all planes at most 16 run-starting group bits and 16 run bits
 // (a run passes each coefficient once).  With P <= 32, the start offset
-// (< 32) and the last 32-bit window, every read stays below bit 632: 20
-// words hold any block.
-constexpr uint32_t kVarStage = 20, kVarPad = 3, kVarRow = kVarStage + kVarPad;
+// (< 32) and the last 32-bit window, every read stays below bit 632 of the
+// block's first word: 20 words hold any block.  The staged run starts at the
+// 16-byte boundary at or before that word (up to 3 words earlier), so that it
+// is six 16-byte loads: 24 words.
+constexpr uint32_t kVarStage = 24, kVarPad = 3, kVarRow = kVarStage + kVarPad;
 
 // Reading a lane's code straight from global memory: two loads a window.
 struct GlobalBits {
@@ -80,9 +82,9 @@ struct GlobalBits {
     __device__ __forceinline__ uint32_t window(uint32_t pos) const { return vwindow(g, lim, pos); }
 };
 
-// Reading a lane's block staged in LDS: words 0..kVarStage-1 of its view
-// from word b0 at lw[k * kVarThreads], then kVarPad zero words; positions
-// count from bit 32 * b0.  A window past the staged words reads the zero
+// Reading a lane's block staged in LDS: kVarStage words of its view from
+// word b0 at lw[k * kVarThreads], then kVarPad zero words; positions count
+// from bit 32 * b0.  A window past the staged words reads the zero
 // padding (the word index is clamped to it), so a block that runs past
 // 32 * (kVarStage - 1) bits must be decoded again from global memory.
 struct StagedBits {
@@ -200,21 +202,40 @@ __device__ __forceinline__ bool var_next_block(const uint32_t* g, uint32_t lim, 
                                                int mode, int param, bool live, uint32_t& pos, int& emax,
                                                uint32_t (&cf)[16])
 {
-    const uint32_t b0 = pos >> 5;
+    // the run of words staged: from the 16-byte boundary at or before the
+    // block's first word; a 16-byte piece inside the view is one load, a
+    // piece reaching before the view's first word or past its end is read
+    // word by word (zero outside)
+    const uint32_t m = (uint32_t)(reinterpret_cast<uintptr_t>(g + (pos >> 5)) >> 2) & 3u;
+    const int64_t b0 = (int64_t)(pos >> 5) - (int64_t)m; // may be before the view
 #pragma unroll
-    for (uint32_t k = 0; k < kVarStage; ++k)
-        row[k * kVarThreads] = live ? vword(g, lim, b0 + k) : 0u;
-    uint32_t lpos = pos & 31u;
+    for (uint32_t k = 0; k < kVarStage / 4; ++k) {
+        const int64_t s = b0 + 4 * (int64_t)k;
+        u32x4 v = u32x4{0u, 0u, 0u, 0u};
+        if (live) {
+            if (s >= 0 && s + 4 <= (int64_t)lim) {
+                v = *reinterpret_cast<const u32x4*>(g + s);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    v[i] = (s + i >= 0 && s + i < (int64_t)lim) ? g[s + i] : 0u;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            row[(4 * k + i) * kVarThreads] = v[i];
+    }
+    uint32_t lpos = 32u * m + (pos & 31u);
     bool nz = var_block_coeffs(StagedBits{row}, tab, mode, param, live, lpos, emax, cf);
     const bool over = live && lpos >= 32u * (kVarStage - 1u);
     if (__any(over)) {
         if (over) {
             uint32_t p = pos;
             nz = var_block_coeffs(GlobalBits{g, lim}, tab, mode, param, true, p, emax, cf);
-            lpos = p - 32u * b0;
+            lpos = (uint32_t)((int64_t)p - 32 * b0);
         }
     }
-    pos = 32u * b0 + lpos;
+    pos = (uint32_t)(32 * b0 + (int64_t)lpos);
     return nz;
 }
 
