@@ -39,13 +39,18 @@ namespace wh {
 
 namespace {
 
-constexpr int kVarThreads = 256;
+// Workgroup sizes: 256 lanes, or 1024 from 2^18 lanes of work up (16 waves
+// per CU share one section table, where LDS holds only two 256-lane
+// workgroups, 8 waves).
+constexpr int kVarThreadsSmall = 256, kVarThreadsLarge = 1024;
+constexpr uint64_t kVarLargeFrom = 1ull << 18;
 
 __device__ const SectionTable g_var_section_table{};
 
+template <int T>
 __device__ __forceinline__ void load_table(uint32_t* tab)
 {
-    for (int i = threadIdx.x; i < kSecEntries; i += kVarThreads)
+    for (int i = threadIdx.x; i < kSecEntries; i += T)
         tab[i] = g_var_section_table.e[i];
     __syncthreads();
 }
@@ -83,16 +88,17 @@ struct GlobalBits {
 };
 
 // Reading a lane's block staged in LDS: kVarStage words of its view from
-// word b0 at lw[k * kVarThreads], then kVarPad zero words; positions count
+// word b0 at lw[k * T], then kVarPad zero words; positions count
 // from bit 32 * b0.  A window past the staged words reads the zero
 // padding (the word index is clamped to it), so a block that runs past
 // 32 * (kVarStage - 1) bits must be decoded again from global memory.
+template <int T>
 struct StagedBits {
     const uint32_t* lw;
     __device__ __forceinline__ uint32_t window(uint32_t pos) const
     {
         const uint32_t q = __builtin_elementwise_min(pos >> 5, kVarStage + 1u);
-        return funnel(lw[(q + 1) * kVarThreads], lw[q * kVarThreads], pos & 31u);
+        return funnel(lw[(q + 1) * T], lw[q * T], pos & 31u);
     }
 };
 
@@ -198,6 +204,7 @@ __device__ __forceinline__ void lane_view(const uint32_t* code, uint64_t nwords,
 // words would be decoded again from global memory; by the bound above that
 // never happens for codes of at most 32 planes, and the check keeps a code
 // that breaks the bound (a corrupt stream) from decoding out of padding.
+template <int T>
 __device__ __forceinline__ bool var_next_block(const uint32_t* g, uint32_t lim, uint32_t* row, const uint32_t* tab,
                                                int mode, int param, bool live, uint32_t& pos, int& emax,
                                                uint32_t (&cf)[16])
@@ -223,10 +230,10 @@ __device__ __forceinline__ bool var_next_block(const uint32_t* g, uint32_t lim, 
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            row[(4 * k + i) * kVarThreads] = v[i];
+            row[(4 * k + i) * T] = v[i];
     }
     uint32_t lpos = 32u * m + (pos & 31u);
-    bool nz = var_block_coeffs(StagedBits{row}, tab, mode, param, live, lpos, emax, cf);
+    bool nz = var_block_coeffs(StagedBits<T>{row}, tab, mode, param, live, lpos, emax, cf);
     const bool over = live && lpos >= 32u * (kVarStage - 1u);
     if (__any(over)) {
         if (over) {
@@ -241,26 +248,28 @@ __device__ __forceinline__ bool var_next_block(const uint32_t* g, uint32_t lim, 
 
 // Zero the padding words after a lane's staged block (once per kernel: the
 // staging writes words 0..kVarStage-1 only).
+template <int T>
 __device__ __forceinline__ void clear_var_pad(uint32_t* row)
 {
 #pragma unroll
     for (uint32_t k = kVarStage; k < kVarRow; ++k)
-        row[k * kVarThreads] = 0u;
+        row[k * T] = 0u;
 }
 
 // Whole matrix into row-major FP32: one lane per (block row, group).
-__global__ void __launch_bounds__(kVarThreads) var_decode_kernel(const uint64_t* __restrict__ index,
+template <int T>
+__global__ void __launch_bounds__(T) var_decode_kernel(const uint64_t* __restrict__ index,
                                                                  const uint32_t* __restrict__ code, uint64_t nwords,
                                                                  int mode, int param, uint32_t rows, uint32_t cols,
                                                                  uint32_t nbc, uint32_t ngroups, uint64_t nlanes,
                                                                  float* __restrict__ out)
 {
     __shared__ uint32_t tab[kSecEntries];
-    __shared__ uint32_t stage[kVarThreads * kVarRow];
+    __shared__ uint32_t stage[T * kVarRow];
     uint32_t* row = stage + threadIdx.x;
-    clear_var_pad(row);
-    load_table(tab);
-    const uint64_t lane_id = (uint64_t)blockIdx.x * kVarThreads + threadIdx.x;
+    clear_var_pad<T>(row);
+    load_table<T>(tab);
+    const uint64_t lane_id = (uint64_t)blockIdx.x * T + threadIdx.x;
     const bool in = lane_id < nlanes;
     const uint32_t bi = in ? (uint32_t)(lane_id / ngroups) : 0u, a = in ? (uint32_t)(lane_id % ngroups) : 0u;
     const uint32_t* g;
@@ -271,7 +280,7 @@ __global__ void __launch_bounds__(kVarThreads) var_decode_kernel(const uint64_t*
         const bool live = in && bj < nbc;
         int emax;
         uint32_t iv[16];
-        var_next_block(g, lim, row, tab, mode, param, live, pos, emax, iv);
+        var_next_block<T>(g, lim, row, tab, mode, param, live, pos, emax, iv);
         inv_xform(iv);
         if (live) {
             // a block row of 4 values is one 16-byte non-temporal store when
@@ -329,11 +338,11 @@ struct VarTwoSumAcc {
 };
 
 // Fused decode + GEMV over block rows [bi_begin, bi_end): G = 2^lg lanes
-// (1..8) per block row, 512 / G block rows per workgroup; lane gl of a row
+// (1..8) per block row, T / G block rows per workgroup; lane gl of a row
 // takes group slab * G + gl (32 blocks).  Output row i of the range is
 // matrix row 4 * bi_begin + skip + i.
-template <typename Acc>
-__global__ void __launch_bounds__(kVarThreads) var_gemv_kernel(
+template <int T, typename Acc>
+__global__ void __launch_bounds__(T) var_gemv_kernel(
     const uint64_t* __restrict__ index, const uint32_t* __restrict__ code, uint64_t nwords, int mode, int param,
     const float* __restrict__ u, float* __restrict__ y, double* __restrict__ part, uint32_t nbc, uint32_t ngroups,
     uint32_t bi_begin, uint32_t bi_end, uint32_t nslab, uint32_t cols, uint32_t nrows, uint32_t skip, uint32_t lg)
@@ -341,13 +350,13 @@ __global__ void __launch_bounds__(kVarThreads) var_gemv_kernel(
     __shared__ uint32_t tab[kSecEntries];
     // the lanes' staging rows; after the blocks, the row sums per group
     // (<= 512) and row of the block
-    __shared__ double stage_d[kVarThreads * kVarRow / 2];
-    static_assert(kVarRow * kVarThreads / 2 >= 4 * kVarThreads, "the row sums fit the staging area");
+    __shared__ double stage_d[T * kVarRow / 2];
+    static_assert(kVarRow * T / 2 >= 4 * T, "the row sums fit the staging area");
     uint32_t* row = reinterpret_cast<uint32_t*>(stage_d) + threadIdx.x;
     double* red = stage_d;
-    clear_var_pad(row);
-    load_table(tab);
-    const uint32_t G = 1u << lg, groups = (uint32_t)kVarThreads >> lg;
+    clear_var_pad<T>(row);
+    load_table<T>(tab);
+    const uint32_t G = 1u << lg, groups = (uint32_t)T >> lg;
     const uint32_t grp = threadIdx.x >> lg, gl = threadIdx.x & (G - 1);
     const uint32_t tile = blockIdx.x / nslab, slab = blockIdx.x % nslab;
     const uint32_t bi = bi_begin + tile * groups + grp;
@@ -371,7 +380,7 @@ __global__ void __launch_bounds__(kVarThreads) var_gemv_kernel(
         }
         int emax;
         uint32_t iv[16];
-        const bool nz = var_next_block(g, lim, row, tab, mode, param, live, pos, emax, iv);
+        const bool nz = var_next_block<T>(g, lim, row, tab, mode, param, live, pos, emax, iv);
         if (live && nz) {
             // the exact integer inverse transform (not B (C (B^T u))): a
             // coefficient cut to its top planes can reach -2^31, where the
@@ -578,15 +587,22 @@ hipError_t var_decode(const Matrix& m, float* out, hipStream_t st)
     const uint64_t* index = static_cast<const uint64_t*>(m.dptr);
     const uint32_t* code = reinterpret_cast<const uint32_t*>(static_cast<const char*>(m.dptr) + ib);
     const uint64_t nwords = (m.nbytes - ib) / 4;
-    hipLaunchKernelGGL(var_decode_kernel, dim3(grid_of(nlanes, kVarThreads)), dim3(kVarThreads), 0, st, index, code,
-                       nwords, mode, param, m.desc.rows, m.desc.cols, nbc, ng, nlanes, out);
+    if (nlanes >= kVarLargeFrom)
+        hipLaunchKernelGGL(var_decode_kernel<kVarThreadsLarge>, dim3(grid_of(nlanes, kVarThreadsLarge)),
+                           dim3(kVarThreadsLarge), 0, st, index, code, nwords, mode, param, m.desc.rows, m.desc.cols,
+                           nbc, ng, nlanes, out);
+    else
+        hipLaunchKernelGGL(var_decode_kernel<kVarThreadsSmall>, dim3(grid_of(nlanes, kVarThreadsSmall)),
+                           dim3(kVarThreadsSmall), 0, st, index, code, nwords, mode, param, m.desc.rows, m.desc.cols,
+                           nbc, ng, nlanes, out);
     return hipGetLastError();
 }
 
 // Launch shape: G lanes per block row, the smallest power of two (1..8)
-// that covers the row's groups, or 8; slabs of G groups.
+// that covers the row's groups, or 8; slabs of G groups; workgroups of
+// `threads` lanes.
 struct VarPlan {
-    uint32_t lg, nslab, ntiles, bi_begin, bi_end;
+    uint32_t lg, nslab, ntiles, bi_begin, bi_end, threads;
 };
 
 VarPlan var_plan(const Matrix& m, uint32_t row_begin, uint32_t row_end)
@@ -599,7 +615,9 @@ VarPlan var_plan(const Matrix& m, uint32_t row_begin, uint32_t row_end)
     p.nslab = (ng + (1u << p.lg) - 1) >> p.lg;
     p.bi_begin = row_begin / 4;
     p.bi_end = (row_end + 3) / 4;
-    const uint32_t rows_per_tile = (uint32_t)kVarThreads >> p.lg;
+    const uint64_t lanes = (uint64_t)(p.bi_end - p.bi_begin) * p.nslab << p.lg;
+    p.threads = lanes >= kVarLargeFrom ? kVarThreadsLarge : kVarThreadsSmall;
+    const uint32_t rows_per_tile = p.threads >> p.lg;
     p.ntiles = (p.bi_end - p.bi_begin + rows_per_tile - 1) / rows_per_tile;
     return p;
 }
@@ -626,12 +644,23 @@ hipError_t var_gemv(const Matrix& m, AccMode acc, const float* u, float* y, uint
     const uint64_t nwords = (m.nbytes - ib) / 4;
     const uint32_t nrows = row_end - row_begin, skip = row_begin & 3u;
     const dim3 grid(p.ntiles * p.nslab);
-    if (acc == AccMode::TwoSum)
-        hipLaunchKernelGGL(var_gemv_kernel<VarTwoSumAcc>, grid, dim3(kVarThreads), 0, st, index, code, nwords, mode,
-                           param, u, y, part, nbc, ng, p.bi_begin, p.bi_end, p.nslab, m.desc.cols, nrows, skip, p.lg);
+    const dim3 block(p.threads);
+    if (acc == AccMode::TwoSum && p.threads == kVarThreadsLarge)
+        hipLaunchKernelGGL((var_gemv_kernel<kVarThreadsLarge, VarTwoSumAcc>), grid, block, 0, st, index, code, nwords,
+                           mode, param, u, y, part, nbc, ng, p.bi_begin, p.bi_end, p.nslab, m.desc.cols, nrows, skip,
+                           p.lg);
+    else if (acc == AccMode::TwoSum)
+        hipLaunchKernelGGL((var_gemv_kernel<kVarThreadsSmall, VarTwoSumAcc>), grid, block, 0, st, index, code, nwords,
+                           mode, param, u, y, part, nbc, ng, p.bi_begin, p.bi_end, p.nslab, m.desc.cols, nrows, skip,
+                           p.lg);
+    else if (p.threads == kVarThreadsLarge)
+        hipLaunchKernelGGL((var_gemv_kernel<kVarThreadsLarge, VarFp64Acc>), grid, block, 0, st, index, code, nwords,
+                           mode, param, u, y, part, nbc, ng, p.bi_begin, p.bi_end, p.nslab, m.desc.cols, nrows, skip,
+                           p.lg);
     else
-        hipLaunchKernelGGL(var_gemv_kernel<VarFp64Acc>, grid, dim3(kVarThreads), 0, st, index, code, nwords, mode,
-                           param, u, y, part, nbc, ng, p.bi_begin, p.bi_end, p.nslab, m.desc.cols, nrows, skip, p.lg);
+        hipLaunchKernelGGL((var_gemv_kernel<kVarThreadsSmall, VarFp64Acc>), grid, block, 0, st, index, code, nwords,
+                           mode, param, u, y, part, nbc, ng, p.bi_begin, p.bi_end, p.nslab, m.desc.cols, nrows, skip,
+                           p.lg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p.nslab == 1)
         return e;

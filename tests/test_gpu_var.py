@@ -9,6 +9,8 @@ Sec. 4.3, Table 2) against the oracle.
            of the oracle-decoded matrix, on row ranges that start and end
            inside block rows, FP64 and TwoSum accumulation, 1 to 8 lanes per
            block row (the number of 32-block groups in a row)
+  large    2^18 lanes and more (the 1024-lane workgroups): decode bit-exact
+           and the GEMV on sampled bands of block rows
   errors   Fig. 7 mode, batched products and short storage are refused
 """
 import numpy as np
@@ -77,6 +79,40 @@ def test_gemv(gpu_ctx, shape, fmt, param):
             yh = y.cpu().numpy()
             assert rel_l2(yh[:re - rb], ref[rb:re]) <= 1e-6, (flags, rb, re)
             assert np.all(yh[re - rb:] == -7.0)
+    wh.wh_unload(gpu_ctx, mat)
+
+
+# 2^18 lanes (one per block row and 32-block group) and more take the
+# 1024-lane workgroups; the oracle decodes sampled bands of block rows from
+# the index, among them the first, the last and bands across workgroup tiles
+# (16 block rows per decode workgroup, 128 per GEMV tile at 8 lanes a row)
+@pytest.mark.parametrize("rows,cols,fmt,param", [(16382, 8190, wh.WH_FMT_ZFP_FIXED_PRECISION, 17),
+                                                 (16384, 8192, wh.WH_FMT_ZFP_FIXED_ACCURACY, -20)])
+def test_large_launch_sampled(gpu_ctx, rows, cols, fmt, param):
+    M = synth.matrix(synth.MatrixSpec(rows, cols, 32, 8.0, seed=24))
+    rate = param if fmt == wh.WH_FMT_ZFP_FIXED_PRECISION else wh.accuracy_rate(param)
+    omode = oracle.VAR_PRECISION if fmt == wh.WH_FMT_ZFP_FIXED_PRECISION else oracle.VAR_ACCURACY
+    buf = wh.wh_encode_var(M, fmt, rate)
+    ib = wh.wh_var_index_bytes(rows, cols)
+    index = buf[:ib].view(np.uint64)
+    nbr, ng = (rows + 3) // 4, ((cols + 3) // 4 + 31) // 32
+    assert nbr * ng >= 1 << 18
+    mat = wh.wh_load_compressed(gpu_ctx, rows, cols, fmt, rate, buf)
+    out = torch.empty((rows, cols), device="cuda")
+    wh.wh_decode(gpu_ctx, mat, out)
+    u_np = synth.uniform(cols, seed=25)
+    y = torch.full((rows + 2,), -7.0, device="cuda")
+    wh.wh_gemv(gpu_ctx, mat, torch.from_numpy(u_np).cuda(), y, 0, rows, wh.WH_ACC_DEFAULT)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    assert np.all(yh[rows:] == -7.0)
+    for b0, b1 in [(0, 20), (120, 136), (1010, 1030), (2047, 2049), (nbr - 20, nbr)]:
+        r0, r1 = 4 * b0, min(4 * b1, rows)
+        want = oracle.decode_var(buf[ib:], index[b0 * ng:b1 * ng], r1 - r0, cols, omode, param)
+        got = out[r0:r1].cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (b0, b1)
+        ref = want.astype(np.float64) @ u_np.astype(np.float64)
+        assert rel_l2(yh[r0:r1], ref) <= 1e-6, (b0, b1)
     wh.wh_unload(gpu_ctx, mat)
 
 
