@@ -39,9 +39,9 @@ namespace wh {
 
 namespace {
 
-// Workgroup sizes: 256 lanes, or 1024 from 2^18 lanes of work up (16 waves
-// per CU share one section table, where LDS holds only two 256-lane
-// workgroups, 8 waves).
+// Workgroup sizes: 256 lanes, or for the fused GEMV 1024 from 2^18 lanes of
+// work up (16 waves per CU share one section table, where LDS holds only two
+// 256-lane workgroups, 8 waves).
 constexpr int kVarThreadsSmall = 256, kVarThreadsLarge = 1024;
 constexpr uint64_t kVarLargeFrom = 1ull << 18;
 
@@ -256,14 +256,22 @@ __device__ __forceinline__ void clear_var_pad(uint32_t* row)
         row[k * T] = 0u;
 }
 
-// Whole matrix into row-major FP32: one lane per (block row, group).
-template <int T>
-__global__ void __launch_bounds__(T) var_decode_kernel(const uint64_t* __restrict__ index,
-                                                                 const uint32_t* __restrict__ code, uint64_t nwords,
-                                                                 int mode, int param, uint32_t rows, uint32_t cols,
-                                                                 uint32_t nbc, uint32_t ngroups, uint64_t nlanes,
-                                                                 float* __restrict__ out)
+// Whole matrix into row-major FP32: one lane per (block row, group), in
+// 256-lane workgroups.  A lane holds kVarSpan decoded blocks in registers
+// (134 VGPRs, within the two waves per SIMD that LDS allows) and then
+// writes each of its 4 rows as kVarSpan adjacent 16-byte stores, 64
+// contiguous bytes.  The stores are ordinary (cached) ones, so that L2 can
+// gather a lane's pieces of a row into whole lines: non-temporal stores of
+// single blocks, from lanes 512 bytes apart, took 2.6 times as long at
+// 8192^2.
+constexpr int kVarSpan = 4;
+
+__global__ void __launch_bounds__(kVarThreadsSmall) var_decode_kernel(
+    const uint64_t* __restrict__ index, const uint32_t* __restrict__ code, uint64_t nwords, int mode, int param,
+    uint32_t rows, uint32_t cols, uint32_t nbc, uint32_t ngroups, uint64_t nlanes, float* __restrict__ out)
 {
+    constexpr int T = kVarThreadsSmall;
+    static_assert(32 % kVarSpan == 0, "spans tile a group");
     __shared__ uint32_t tab[kSecEntries];
     __shared__ uint32_t stage[T * kVarRow];
     uint32_t* row = stage + threadIdx.x;
@@ -275,34 +283,50 @@ __global__ void __launch_bounds__(T) var_decode_kernel(const uint64_t* __restric
     const uint32_t* g;
     uint32_t lim, pos;
     lane_view(code, nwords, in ? index[lane_id] : 0ull, g, lim, pos);
-    for (uint32_t j = 0; j < 32u; ++j) {
-        const uint32_t bj = a * 32u + j;
-        const bool live = in && bj < nbc;
-        int emax;
-        uint32_t iv[16];
-        var_next_block<T>(g, lim, row, tab, mode, param, live, pos, emax, iv);
-        inv_xform(iv);
-        if (live) {
-            // a block row of 4 values is one 16-byte non-temporal store when
-            // the matrix's rows are whole blocks (then every such run is
-            // aligned); edge blocks of other shapes go value by value
-            const bool whole = (cols & 3u) == 0u;
+    // rows of whole blocks: every span of whole blocks starts 16-byte aligned
+    const bool whole = (cols & 3u) == 0u;
+    for (uint32_t j0 = 0; j0 < 32u; j0 += kVarSpan) {
+        float v[kVarSpan][16];
+#pragma unroll kVarSpan
+        for (int s = 0; s < kVarSpan; ++s) {
+            const uint32_t bj = a * 32u + j0 + s;
+            int emax;
+            uint32_t iv[16];
+            var_next_block<T>(g, lim, row, tab, mode, param, in && bj < nbc, pos, emax, iv);
+            inv_xform(iv);
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                v[s][i] = __builtin_ldexpf((float)(int32_t)iv[i], emax - 30);
+        }
+        const uint32_t bj0 = a * 32u + j0;
+        if (!in || bj0 >= nbc)
+            continue;
+        if (whole && bj0 + kVarSpan <= nbc) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 if (4 * bi + r >= rows)
                     continue;
-                float v[4];
+                f32x4* o = reinterpret_cast<f32x4*>(out + (uint64_t)(4 * bi + r) * cols + 4 * bj0);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    v[c] = __builtin_ldexpf((float)(int32_t)iv[4 * r + c], emax - 30);
-                float* o = out + (uint64_t)(4 * bi + r) * cols + 4 * bj;
-                if (whole) {
-                    __builtin_nontemporal_store(f32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<f32x4*>(o));
-                } else {
+                for (int s = 0; s < kVarSpan; ++s)
+                    o[s] = f32x4{v[s][4 * r], v[s][4 * r + 1], v[s][4 * r + 2], v[s][4 * r + 3]};
+            }
+        } else {
+            // the matrix edge: value by value
+#pragma unroll
+            for (int s = 0; s < kVarSpan; ++s) {
+                const uint32_t bj = bj0 + s;
+                if (bj >= nbc)
+                    continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (4 * bi + r >= rows)
+                        continue;
+                    float* o = out + (uint64_t)(4 * bi + r) * cols + 4 * bj;
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
                         if (4 * bj + c < cols)
-                            o[c] = v[c];
+                            o[c] = v[s][4 * r + c];
                 }
             }
         }
@@ -587,14 +611,8 @@ hipError_t var_decode(const Matrix& m, float* out, hipStream_t st)
     const uint64_t* index = static_cast<const uint64_t*>(m.dptr);
     const uint32_t* code = reinterpret_cast<const uint32_t*>(static_cast<const char*>(m.dptr) + ib);
     const uint64_t nwords = (m.nbytes - ib) / 4;
-    if (nlanes >= kVarLargeFrom)
-        hipLaunchKernelGGL(var_decode_kernel<kVarThreadsLarge>, dim3(grid_of(nlanes, kVarThreadsLarge)),
-                           dim3(kVarThreadsLarge), 0, st, index, code, nwords, mode, param, m.desc.rows, m.desc.cols,
-                           nbc, ng, nlanes, out);
-    else
-        hipLaunchKernelGGL(var_decode_kernel<kVarThreadsSmall>, dim3(grid_of(nlanes, kVarThreadsSmall)),
-                           dim3(kVarThreadsSmall), 0, st, index, code, nwords, mode, param, m.desc.rows, m.desc.cols,
-                           nbc, ng, nlanes, out);
+    hipLaunchKernelGGL(var_decode_kernel, dim3(grid_of(nlanes, kVarThreadsSmall)), dim3(kVarThreadsSmall), 0, st,
+                       index, code, nwords, mode, param, m.desc.rows, m.desc.cols, nbc, ng, nlanes, out);
     return hipGetLastError();
 }
 
