@@ -124,10 +124,11 @@ const char *wh_status_str(wh_status st);
  * (column slabs), read here, fix the compressed GEMV's launch shape instead
  * of the planner's choice, and WH_MRHS_SLABS the multi-RHS kernel's column
  * slabs (for launch-shape sweeps); invalid values are ignored.  Results stay within the stated tolerances for every shape.
- * WH_MRHS_FP32=1 keeps FP32 right-hand sides on the FP32 matrix cores for
- * every k (by default, from 17 right-hand sides up, the FP32 operands are
- * each split into three BF16 parts and their six significant products run
- * on the BF16 matrix cores; the result stays within the FP32 tolerance).
+ * WH_MRHS_FP32=1 keeps FP32 right-hand sides on the 16x16x4 FP32 matrix-core
+ * instruction for every k (by default up to 4 right-hand sides run on the
+ * 4x4x1 one, and from 17 up the FP32 operands are each split into three
+ * BF16 parts and their six significant products run on the BF16 matrix
+ * cores; the result stays within the FP32 tolerance either way).
  * WH_SERVE_PACE (a number from 1 to 16, default 4) paces a served matrix
  * whose requests can no longer meet their deadlines: while other work waits,
  * it gets one launch per that many of its launch times.
@@ -234,9 +235,10 @@ wh_status wh_gemv_plan_info(uint32_t rows, uint32_t cols, uint32_t row_begin, ui
  * 1 <= k <= 64.  zfp format only; WH_PAPER_MP only with k = 1.  The matrix
  * cores contract the scaled coefficients against B^T U (as wh_gemv), FP64
  * across columns.  FP32 U: on the FP32 matrix cores up to 16 right-hand
- * sides; from 17 up each FP32 operand is split into three BF16 parts and the
- * six significant part products run on the BF16 matrix cores (within the
- * FP32 tolerance; WH_MRHS_FP32=1 at wh_create keeps the FP32 cores).  BF16 U:
+ * sides (4x4x1 MFMAs up to 4, 16x16x4 above); from 17 up each FP32 operand
+ * is split into three BF16 parts and the six significant part products run
+ * on the BF16 matrix cores (within the FP32 tolerance; WH_MRHS_FP32=1 at
+ * wh_create keeps the 16x16x4 FP32 cores).  BF16 U:
  * both operands rounded to BF16. */
 #define WH_U_F32 0
 #define WH_U_BF16 1

@@ -56,7 +56,7 @@ struct GemvTuning {
     uint32_t rows = 0;  // block rows per group and tile: 1 .. kGemvMaxRowsPerGroup
     uint32_t slabs = 0; // column slabs (at most one per group width of block columns)
     uint32_t mrhs_slabs = 0; // column slabs of the multi-RHS kernel
-    uint32_t mrhs_fp32 = 0;  // 1: FP32 U always on the FP32 MFMA (no three-part split)
+    uint32_t mrhs_fp32 = 0;  // 1: FP32 U always on the 16x16x4 FP32 MFMA (no three-part split, no 4x4x1)
 };
 
 // Launch geometry of the multi-RHS kernel: tiles of 4 block-rows per wave x
@@ -67,10 +67,18 @@ typedef GemvPlan MrhsPlan;
 // significant products go to the BF16 MFMA (X6: from 17 right-hand sides up,
 // where the FP32 MFMA's time, which does not overlap the decoder's VALU work,
 // exceeds the split's VALU cost).
-enum class MrhsMath : uint32_t { F32 = 0, Bf16 = 1, X6 = 2 };
+// F32: v_mfma_f32_16x16x4f32 over groups of 16 right-hand sides; F32N: up
+// to kMrhsNarrowMax right-hand sides on v_mfma_f32_4x4x1f32 (16 blocks);
+// Bf16: BF16 U; X6: FP32 U as three BF16 parts.
+enum class MrhsMath : uint32_t { F32 = 0, Bf16 = 1, X6 = 2, F32N = 3 };
+constexpr uint32_t kMrhsNarrowMax = 4;
 inline MrhsMath mrhs_math(uint32_t k, bool bf16, bool force_fp32)
 {
-    return bf16 ? MrhsMath::Bf16 : (k > 16 && !force_fp32 ? MrhsMath::X6 : MrhsMath::F32);
+    if (bf16)
+        return MrhsMath::Bf16;
+    if (force_fp32)
+        return MrhsMath::F32;
+    return k > 16 ? MrhsMath::X6 : (k <= kMrhsNarrowMax ? MrhsMath::F32N : MrhsMath::F32);
 }
 // Waves per workgroup for NT groups of 16 right-hand sides.
 constexpr int mrhs_waves(int nt, MrhsMath m) { return m == MrhsMath::X6 ? 8 : (nt == 1 ? 12 : 8); }

@@ -470,6 +470,10 @@ __global__ void __launch_bounds__(kGemvThreads<NW>) gemv_kernel(const uint32_t* 
 //            v_mfma_f32_16x16x4f32, K = the quarter's 4 block columns, one
 //            MFMA per coefficient column: 4 MFMAs per quarter and 16
 //            right-hand sides
+//   FP32 U,  up to 4 right-hand sides: the same halves on
+//   k <= 4   v_mfma_f32_4x4x1f32 (16 blocks of 4 x 4, K = 1; below,
+//            mrhs_load_bn): 8 MFMAs per half, a quarter of the 16x16x4
+//            cycles, which at k <= 4 would contract zero columns
 //   BF16 U   two halves of 8 block columns, written rounded to BF16 and
 //            contracted with v_mfma_f32_16x16x32_bf16 (K = 32), 1 MFMA per
 //            half and 16 right-hand sides
@@ -496,7 +500,8 @@ static_assert(4 * mrhs_waves(1, MrhsMath::F32) <= (int)kMrhsMaxTileBlockRows &&
                   4 * mrhs_waves(4, MrhsMath::F32) <= (int)kMrhsMaxTileBlockRows &&
                   4 * mrhs_waves(2, MrhsMath::X6) <= (int)kMrhsMaxTileBlockRows,
               "block rows per multi-RHS workgroup");
-constexpr int kMathF32 = (int)MrhsMath::F32, kMathBf16 = (int)MrhsMath::Bf16, kMathX6 = (int)MrhsMath::X6;
+constexpr int kMathF32 = (int)MrhsMath::F32, kMathBf16 = (int)MrhsMath::Bf16, kMathX6 = (int)MrhsMath::X6,
+              kMathF32N = (int)MrhsMath::F32N;
 constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's BF16 half tile (40 BF16)
 constexpr int kATile32Stride = 32;    // floats per LDS row of a wave's FP32 half tile (swizzled)
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
@@ -649,6 +654,25 @@ __device__ __forceinline__ void mrhs_load_bq(const float* __restrict__ btf, uint
 template <int NT>
 constexpr int kMrhsAhead = NT == 1 ? 3 : (NT == 2 ? 2 : 1);
 
+// FP32 U, up to 4 right-hand sides on v_mfma_f32_4x4x1f32 (16 blocks of
+// 4 x 4, K = 1), where the 16x16x4 MFMA would spend three quarters of its
+// cycles on zero columns.  MFMA block b = 4 t + s of lane l (t = l / 16,
+// s = l / 4 % 4) sums block row t over its share s of the block columns:
+// of each half of a step, block columns 2 s and 2 s + 1, one per "quarter"
+// q, one MFMA per coefficient column m; j = l % 4 is the right-hand side.
+// The B operands of quarter qi = 2 h + q of a step for this lane: B^T U's
+// four values m = 0..3 for right-hand side j at block column
+// cb + 8 h + 2 s + q, from the FP32 layout of one group of 16.
+__device__ __forceinline__ void mrhs_load_bn(const float* __restrict__ btf, uint32_t cb, int qi, int lane, f32x4& b)
+{
+    const uint32_t sh = ((uint32_t)lane >> 2) & 3u, j = (uint32_t)lane & 3u;
+    const uint32_t bc = cb + 8u * (uint32_t)(qi >> 1) + 2u * sh + (uint32_t)(qi & 1);
+    b = *reinterpret_cast<const f32x4*>(btf + ((uint64_t)bc * 16 + j) * 4);
+}
+constexpr int kMrhsNarrowAhead = 3;
+static_assert(kMrhsNarrowMax <= 4, "the 4x4x1 path holds one group of 4 right-hand sides");
+static_assert(16 * kATile32Stride >= 4 * 8 * 16, "a half's 32 blocks fit the FP32 tile");
+
 // X6: the B operand words (three parts, 16 bytes each) of one half and one
 // group of 16 right-hand sides for this lane.
 template <int NT>
@@ -675,14 +699,18 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
                 uint32_t ldy, double* __restrict__ part, uint32_t nbc, uint32_t bi_begin, uint32_t bi_end,
                 uint32_t slab_bc, uint32_t nslab, uint32_t nrows_out)
 {
-    constexpr bool BF16U = MATH == kMathBf16, X6 = MATH == kMathX6;
+    constexpr bool BF16U = MATH == kMathBf16, X6 = MATH == kMathX6, NARROW = MATH == kMathF32N;
     constexpr int W = mrhs_waves(NT, (MrhsMath)MATH), T = 64 * W;
+    // accumulator tiles per lane: one per group of 16 right-hand sides, or
+    // one for the 4x4x1 path (its groups of 4 lie in different lanes)
+    constexpr int NA = NARROW ? 1 : NT;
     __shared__ uint32_t lds[T * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
     // the wave's A tile: FP32 halves (16 x 32, swizzled), BF16 halves, or
     // three BF16 halves (one per part) for X6
     __shared__ __align__(16) float atile[W][X6 ? 3 * 16 * kATileStride
-                                              : (MATH == kMathF32 ? 16 * kATile32Stride : 16 * kATileStride)];
+                                              : (MATH == kMathF32 || MATH == kMathF32N ? 16 * kATile32Stride
+                                                                                         : 16 * kATileStride)];
     uint32_t* row = lds + threadIdx.x;
     clear_pad<NW, T>(row);
     load_section_table<T>(tab); // the last workgroup barrier
@@ -709,10 +737,10 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
                 w[q] = 0u; // decodes as a zero block
     }
 
-    mf32x4 acc[NT];
-    double sum[NT][4];
+    mf32x4 acc[NA];
+    double sum[NA][4];
 #pragma unroll
-    for (int n = 0; n < NT; ++n)
+    for (int n = 0; n < NA; ++n)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             sum[n][j] = 0.0;
@@ -735,8 +763,8 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
         }
         // ---- B operands in flight during the decode (block columns cb ..
         // cb + 15 lie inside the workspace: it spans whole steps)
-        constexpr int AH = kMrhsAhead<NT>;
-        f32x4 bq[MATH == kMathF32 ? AH : 1][NT];
+        constexpr int AH = NARROW ? kMrhsNarrowAhead : kMrhsAhead<NT>;
+        f32x4 bq[MATH == kMathF32 || NARROW ? AH : 1][NARROW ? 1 : NT];
         u32x4 bh[BF16U ? 2 : 1][NT];
         // X6: the B parts of the (half, group) in use and the kX6Ahead after it
         u32x4 bx[X6 ? kX6Ahead + 1 : 1][3];
@@ -752,6 +780,10 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
                 for (int n = 0; n < NT; ++n)
                     bh[h][n] = *reinterpret_cast<const u32x4*>(
                         btb + (((uint64_t)(cb / 2 + 4 * h + g) * NT + n) * 16 + j) * 8);
+        } else if constexpr (NARROW) {
+#pragma unroll
+            for (int q = 0; q < AH; ++q)
+                mrhs_load_bn(btf, cb, q, lane, bq[q][0]);
         } else {
 #pragma unroll
             for (int q = 0; q < AH; ++q)
@@ -769,9 +801,41 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
         if (__any(cut) && cut) // rare: the exact lift (see exact_block_coeffs)
             exact_block_coeffs(cf, emax, sc);
 #pragma unroll
-        for (int n = 0; n < NT; ++n)
+        for (int n = 0; n < NA; ++n)
             acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
-        if constexpr (MATH == kMathF32) {
+        if constexpr (NARROW) {
+            // ---- two halves of 8 block columns (the MFMA blocks and shares
+            // of mrhs_load_bn): the half's lanes write their blocks to the
+            // wave's tile as [t][q][s][r][m], row r's place XORed with 2 q so
+            // that the 8 writes of a block row fall on distinct banks; lane
+            // (t, s, r) then reads row r of its share's block column q and
+            // runs its 4 MFMAs (A: lane r + 4 b holds A_b[r]; B: lane j + 4 b
+            // holds B_b[j]; D_b[r][j]: lane j + 4 b, register r)
+            const int tn = lane >> 4, sn = (lane >> 2) & 3, rn = lane & 3;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                wave_sync_lds();
+                if ((c >> 3) == h) {
+                    const int qw = c & 1;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        *reinterpret_cast<f32x4*>(at + ((t * 2 + qw) * 4 + ((c & 7) >> 1)) * 16 + (r ^ (2 * qw)) * 4) =
+                            f32x4{sc[4 * r], sc[4 * r + 1], sc[4 * r + 2], sc[4 * r + 3]};
+                }
+                wave_sync_lds();
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int qi = 2 * h + q, slot = qi % AH;
+                    const f32x4 a4 =
+                        *reinterpret_cast<const f32x4*>(at + ((tn * 2 + q) * 4 + sn) * 16 + (rn ^ (2 * q)) * 4);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a4[m], bq[slot][0][m], acc[0], 0, 0, 0);
+                    if (qi + AH < 4) // the quarter AH on into the slot just used
+                        mrhs_load_bn(btf, cb, qi + AH, lane, bq[slot][0]);
+                }
+            }
+        } else if constexpr (MATH == kMathF32) {
             // ---- two halves of 8 block columns: the half's lanes write their
             // blocks to the wave's 16 x 32 tile (row 4t + r, a 4-float group
             // per block column, the group index XORed with the row's low
@@ -901,17 +965,29 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
             }
         }
 #pragma unroll
-        for (int n = 0; n < NT; ++n)
+        for (int n = 0; n < NA; ++n)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 sum[n][j] += (double)acc[n][j];
     }
 
+    // ---- 4x4x1 sums: lane (t, s, j) holds block row t's sums over its
+    // share s of the block columns for right-hand side j; the four shares
+    // are added (the same order in every lane).  lane % 16 = j + 4 s: the
+    // share-0 lanes hold their right-hand sides as in the 16x16 layout, the
+    // others land on right-hand sides >= 4 >= k
+    if constexpr (NARROW) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sum[0][j] += __shfl_xor(sum[0][j], 4, 64);
+            sum[0][j] += __shfl_xor(sum[0][j], 8, 64);
+        }
+    }
     // ---- B on each block row's four coefficient-row sums; D[i][j]: lane
     // holds rows 4*(lane/16) + j, right-hand side lane%16
     const uint32_t nrows = (bi_end - bi_begin) * 4;
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
+    for (int n = 0; n < NA; ++n) {
         lin_inv_lift<double>(sum[n][0], sum[n][1], sum[n][2], sum[n][3]);
         const uint32_t rhs = 16 * n + (lane & 15);
         if (rhs >= k)
@@ -1081,7 +1157,11 @@ hipError_t launch_mrhs(const MrhsPlan& pl, const uint32_t* s, const void* U, uin
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    switch (nt * 3 + (int)math) {
+    if (math == MrhsMath::F32N) {
+        if (k > kMrhsNarrowMax)
+            return hipErrorInvalidValue; // the planner gives the 4x4x1 path only up to kMrhsNarrowMax
+        e = launch_mrhs_t<NW, kMathF32N, 1>(pl, s, btu, k, Y, ldy, part, st);
+    } else switch (nt * 3 + (int)math) {
     case 3: e = launch_mrhs_t<NW, kMathF32, 1>(pl, s, btu, k, Y, ldy, part, st); break;
     case 4: e = launch_mrhs_t<NW, kMathBf16, 1>(pl, s, btu, k, Y, ldy, part, st); break;
     case 6: e = launch_mrhs_t<NW, kMathF32, 2>(pl, s, btu, k, Y, ldy, part, st); break;

@@ -2,10 +2,11 @@
 
 Reference: the oracle-decoded matrix in FP64 times the k vectors (a plain
 FP64 matrix product of the oracle's decode).  Bounds: FP32 vectors, relative
-L2 1e-6 per right-hand side, whether they run on the FP32 matrix cores (up
-to 16 right-hand sides, or always with WH_MRHS_FP32=1) or split into three
-BF16 parts on the BF16 matrix cores (from 17 up); BF16 vectors (the decoded
-values rounded to BF16 for the contraction), 2e-3.
+L2 1e-6 per right-hand side, whether they run on the FP32 matrix cores
+(4x4x1 MFMAs up to 4 right-hand sides, 16x16x4 up to 16, or 16x16x4 always
+with WH_MRHS_FP32=1) or split into three BF16 parts on the BF16 matrix cores
+(from 17 up); BF16 vectors (the decoded values rounded to BF16 for the
+contraction), 2e-3.
 """
 import os
 
@@ -32,7 +33,7 @@ def small_mrhs():
     return s, Mhat
 
 
-@pytest.mark.parametrize("k", [1, 2, 4, 16, 17, 33, 64])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 9, 16, 17, 33, 64])
 def test_mrhs_fp32(gpu_ctx, small_mrhs, k):
     s, Mhat = small_mrhs
     U = synth.u_batch(synth.SMALL, k)
@@ -67,7 +68,7 @@ def test_mrhs_bf16(gpu_ctx, small_mrhs, k):
 
 @pytest.mark.parametrize("shape", [(4, 4), (68, 260), (260, 68), (1028, 1092)])
 @pytest.mark.parametrize("rate", [8, 16])
-@pytest.mark.parametrize("k", [5, 40])
+@pytest.mark.parametrize("k", [3, 5, 40])
 def test_mrhs_ragged(gpu_ctx, shape, rate, k):
     rows, cols = shape
     spec = synth.MatrixSpec(rows, cols, 32, 8.0, seed=13)
@@ -140,12 +141,12 @@ def test_mrhs_low_rates_wide_range(gpu_ctx, rate, k):
     wh.wh_unload(gpu_ctx, mat)
 
 
-@pytest.mark.parametrize("k", [17, 33, 64])
+@pytest.mark.parametrize("k", [3, 4, 17, 33, 64])
 def test_mrhs_split_bf16_against_fp32_cores(small_mrhs, k):
-    """From 17 right-hand sides up FP32 vectors run as three BF16 parts on
-    the BF16 matrix cores; a context made with WH_MRHS_FP32=1 keeps them on
-    the FP32 cores.  Both are within 1e-6 of the oracle, and within 1e-6 of
-    each other."""
+    """Up to 4 right-hand sides FP32 vectors run on the 4x4x1 FP32 MFMA, from
+    17 up as three BF16 parts on the BF16 matrix cores; a context made with
+    WH_MRHS_FP32=1 keeps them on the 16x16x4 FP32 MFMA.  Both are within 1e-6
+    of the oracle, and within 1e-6 of each other."""
     s, Mhat = small_mrhs
     U = synth.u_batch(synth.SMALL, k)
     ref = U.astype(np.float64) @ Mhat.T
@@ -167,6 +168,6 @@ def test_mrhs_split_bf16_against_fp32_cores(small_mrhs, k):
         out[force] = Y.cpu().numpy()
         wh.wh_destroy(ctx)
         err = per_rhs_rel_l2(out[force], ref)
-        print(f"k={k} {'FP32 cores' if force else 'BF16 parts'}: worst per-RHS rel-L2 {err.max():.3e}")
+        print(f"k={k} {'16x16x4 FP32' if force else 'default path'}: worst per-RHS rel-L2 {err.max():.3e}")
         assert err.max() <= 1e-6
     assert per_rhs_rel_l2(out[0], out[1].astype(np.float64)).max() <= 1e-6
