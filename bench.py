@@ -46,8 +46,10 @@ def parse():
     ap.add_argument("--serving", type=int, default=1, help="also run the Poisson serving load")
     ap.add_argument("--serving-requests", type=int, default=20000)
     ap.add_argument("--leg", default="", help="'host-pipeline' (internal), 'serving' (the three-matrix load of "
-                                              "--serving-requests requests) or 'thermal' (the thermal step) runs "
+                                              "--serving-requests requests), 'thermal' (the thermal step) or "
+                                              "'var' (the variable-rate modes on a --var-size square matrix) runs "
                                               "only that leg and prints its JSON")
+    ap.add_argument("--var-size", type=int, default=8192, help="matrix side of --leg var")
     ap.add_argument("--probe", type=int, default=0,
                     help="counter-pass mode, prints no JSON: 1 = 3 launches of the timed configuration, then 3 "
                          "plain 4 GiB device copies (the calibration kernel for FETCH_SIZE / WRITE_SIZE) and 3 "
@@ -446,7 +448,7 @@ VAR_SPEC_ARGS = (8192, 8192, 128, 16.0)
 
 def bench_var(ctx, steps):
     """The variable-rate modes (Sec. 4.3, Table 2) on an 8192 x 8192 synthetic
-    matrix, beside fixed rate 8: bits per value (index included), the
+    matrix (VAR_SPEC_ARGS), beside fixed rate 8: bits per value (index included), the
     Table 2 error columns (NRMSE over the source's range, PSNR =
     -20 log10(2 NRMSE)), the host encoder's time, the GPU decode rate in the
     paper's W_c convention (uncompressed bytes per second) and the fused
@@ -770,6 +772,12 @@ def main():
     ctx = wh.wh_create(0, 0)
     if args.leg == "thermal":
         print(json.dumps(bench_thermal(ctx, args.steps)), flush=True)
+        wh.wh_destroy(ctx)
+        return
+    if args.leg == "var":
+        global VAR_SPEC_ARGS
+        VAR_SPEC_ARGS = (args.var_size, args.var_size) + tuple(VAR_SPEC_ARGS[2:])
+        print(json.dumps(bench_var(ctx, args.steps)), flush=True)
         wh.wh_destroy(ctx)
         return
     if args.leg == "host-pipeline":
