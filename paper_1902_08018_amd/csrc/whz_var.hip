@@ -15,10 +15,10 @@
 //
 // Decoding: one lane per group of 32 blocks, the blocks in sequence; the
 // lanes of a wave run the bit planes in lockstep (as the fixed-rate decoder),
-// each with its own lowest plane.  Before each block a lane copies the next
-// 20 words of its code into its own LDS row (word-major, as the fixed-rate
-// staging), so the decoder's window reads are LDS reads, not chains of
-// dependent global loads.  The fused GEMV gives 1 to 8 lanes (groups) to a block row
+// each with its own lowest plane.  Before each block a lane brings the next
+// words of its code into its own LDS ring (word-major, as the fixed-rate
+// staging; only the 16-byte pieces not already there), so the decoder's
+// window reads are LDS reads, not chains of dependent global loads.  The fused GEMV gives 1 to 8 lanes (groups) to a block row
 // and multiplies each block's exactly decoded values by u.  The encoder runs
 // on the host (the paper encodes offline, Sec. 4.3).
 #include <hip/hip_runtime.h>
@@ -69,16 +69,19 @@ __device__ __forceinline__ uint32_t vwindow(const uint32_t* __restrict__ g, uint
     return funnel(vword(g, lim, q + 1), vword(g, lim, q), pos & 31u);
 }
 
-// Words of code staged in LDS per block, and the zero words after them.  A
-// block of P planes takes at most 25 + 17 P bits: the 9-bit header, at most
-// 16 verbatim bits a plane after the first, one ending group bit a plane,
-// and across all planes at most 16 run-starting group bits and 16 run bits
-// (a run passes each coefficient once).  With P <= 32, the start offset
-// (< 32) and the last 32-bit window, every read stays below bit 632 of the
-// block's first word: 20 words hold any block.  The staged run starts at the
-// 16-byte boundary at or before that word (up to 3 words earlier), so that it
-// is six 16-byte loads: 24 words.
-constexpr uint32_t kVarStage = 24, kVarPad = 3, kVarRow = kVarStage + kVarPad;
+// A lane's code in LDS: a ring of kVarRing words, refilled 16 bytes at a
+// time, so that each piece of the code is loaded from global memory once.
+// A block of P planes takes at most 25 + 17 P bits: the 9-bit header, at
+// most 16 verbatim bits a plane after the first, one ending group bit a
+// plane, and across all planes at most 16 run-starting group bits and 16 run
+// bits (a run passes each coefficient once).  With P <= 32, the start
+// offset (< 32) and the last 32-bit window, every read stays below bit 632
+// of the block's first word: 20 words hold any block.  Before a block the
+// ring is filled through 24 words from the 16-byte boundary at or before
+// that word (up to 3 words earlier): 6 pieces, of which the blocks before
+// have already loaded all but the new ones.  One word after the ring
+// mirrors its first, so that a window's two words are always adjacent.
+constexpr uint32_t kVarRing = 24, kVarRow = kVarRing + 1;
 
 // Reading a lane's code straight from global memory: two loads a window.
 struct GlobalBits {
@@ -87,17 +90,19 @@ struct GlobalBits {
     __device__ __forceinline__ uint32_t window(uint32_t pos) const { return vwindow(g, lim, pos); }
 };
 
-// Reading a lane's block staged in LDS: kVarStage words of its view from
-// word b0 at lw[k * T], then kVarPad zero words; positions count
-// from bit 32 * b0.  A window past the staged words reads the zero
-// padding (the word index is clamped to it), so a block that runs past
-// 32 * (kVarStage - 1) bits must be decoded again from global memory.
+// Reading a block from a lane's ring at lw[k * T]: positions count from bit 0
+// of the block's first 16-byte piece, which sits at word sb of the ring.  A
+// window at or past word kVarRing - 1 reads the last word's slot (the word
+// index is clamped), so a block that runs past 32 * (kVarRing - 1) bits
+// must be decoded again from global memory.
 template <int T>
 struct StagedBits {
     const uint32_t* lw;
+    uint32_t sb;
     __device__ __forceinline__ uint32_t window(uint32_t pos) const
     {
-        const uint32_t q = __builtin_elementwise_min(pos >> 5, kVarStage + 1u);
+        uint32_t q = __builtin_elementwise_min(pos >> 5, kVarRing - 1u) + sb;
+        q = __builtin_elementwise_min(q, q - kVarRing); // the ring's slot
         return funnel(lw[(q + 1) * T], lw[q * T], pos & 31u);
     }
 };
@@ -199,61 +204,82 @@ __device__ __forceinline__ void lane_view(const uint32_t* code, uint64_t nwords,
     pos = (uint32_t)(start & 31u);
 }
 
-// The next block of a lane's view at bit pos (advanced past it): staged in
-// the lane's LDS row and decoded there.  A block that read past the staged
-// words would be decoded again from global memory; by the bound above that
-// never happens for codes of at most 32 planes, and the check keeps a code
-// that breaks the bound (a corrupt stream) from decoding out of padding.
+// A lane's ring: `head` is the view word (counted from the 16-byte boundary
+// at or before the view's first word) up to which it is filled, a multiple
+// of 4; `hs` the ring piece (0..5) that word goes to.  Both start at 0.
+struct VarRing {
+    uint32_t head = 0u, hs = 0u;
+};
+
+// The next block of a lane's view at bit pos (advanced past it): the ring is
+// refilled through 24 words from the block's 16-byte piece and the block
+// decoded there.  A piece inside the view is one 16-byte load, a piece
+// reaching before the view's first word or past its end is read word by word
+// (zero outside).  A block that read past the ring would be decoded again
+// from global memory; by the bound above that never happens for codes of at
+// most 32 planes, and the check keeps a code that breaks the bound (a
+// corrupt stream) from decoding out of stale ring words.
 template <int T>
 __device__ __forceinline__ bool var_next_block(const uint32_t* g, uint32_t lim, uint32_t* row, const uint32_t* tab,
                                                int mode, int param, bool live, uint32_t& pos, int& emax,
-                                               uint32_t (&cf)[16])
+                                               uint32_t (&cf)[16], VarRing& ring)
 {
-    // the run of words staged: from the 16-byte boundary at or before the
-    // block's first word; a 16-byte piece inside the view is one load, a
-    // piece reaching before the view's first word or past its end is read
-    // word by word (zero outside)
-    const uint32_t m = (uint32_t)(reinterpret_cast<uintptr_t>(g + (pos >> 5)) >> 2) & 3u;
-    const int64_t b0 = (int64_t)(pos >> 5) - (int64_t)m; // may be before the view
+    constexpr uint32_t kPieces = kVarRing / 4;
+    const uint32_t a = (uint32_t)(reinterpret_cast<uintptr_t>(g) >> 2) & 3u; // g's word within its 16 bytes
+    const uint32_t b = ((pos >> 5) + a) & ~3u; // the block's first piece, in words from g - a
+    const uint32_t h0 = __builtin_elementwise_max(ring.head, b);
+    const uint32_t n = live ? (b + kVarRing - h0) >> 2 : 0u; // pieces to load
+    u32x4 v[kPieces];
 #pragma unroll
-    for (uint32_t k = 0; k < kVarStage / 4; ++k) {
-        const int64_t s = b0 + 4 * (int64_t)k;
-        u32x4 v = u32x4{0u, 0u, 0u, 0u};
-        if (live) {
-            if (s >= 0 && s + 4 <= (int64_t)lim) {
-                v = *reinterpret_cast<const u32x4*>(g + s);
-            } else {
+    for (uint32_t k = 0; k < kPieces; ++k) {
+        v[k] = u32x4{0u, 0u, 0u, 0u};
+        if (__any(k < n)) {
+            if (k < n) {
+                const int64_t s0 = (int64_t)(h0 + 4 * k) - (int64_t)a; // view word of the piece's first word
+                if (s0 >= 0 && s0 + 4 <= (int64_t)lim) {
+                    v[k] = *reinterpret_cast<const u32x4*>(g + s0);
+                } else {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    v[i] = (s + i >= 0 && s + i < (int64_t)lim) ? g[s + i] : 0u;
+                    for (int i = 0; i < 4; ++i)
+                        v[k][i] = (s0 + i >= 0 && s0 + i < (int64_t)lim) ? g[s0 + i] : 0u;
+                }
             }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            row[(4 * k + i) * T] = v[i];
     }
-    uint32_t lpos = 32u * m + (pos & 31u);
-    bool nz = var_block_coeffs(StagedBits<T>{row}, tab, mode, param, live, lpos, emax, cf);
-    const bool over = live && lpos >= 32u * (kVarStage - 1u);
+    // the pieces into their ring slots, piece h0 / 4 + k at slot c0 + k
+    // (mod 6): on from the head's slot, or from slot 0 when the block starts
+    // past the ring's end (all 6 pieces are new then)
+    const uint32_t c0 = h0 > ring.head ? 0u : ring.hs;
+#pragma unroll
+    for (uint32_t k = 0; k < kPieces; ++k) {
+        if (k < n) {
+            uint32_t c = c0 + k;
+            c = __builtin_elementwise_min(c, c - kPieces);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                row[(4 * c + i) * T] = v[k][i];
+            if (c == 0)
+                row[kVarRing * T] = v[k][0]; // the mirror word
+        }
+    }
+    if (live) {
+        const uint32_t hs = c0 + n;
+        ring.hs = __builtin_elementwise_min(hs, hs - kPieces);
+        ring.head = b + kVarRing;
+    }
+    // the block's piece b sits where the ring's head is now (24 words on)
+    uint32_t lpos = pos + 32u * a - 32u * b;
+    bool nz = var_block_coeffs(StagedBits<T>{row, 4u * ring.hs}, tab, mode, param, live, lpos, emax, cf);
+    const bool over = live && lpos >= 32u * (kVarRing - 1u);
     if (__any(over)) {
         if (over) {
             uint32_t p = pos;
             nz = var_block_coeffs(GlobalBits{g, lim}, tab, mode, param, true, p, emax, cf);
-            lpos = (uint32_t)((int64_t)p - 32 * b0);
+            lpos = p + 32u * a - 32u * b;
         }
     }
-    pos = (uint32_t)(32 * b0 + (int64_t)lpos);
+    pos = lpos + 32u * b - 32u * a;
     return nz;
-}
-
-// Zero the padding words after a lane's staged block (once per kernel: the
-// staging writes words 0..kVarStage-1 only).
-template <int T>
-__device__ __forceinline__ void clear_var_pad(uint32_t* row)
-{
-#pragma unroll
-    for (uint32_t k = kVarStage; k < kVarRow; ++k)
-        row[k * T] = 0u;
 }
 
 // Whole matrix into row-major FP32: one lane per (block row, group), in
@@ -275,7 +301,6 @@ __global__ void __launch_bounds__(kVarThreadsSmall) var_decode_kernel(
     __shared__ uint32_t tab[kSecEntries];
     __shared__ uint32_t stage[T * kVarRow];
     uint32_t* row = stage + threadIdx.x;
-    clear_var_pad<T>(row);
     load_table<T>(tab);
     const uint64_t lane_id = (uint64_t)blockIdx.x * T + threadIdx.x;
     const bool in = lane_id < nlanes;
@@ -283,6 +308,7 @@ __global__ void __launch_bounds__(kVarThreadsSmall) var_decode_kernel(
     const uint32_t* g;
     uint32_t lim, pos;
     lane_view(code, nwords, in ? index[lane_id] : 0ull, g, lim, pos);
+    VarRing ring;
     // rows of whole blocks: every span of whole blocks starts 16-byte aligned
     const bool whole = (cols & 3u) == 0u;
     for (uint32_t j0 = 0; j0 < 32u; j0 += kVarSpan) {
@@ -292,7 +318,7 @@ __global__ void __launch_bounds__(kVarThreadsSmall) var_decode_kernel(
             const uint32_t bj = a * 32u + j0 + s;
             int emax;
             uint32_t iv[16];
-            var_next_block<T>(g, lim, row, tab, mode, param, in && bj < nbc, pos, emax, iv);
+            var_next_block<T>(g, lim, row, tab, mode, param, in && bj < nbc, pos, emax, iv, ring);
             inv_xform(iv);
 #pragma unroll
             for (int i = 0; i < 16; ++i)
@@ -378,7 +404,6 @@ __global__ void __launch_bounds__(T) var_gemv_kernel(
     static_assert(kVarRow * T / 2 >= 4 * T, "the row sums fit the staging area");
     uint32_t* row = reinterpret_cast<uint32_t*>(stage_d) + threadIdx.x;
     double* red = stage_d;
-    clear_var_pad<T>(row);
     load_table<T>(tab);
     const uint32_t G = 1u << lg, groups = (uint32_t)T >> lg;
     const uint32_t grp = threadIdx.x >> lg, gl = threadIdx.x & (G - 1);
@@ -389,6 +414,7 @@ __global__ void __launch_bounds__(T) var_gemv_kernel(
     const uint32_t* g;
     uint32_t lim, pos;
     lane_view(code, nwords, in ? index[(uint64_t)bi * ngroups + a] : 0ull, g, lim, pos);
+    VarRing ring;
     Acc acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -404,7 +430,7 @@ __global__ void __launch_bounds__(T) var_gemv_kernel(
         }
         int emax;
         uint32_t iv[16];
-        const bool nz = var_next_block<T>(g, lim, row, tab, mode, param, live, pos, emax, iv);
+        const bool nz = var_next_block<T>(g, lim, row, tab, mode, param, live, pos, emax, iv, ring);
         if (live && nz) {
             // the exact integer inverse transform (not B (C (B^T u))): a
             // coefficient cut to its top planes can reach -2^31, where the
