@@ -305,8 +305,12 @@ __device__ __forceinline__ void exact_block_coeffs(const uint32_t (&cf)[16], int
 // 512 lanes; narrow ones (few block columns) use small groups, so that every
 // lane has blocks to decode.  Output row i of the range is matrix row
 // 4 * bi_begin + skip + i.
+// two workgroups per CU: 1024-lane ones in 64 VGPRs (32 waves)
+template <int NW>
+constexpr int kGemvMinWaves = kGemvThreads<NW> == 1024 ? 8 : 6;
+
 template <int NW, typename Acc>
-__global__ void __launch_bounds__(kGemvThreads<NW>) gemv_kernel(const uint32_t* __restrict__ stream,
+__global__ void __launch_bounds__(kGemvThreads<NW>, kGemvMinWaves<NW>) gemv_kernel(const uint32_t* __restrict__ stream,
                                                         const float* __restrict__ u, float* __restrict__ y,
                                                         double* __restrict__ part, uint32_t nbc, uint32_t bi_begin,
                                                         uint32_t bi_end, uint32_t slab_bc, uint32_t nslab,
