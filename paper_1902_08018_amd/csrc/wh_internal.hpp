@@ -12,17 +12,21 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // Accumulation of the cross-block row sums.
 enum class AccMode { Fp64, TwoSum, PaperMp };
 
-// Workgroup size of the fused GEMV: 1024 lanes up to 12 bits/value, 768
+// Workgroup size of the fused GEMV: 1024 lanes up to 16 bits/value, 768
 // above.  Two workgroups share a CU: 32 waves at 1024 lanes, in 64 VGPRs
 // each (the launch bounds ask for that), or 24 at 768 lanes, where a lane
-// stages 10 or more words of LDS and two 1024-lane workgroups would not fit.
+// stages 13 or more words of LDS and two 1024-lane workgroups would not fit.
 // The most lanes a group spans (512; 256 for 768, the largest power of two
 // dividing it); the most block rows one lane group takes per tile.  The LDS
 // doubles that hold the groups' row sums (slots x 4 x rows per group: one
 // slot per wave, or per group of fewer than 64 lanes) are as many as the
 // workgroup's lanes.
 constexpr uint32_t kGemvLanes = 512;
-constexpr uint32_t gemv_wg_lanes(uint32_t rate) { return rate <= 12 ? 1024u : 768u; }
+constexpr uint32_t gemv_wg_lanes(uint32_t rate) { return rate <= 16 ? 1024u : 768u; }
+// LDS of one workgroup when two share a CU
+constexpr uint32_t kLdsPerWorkgroupOfTwo = 160u * 1024u / 2u;
+// from 14 bits/value the row sums share the staging rows: one tile row
+constexpr bool gemv_one_tile_row(uint32_t rate) { return rate >= 14 && rate <= 16; }
 constexpr uint32_t gemv_max_lg(uint32_t lanes) { return lanes == 768u ? 8u : 9u; }
 constexpr int kGemvMaxRowsPerGroup = 4;
 constexpr uint32_t gemv_slots(uint32_t lg, uint32_t lanes) { return lg >= 6 ? lanes / 64 : lanes >> lg; }

@@ -146,7 +146,7 @@ GemvPlan whz_gemv_plan(uint32_t rate, uint32_t rows, uint32_t cols, uint32_t row
         while ((1u << lg) < tune->lanes && lg < max_lg)
             ++lg;
     }
-    if (tune && tune->rows && gemv_slots(lg, lanes) * 4 * tune->rows <= lanes)
+    if (tune && tune->rows && gemv_slots(lg, lanes) * 4 * tune->rows <= lanes && !gemv_one_tile_row(rate))
         rpg = tune->rows;
     pl.lg = lg;
     pl.rpg = rpg;

@@ -308,6 +308,13 @@ __device__ __forceinline__ void exact_block_coeffs(const uint32_t (&cf)[16], int
 // two workgroups per CU: 1024-lane ones in 64 VGPRs (32 waves)
 template <int NW>
 constexpr int kGemvMinWaves = kGemvThreads<NW> == 1024 ? 8 : 6;
+// From 14 bits/value a 1024-lane workgroup's staging rows and section table
+// leave no room for its own row-sum doubles within two workgroups' LDS; the
+// sums then go over the staging rows once every wave has decoded its blocks,
+// which needs one tile row per group (the planner's choice there).
+template <int NW>
+constexpr bool kGemvSumsInStaging =
+    kGemvThreads<NW> * (kStagedWords<NW> * 4 + 8) + kSecEntries * 4 > kLdsPerWorkgroupOfTwo;
 
 template <int NW, typename Acc>
 __global__ void __launch_bounds__(kGemvThreads<NW>, kGemvMinWaves<NW>) gemv_kernel(const uint32_t* __restrict__ stream,
@@ -318,11 +325,15 @@ __global__ void __launch_bounds__(kGemvThreads<NW>, kGemvMinWaves<NW>) gemv_kern
                                                         uint32_t skip)
 {
     constexpr int THREADS = kGemvThreads<NW>;
-    __shared__ uint32_t lds[THREADS * kStagedWords<NW>];
+    constexpr bool kShared = kGemvSumsInStaging<NW>;
+    __shared__ __align__(16) uint32_t lds[THREADS * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
     // a group's four row sums per tile row: one slot per wave when a group
-    // spans whole waves, else one per group
-    __shared__ double red[THREADS];
+    // spans whole waves, else one per group (over the staging rows when they
+    // must share its LDS)
+    __shared__ double red_own[kShared ? 1 : THREADS];
+    static_assert(!kShared || kStagedWords<NW> >= 2, "the row sums fit the staging rows");
+    double* red = kShared ? reinterpret_cast<double*>(lds) : red_own;
     uint32_t* row = lds + threadIdx.x;
     clear_pad<NW, THREADS>(row);
     load_section_table<THREADS>(tab);
@@ -345,14 +356,16 @@ __global__ void __launch_bounds__(kGemvThreads<NW>, kGemvMinWaves<NW>) gemv_kern
 #pragma unroll 1
     for (uint32_t t = 0; t < rpg; ++t) {
         const uint32_t bi = bi0 + t * groups + grp;
-        if (bi >= bi_end) // the same for every lane of the group
+        // the same for every lane of the group; with the sums over the
+        // staging rows (one tile row) every wave goes on to the barrier below
+        if (!kShared && bi >= bi_end)
             break;
         Acc acc[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             acc[r].zero();
         const uint32_t* srow = stream + (uint64_t)bi * nbc * NW;
-        for (uint32_t bj = bc0 + gl; bj < bc1; bj += G) {
+        for (uint32_t bj = bc0 + gl; bi < bi_end && bj < bc1; bj += G) {
             float4 uu;
             if (4 * bj + 3 < cols) {
                 uu = u4[bj];
@@ -404,12 +417,18 @@ __global__ void __launch_bounds__(kGemvThreads<NW>, kGemvMinWaves<NW>) gemv_kern
         }
         // reduce the row's sums across the group's lanes within the wave
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 4; ++r)
             for (int mask = first_mask; mask >= 1; mask >>= 1)
                 acc[r].merge_from_lane(mask);
-            if (leader)
+        if constexpr (kShared)
+            __syncthreads(); // every wave is done with its staging rows
+        if (leader && bi < bi_end) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
                 red[slot * slot_len + 4 * t + r] = acc[r].value();
         }
+        if constexpr (kShared)
+            break; // one tile row (checked at launch)
     }
 
     // then across the waves of a group, one lane per block row (per row of
@@ -1096,6 +1115,8 @@ hipError_t launch_gemv_t(const GemvPlan& pl, const uint32_t* s, const float* u, 
                          hipStream_t st)
 {
     if (pl.lanes != (uint32_t)kGemvThreads<NW>) // a plan made for another rate
+        return hipErrorInvalidValue;
+    if (kGemvSumsInStaging<NW> && pl.rpg != 1) // the row sums over the staging rows hold one tile row
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((gemv_kernel<NW, Acc>), dim3(pl.ntiles * pl.nslab), dim3(kGemvThreads<NW>), 0, st, s, u, y,
                        part, pl.nbc, pl.bi_begin, pl.bi_end, pl.slab_bc, pl.nslab, pl.cols, pl.nrows, pl.lg, pl.rpg,
