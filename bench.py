@@ -28,8 +28,11 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue: 256 CUs x 64 lanes (4 SIMDs x 16 lanes) x 2.4 GHz, in T lane-ops/s
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU: the published FP32 vector rate (157.3 TFLOP/s, an FMA counting two)
+# in lane operations: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, T lane-ops/s.
+# (The kernel's measured issue rate, 628 G wave64 instructions/s, is above the
+# 614 G/s that 16 lanes per SIMD per cycle would allow.)
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 PARITY_ROWS = 256
 
 
@@ -892,9 +895,9 @@ def main():
                      "frac_of_read_ceiling": round(achieved / read_gbs, 4)},
     }
     if valu_insts:
-        # the decoder's own bound: VALU issue, 64 lanes per wave64 instruction
+        # the decoder's VALU work: 64 lanes per wave64 instruction
         # (SQ_INSTS_VALU of a counter run on this kernel source) over this run's
-        # kernel time, against one wave64 instruction per CU per cycle
+        # kernel time, against the chip's vector rate
         ops = valu_insts * 64
         out["roofline"]["valu"] = {"lane_ops_per_launch": ops, "achieved": round(ops / (kern_ms * 1e-3) / 1e12, 2),
                                    "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
