@@ -526,7 +526,7 @@ static_assert(4 * mrhs_waves(1, MrhsMath::F32) <= (int)kMrhsMaxTileBlockRows &&
 constexpr int kMathF32 = (int)MrhsMath::F32, kMathBf16 = (int)MrhsMath::Bf16, kMathX6 = (int)MrhsMath::X6,
               kMathF32N = (int)MrhsMath::F32N;
 constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's BF16 half tile (40 BF16)
-constexpr int kATile32Stride = 32;    // floats per LDS row of a wave's FP32 half tile (swizzled)
+constexpr int kATile32Stride = 16;    // floats per LDS row of a wave's FP32 quarter tile (swizzled)
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -675,26 +675,26 @@ __device__ __forceinline__ void mrhs_load_bq(const float* __restrict__ btf, uint
 // Quarters of B operands loaded ahead (FP32 U), as many as the registers for
 // six (one group of right-hand sides) or four waves per SIMD leave room for.
 template <int NT>
-constexpr int kMrhsAhead = NT == 1 ? 3 : (NT == 2 ? 2 : 1);
+constexpr int kMrhsAhead = NT == 1 ? 1 : (NT == 2 ? 2 : 1);
 
 // FP32 U, up to 4 right-hand sides on v_mfma_f32_4x4x1f32 (16 blocks of
 // 4 x 4, K = 1), where the 16x16x4 MFMA would spend three quarters of its
 // cycles on zero columns.  MFMA block b = 4 t + s of lane l (t = l / 16,
 // s = l / 4 % 4) sums block row t over its share s of the block columns:
-// of each half of a step, block columns 2 s and 2 s + 1, one per "quarter"
-// q, one MFMA per coefficient column m; j = l % 4 is the right-hand side.
-// The B operands of quarter qi = 2 h + q of a step for this lane: B^T U's
-// four values m = 0..3 for right-hand side j at block column
-// cb + 8 h + 2 s + q, from the FP32 layout of one group of 16.
+// of each quarter q of a step, block column 4 q + s, one MFMA per
+// coefficient column m; j = l % 4 is the right-hand side.  The B operands of
+// quarter q of a step for this lane: B^T U's four values m = 0..3 for
+// right-hand side j at block column cb + 4 q + s, from the FP32 layout of
+// one group of 16.
 __device__ __forceinline__ void mrhs_load_bn(const float* __restrict__ btf, uint32_t cb, int qi, int lane, f32x4& b)
 {
     const uint32_t sh = ((uint32_t)lane >> 2) & 3u, j = (uint32_t)lane & 3u;
-    const uint32_t bc = cb + 8u * (uint32_t)(qi >> 1) + 2u * sh + (uint32_t)(qi & 1);
+    const uint32_t bc = cb + 4u * (uint32_t)qi + sh;
     b = *reinterpret_cast<const f32x4*>(btf + ((uint64_t)bc * 16 + j) * 4);
 }
-constexpr int kMrhsNarrowAhead = 3;
+constexpr int kMrhsNarrowAhead = 1;
 static_assert(kMrhsNarrowMax <= 4, "the 4x4x1 path holds one group of 4 right-hand sides");
-static_assert(16 * kATile32Stride >= 4 * 8 * 16, "a half's 32 blocks fit the FP32 tile");
+static_assert(16 * kATile32Stride >= 4 * 4 * 16, "a quarter's 16 blocks fit the FP32 tile");
 
 // X6: the B operand words (three parts, 16 bytes each) of one half and one
 // group of 16 right-hand sides for this lane.
@@ -749,8 +749,12 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
     const float* btf = static_cast<const float*>(btu);
     const uint16_t* btb = static_cast<const uint16_t*>(btu);
 
+    // 16-wave workgroups load each step's block words at the step (their
+    // registers hold no next step's words); smaller ones keep them in flight
+    // one step ahead
+    constexpr bool kAhead = W < 16;
     uint32_t w[NW];
-    {
+    if constexpr (kAhead) {
         const bool valid = bi < bi_end && bc0 + c < bc1;
         if (valid)
             load_block_words<NW>(stream + ((uint64_t)bi * nbc + bc0 + c) * NW, w);
@@ -771,11 +775,20 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
     for (uint32_t cb = bc0; cb < bc1; cb += 16) {
         // ---- this step's block words to the lane's LDS row; the next
         // step's in flight
+        if constexpr (!kAhead) {
+            const bool valid = bi < bi_end && cb + c < bc1;
+            if (valid)
+                load_block_words<NW>(stream + ((uint64_t)bi * nbc + cb + c) * NW, w);
+            else
+#pragma unroll
+                for (int q = 0; q < NW; ++q)
+                    w[q] = 0u;
+        }
 #pragma unroll
         for (int q = 0; q < NW; ++q)
             row[q * T] = w[q];
         const uint32_t w0 = w[0];
-        {
+        if constexpr (kAhead) {
             const bool valid = bi < bi_end && cb + 16 + c < bc1;
             if (valid)
                 load_block_words<NW>(stream + ((uint64_t)bi * nbc + cb + 16 + c) * NW, w);
@@ -827,77 +840,63 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
         for (int n = 0; n < NA; ++n)
             acc[n] = mf32x4{0.f, 0.f, 0.f, 0.f};
         if constexpr (NARROW) {
-            // ---- two halves of 8 block columns (the MFMA blocks and shares
-            // of mrhs_load_bn): the half's lanes write their blocks to the
-            // wave's tile as [t][q][s][r][m], row r's place XORed with 2 q so
-            // that the 8 writes of a block row fall on distinct banks; lane
-            // (t, s, r) then reads row r of its share's block column q and
-            // runs its 4 MFMAs (A: lane r + 4 b holds A_b[r]; B: lane j + 4 b
-            // holds B_b[j]; D_b[r][j]: lane j + 4 b, register r)
+            // ---- four quarters of 4 block columns (the MFMA blocks and
+            // shares of mrhs_load_bn): the quarter's lanes write their blocks
+            // to the wave's tile as [t][s][r][m], then lane (t, s, r) reads
+            // row r of its share's block column and runs its 4 MFMAs (A: lane
+            // r + 4 b holds A_b[r]; B: lane j + 4 b holds B_b[j]; D_b[r][j]:
+            // lane j + 4 b, register r)
             const int tn = lane >> 4, sn = (lane >> 2) & 3, rn = lane & 3;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int q = 0; q < 4; ++q) {
                 wave_sync_lds();
-                if ((c >> 3) == h) {
-                    const int qw = c & 1;
+                if ((c >> 2) == q) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        *reinterpret_cast<f32x4*>(at + ((t * 2 + qw) * 4 + ((c & 7) >> 1)) * 16 + (r ^ (2 * qw)) * 4) =
+                        *reinterpret_cast<f32x4*>(at + ((t * 4 + (c & 3)) * 4 + r) * 4) =
                             f32x4{sc[4 * r], sc[4 * r + 1], sc[4 * r + 2], sc[4 * r + 3]};
                 }
                 wave_sync_lds();
+                const int slot = q % AH;
+                const f32x4 a4 = *reinterpret_cast<const f32x4*>(at + ((tn * 4 + sn) * 4 + rn) * 4);
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int qi = 2 * h + q, slot = qi % AH;
-                    const f32x4 a4 =
-                        *reinterpret_cast<const f32x4*>(at + ((tn * 2 + q) * 4 + sn) * 16 + (rn ^ (2 * q)) * 4);
-#pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        acc[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a4[m], bq[slot][0][m], acc[0], 0, 0, 0);
-                    if (qi + AH < 4) // the quarter AH on into the slot just used
-                        mrhs_load_bn(btf, cb, qi + AH, lane, bq[slot][0]);
-                }
+                for (int m = 0; m < 4; ++m)
+                    acc[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a4[m], bq[slot][0][m], acc[0], 0, 0, 0);
+                if (q + AH < 4) // the quarter AH on into the slot just used
+                    mrhs_load_bn(btf, cb, q + AH, lane, bq[slot][0]);
             }
         } else if constexpr (MATH == kMathF32) {
-            // ---- two halves of 8 block columns: the half's lanes write their
-            // blocks to the wave's 16 x 32 tile (row 4t + r, a 4-float group
-            // per block column, the group index XORed with the row's low
-            // three bits so that the column reads below spread over the
-            // banks), then every lane reads its A operands for the half's two
-            // quarters
+            // ---- four quarters of 4 block columns: the quarter's lanes write
+            // their blocks to the wave's 16 x 16 tile (row 4t + r, a 4-float
+            // group per block column, the group index XORed with t so that
+            // the column reads below spread over the banks), then every lane
+            // reads its A operands
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int q = 0; q < 4; ++q) {
                 // the tile is the wave's own: lanes read what other lanes of
                 // the wave wrote, so each hand-over is a wave-scope
                 // release/acquire (no workgroup barrier is needed)
                 wave_sync_lds();
-                if ((c >> 3) == h) {
+                if ((c >> 2) == q) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int tr = 4 * t + r;
-                        *reinterpret_cast<f32x4*>(at + tr * kATile32Stride + 4 * ((c & 7) ^ (tr & 7))) =
+                    for (int r = 0; r < 4; ++r)
+                        *reinterpret_cast<f32x4*>(at + (4 * t + r) * kATile32Stride + 4 * ((c & 3) ^ t)) =
                             f32x4{sc[4 * r], sc[4 * r + 1], sc[4 * r + 2], sc[4 * r + 3]};
-                    }
                 }
                 wave_sync_lds();
-                const int ar = lane & 15;
+                const int slot = q % AH, ar = lane & 15;
+                // MFMA m contracts coefficient column m of the quarter's four
+                // block columns (K = block column): lane l holds A[l % 16][l / 16],
+                // coefficient (r, m) = ((l % 16) % 4, m) of block column l / 16
+                const f32x4 a4 =
+                    *reinterpret_cast<const f32x4*>(at + ar * kATile32Stride + 4 * ((lane >> 4) ^ (ar >> 2)));
 #pragma unroll
-                for (int qq = 0; qq < 2; ++qq) {
-                    const int q = 2 * h + qq, slot = q % AH;
-                    // MFMA m contracts coefficient column m of the quarter's
-                    // four block columns (K = block column): lane l holds
-                    // A[l % 16][l / 16], coefficient (r, m) = ((l % 16) % 4, m)
-                    // of the quarter's block column l / 16
-                    const f32x4 a4 = *reinterpret_cast<const f32x4*>(
-                        at + ar * kATile32Stride + 4 * (((lane >> 4) + 4 * qq) ^ (ar & 7)));
+                for (int m = 0; m < 4; ++m)
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
-#pragma unroll
-                        for (int n = 0; n < NT; ++n)
-                            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[m], bq[slot][n][m], acc[n], 0, 0, 0);
-                    if (q + AH < 4) // the quarter after next into the slot just used
-                        mrhs_load_bq<NT>(btf, cb + 4 * (q + AH), lane, bq[slot]);
-                }
+                    for (int n = 0; n < NT; ++n)
+                        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[m], bq[slot][n][m], acc[n], 0, 0, 0);
+                if (q + AH < 4) // the quarter after next into the slot just used
+                    mrhs_load_bq<NT>(btf, cb + 4 * (q + AH), lane, bq[slot]);
             }
         } else if constexpr (X6) {
             // ---- the coefficients' three BF16 parts, packed in pairs; both
