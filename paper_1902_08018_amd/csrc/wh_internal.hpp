@@ -86,13 +86,9 @@ inline MrhsMath mrhs_math(uint32_t k, bool bf16, bool force_fp32)
         return MrhsMath::F32;
     return k > 16 ? MrhsMath::X6 : (k <= kMrhsNarrowMax ? MrhsMath::F32N : MrhsMath::F32);
 }
-// Waves per workgroup for NT groups of 16 right-hand sides: 16 for FP32 U
-// up to 16 right-hand sides, 12 for BF16 U, 8 above (two workgroups per CU
-// in LDS and registers).
-constexpr int mrhs_waves(int nt, MrhsMath m)
-{
-    return m == MrhsMath::X6 ? 8 : (nt == 1 ? (m == MrhsMath::Bf16 ? 12 : 16) : 8);
-}
+// Waves per workgroup for NT groups of 16 right-hand sides: 16 up to 16
+// right-hand sides, 8 above (two workgroups per CU in LDS and registers).
+constexpr int mrhs_waves(int nt, MrhsMath m) { return m == MrhsMath::X6 ? 8 : (nt == 1 ? 16 : 8); }
 constexpr uint32_t kMrhsMaxTileBlockRows = 64;
 constexpr uint32_t kMaxRhs = 64;
 

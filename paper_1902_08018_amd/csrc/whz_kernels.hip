@@ -533,6 +533,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // the BF16 tile of a wave: 16 rows of 32 BF16 coefficients (8 block columns)
 // plus 8 of padding, in the same LDS as the FP32 quarter tile
 constexpr int kATile16Stride = 40;
+constexpr int kATileBf16Stride = 32; // BF16 per LDS row of a wave's BF16 half tile (swizzled)
 static_assert(16 * kATile16Stride * 2 <= 16 * kATileStride * 4, "the BF16 tile fits the FP32 one");
 
 __device__ __forceinline__ uint16_t to_bf16_rne(float f)
@@ -732,8 +733,7 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
     // the wave's A tile: FP32 halves (16 x 32, swizzled), BF16 halves, or
     // three BF16 halves (one per part) for X6
     __shared__ __align__(16) float atile[W][X6 ? 3 * 16 * kATileStride
-                                              : (MATH == kMathF32 || MATH == kMathF32N ? 16 * kATile32Stride
-                                                                                         : 16 * kATileStride)];
+                                              : (BF16U ? 16 * kATileBf16Stride / 2 : 16 * kATile32Stride)];
     uint32_t* row = lds + threadIdx.x;
     clear_pad<NW, T>(row);
     load_section_table<T>(tab); // the last workgroup barrier
@@ -809,9 +809,11 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
             for (int i = 0; i < kX6Ahead; ++i)
                 mrhs_load_bx<NT>(btb, cb, i / NT, i % NT, lane, bx[i]);
         } else if constexpr (BF16U) {
+            // the second half's operands load once the first half starts
+            // when 16 waves share the registers
             const uint32_t g = (uint32_t)lane >> 4, j = (uint32_t)lane & 15u;
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < (W >= 16 ? 1 : 2); ++h)
 #pragma unroll
                 for (int n = 0; n < NT; ++n)
                     bh[h][n] = *reinterpret_cast<const u32x4*>(
@@ -958,10 +960,11 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
                 }
         } else {
             // ---- two halves of 8 block columns (K = 32): the lanes of a half
-            // write their blocks' coefficients, rounded to BF16, to the tile
-            // (row 4t + r, columns 4 (c % 8) .. + 3); lane l then holds
-            // A[l % 16][8 (l / 16) .. + 7] (two block columns) and
-            // B[8 (l / 16) .. + 7][l % 16]
+            // write their blocks' coefficients, rounded to BF16, to the 16 x
+            // 32 tile (row 4t + r, columns 4 (c % 8) .. + 3, each 16-byte
+            // pair of block columns XORed with t so that the reads below
+            // spread over the banks); lane l then holds A[l % 16][8 (l / 16)
+            // .. + 7] (two block columns) and B[8 (l / 16) .. + 7][l % 16]
             uint16_t* at16 = reinterpret_cast<uint16_t*>(at);
             uint32_t pk[8];
 #pragma unroll
@@ -969,16 +972,24 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
                 pk[v] = (uint32_t)to_bf16_rne(sc[2 * v]) | (uint32_t)to_bf16_rne(sc[2 * v + 1]) << 16;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
+                if (W >= 16 && h == 1) {
+                    const uint32_t g = (uint32_t)lane >> 4, j = (uint32_t)lane & 15u;
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        bh[1][n] = *reinterpret_cast<const u32x4*>(
+                            btb + (((uint64_t)(cb / 2 + 4 + g) * NT + n) * 16 + j) * 8);
+                }
                 wave_sync_lds();
                 if ((c >> 3) == h) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        *reinterpret_cast<u32x2*>(at16 + (4 * t + r) * kATile16Stride + 4 * (c & 7)) =
-                            u32x2{pk[2 * r], pk[2 * r + 1]};
+                        *reinterpret_cast<u32x2*>(at16 + (4 * t + r) * kATileBf16Stride +
+                                                  8 * (((c & 7) >> 1) ^ t) + 4 * (c & 1)) = u32x2{pk[2 * r], pk[2 * r + 1]};
                 }
                 wave_sync_lds();
-                const u32x4 av =
-                    *reinterpret_cast<const u32x4*>(at16 + (lane & 15) * kATile16Stride + 8 * (lane >> 4));
+                const int ar = lane & 15;
+                const u32x4 av = *reinterpret_cast<const u32x4*>(at16 + ar * kATileBf16Stride +
+                                                                 8 * ((lane >> 4) ^ (ar >> 2)));
                 const mbf16x8 a = __builtin_bit_cast(mbf16x8, av);
 #pragma unroll
                 for (int n = 0; n < NT; ++n)
