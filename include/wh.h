@@ -202,17 +202,18 @@ wh_status wh_gemv(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t 
  * launch plan, kernels and result as wh_gemv, so y is the same.
  *
  * Workspace: the FP64 slab partials live in a device array of the library's
- * of WH_NOALLOC_SCRATCH_BYTES (32 MiB), one per GPU, held from the first
+ * of WH_NOALLOC_SCRATCH_BYTES (64 MiB), one per GPU, held from the first
  * wh_create on that GPU until the process ends.  A call whose plan needs more
  * (column slabs x the range's rows rounded up to whole block rows x 8 bytes;
  * wh_gemv_plan_info gives both) returns WH_ERR_SCRATCH and launches nothing:
- * 65536 x 65536 needs 22.5 MB.  Calls whose work overlaps on one GPU (other
+ * 65536 x 65536 needs 32 MiB, and no matrix of up to 2^33 values more than
+ * 44 MiB.  Calls whose work overlaps on one GPU (other
  * streams, other contexts) share that array and race; calls in order on one
  * stream are safe.  The array keeps the last call's contents; nothing in it
  * has to start at zero.  No hipMalloc, hipFree, event or memset is issued, so
  * the call can be captured into a graph (the graph then keeps using the
  * array). */
-#define WH_NOALLOC_SCRATCH_BYTES (32ull << 20)
+#define WH_NOALLOC_SCRATCH_BYTES (64ull << 20)
 wh_status wh_gemv_noalloc(wh_ctx *ctx, wh_mat m, const float *d_u, float *d_y, uint32_t row_begin,
                           uint32_t row_end, uint32_t flags, void *stream);
 

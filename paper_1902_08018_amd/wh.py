@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 WH_OK, WH_PENDING = 0, 1
 WH_ERR_INVALID, WH_ERR_SHAPE, WH_ERR_FORMAT, WH_ERR_NOMEM = -1, -2, -3, -4
 WH_ERR_BUDGET, WH_ERR_DEVICE, WH_ERR_NOT_FOUND, WH_ERR_SCRATCH = -5, -6, -7, -8
-WH_NOALLOC_SCRATCH_BYTES = 32 << 20
+WH_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 WH_FMT_ZFP_FIXED_RATE, WH_FMT_F32, WH_FMT_F16, WH_FMT_BF16, WH_FMT_FP8E4M3_BS4 = 1, 2, 3, 4, 5
 WH_FMT_ZFP_FIXED_PRECISION, WH_FMT_ZFP_FIXED_ACCURACY = 6, 7

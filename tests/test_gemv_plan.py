@@ -1,6 +1,7 @@
 """The fused GEMV's launch planner (host logic, no GPU): every block of the
 range is covered exactly by the launch, and the measured rule holds (8 lanes
-per block row for square and tall matrices, wider groups for few block rows,
+per block row for square and tall matrices, wider groups for few block rows
+(tiles at least 90 % full),
 narrower ones for few block columns; 2048-ish workgroups; few slabs on
 large matrices)."""
 import math
@@ -21,8 +22,9 @@ def test_plan_covers_the_range(rows, cols, rb, re):
     assert p["bi_begin"] == rb // 4 and p["bi_end"] == (re + 3) // 4 and p["skip"] == rb % 4
     lanes = p["lanes"]
     assert lanes in (4, 8, 16, 32, 64, 128, 256, 512) and p["rows_per_group"] in (1, 2, 4)
-    # rows: tiles of (512 / lanes) * rows_per_group block rows
-    tile_rows = (512 // lanes) * p["rows_per_group"]
+    # rows: tiles of (workgroup lanes / lanes) * rows_per_group block rows
+    assert p["wg_lanes"] in (768, 1024)
+    tile_rows = (p["wg_lanes"] // lanes) * p["rows_per_group"]
     assert p["ntiles"] * tile_rows >= p["bi_end"] - p["bi_begin"] > (p["ntiles"] - 1) * tile_rows
     # columns: slabs of whole lane groups, the last one non-empty
     assert p["slab_bc"] % lanes == 0
@@ -33,9 +35,9 @@ def test_measured_rule():
     big = wh.wh_gemv_plan_info(65536, 65536)
     assert big["lanes"] == 8 and big["rows_per_group"] == 1 and big["nslab"] <= 64
     slit = wh.wh_gemv_plan_info(378, 256000)
-    assert slit["lanes"] == 16 and slit["ntiles"] == 3          # 95 block rows in 32-row tiles
+    assert slit["lanes"] == 32 and slit["ntiles"] == 3          # 95 block rows in 32-row tiles
     tall = wh.wh_gemv_plan_info(256000, 378)
-    assert tall["lanes"] == 8 and tall["nslab"] <= 2
+    assert tall["lanes"] == 8 and tall["nslab"] <= 4            # 95 block columns, ~2000 workgroups
     narrow = wh.wh_gemv_plan_info(4096, 12)
     assert narrow["lanes"] == 4                                  # 3 block columns
     for shape in [(16384, 16384), (10000, 10000), (32768, 16384)]:

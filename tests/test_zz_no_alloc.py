@@ -71,8 +71,8 @@ def test_noalloc_two_calls_match_gemv(gpu_ctx, flags):
 
 
 def test_noalloc_rejects_a_plan_beyond_the_array():
-    # 1024 column slabs over 8192 rows need 64 MiB of partials
-    rows, cols, rate = 8192, 32768, 2
+    # 1024 column slabs over 16384 rows need 128 MiB of partials
+    rows, cols, rate = 16384, 32768, 2
     old = os.environ.get("WH_GEMV_SLABS")
     os.environ["WH_GEMV_SLABS"] = "1024"
     try:
