@@ -298,13 +298,14 @@ __device__ __forceinline__ void exact_block_coeffs(const uint32_t (&cf)[16], int
         sc[i] = __builtin_ldexpf(f[i], emax - 30);
 }
 
-// The workgroup's lanes form groups of 2^lg lanes (4 to 512).  A group
-// sweeps a block row's slab of block columns, its lanes striding them; the
-// workgroup's tile is (512 >> lg) groups x rpg block rows, group g taking the
-// tile's rows g, g + groups, ...  Square and wide matrices use one group of
-// 512 lanes; narrow ones (few block columns) use small groups, so that every
-// lane has blocks to decode.  Output row i of the range is matrix row
-// 4 * bi_begin + skip + i.
+// The workgroup's lanes (1024, or 768 from 17 bits/value) form groups of
+// 2^lg lanes (4 to 512).  A group sweeps a block row's slab of block columns,
+// its lanes striding them; the workgroup's tile is (lanes >> lg) groups x rpg
+// block rows, group g taking the tile's rows g, g + groups, ...  Square and
+// tall matrices use groups of 8 lanes (a wave decodes an 8 x 8 patch of
+// blocks); narrow ones (few block columns) use smaller groups, so that every
+// lane has blocks to decode, and few block rows wider ones.  Output row i of
+// the range is matrix row 4 * bi_begin + skip + i.
 // two workgroups per CU: 1024-lane ones in 64 VGPRs (32 waves)
 template <int NW>
 constexpr int kGemvMinWaves = kGemvThreads<NW> == 1024 ? 8 : 6;
@@ -482,20 +483,21 @@ __global__ void __launch_bounds__(kGemvThreads<NW>, kGemvMinWaves<NW>) gemv_kern
 // start: each wave runs on its own.
 //
 // Workgroup = mrhs_waves(NT) waves, a tile of 4 block rows per wave x a slab
-// of block columns: 12 waves (768 lanes) for up to 16 right-hand sides, so
-// that two workgroups fit a CU in LDS and 24 waves in registers; 8 waves for
-// more, whose FP64 sums leave registers for 16 to 20 waves.  Per step of
-// 16 block columns, each lane decodes one block of its wave's 4 x 16 tile
-// (the next step's block words are already in flight) and keeps its
-// coefficients, scaled by the block's 2^(emax - 30), in registers; then
+// of block columns: 16 waves (1024 lanes) for up to 16 right-hand sides, so
+// that two workgroups fit a CU in LDS and 32 waves in 64 VGPRs each; 8 waves
+// for more, whose FP64 sums leave registers for 16 waves.  Per step of 16
+// block columns, each lane decodes one block of its wave's 4 x 16 tile (with
+// 8-wave workgroups the next step's block words are already in flight) and
+// keeps its coefficients, scaled by the block's 2^(emax - 30), in registers;
+// then
 //   FP32 U   four quarters of 4 block columns: the quarter's lanes write their
 //            blocks to the wave's 16 x 16 LDS tile, which is contracted with
 //            v_mfma_f32_16x16x4f32, K = the quarter's 4 block columns, one
 //            MFMA per coefficient column: 4 MFMAs per quarter and 16
 //            right-hand sides
-//   FP32 U,  up to 4 right-hand sides: the same halves on
+//   FP32 U,  up to 4 right-hand sides: the same quarters on
 //   k <= 4   v_mfma_f32_4x4x1f32 (16 blocks of 4 x 4, K = 1; below,
-//            mrhs_load_bn): 8 MFMAs per half, a quarter of the 16x16x4
+//            mrhs_load_bn): 4 MFMAs per quarter, a quarter of the 16x16x4
 //            cycles, which at k <= 4 would contract zero columns
 //   BF16 U   two halves of 8 block columns, written rounded to BF16 and
 //            contracted with v_mfma_f32_16x16x32_bf16 (K = 32), 1 MFMA per
@@ -525,16 +527,16 @@ static_assert(4 * mrhs_waves(1, MrhsMath::F32) <= (int)kMrhsMaxTileBlockRows &&
               "block rows per multi-RHS workgroup");
 constexpr int kMathF32 = (int)MrhsMath::F32, kMathBf16 = (int)MrhsMath::Bf16, kMathX6 = (int)MrhsMath::X6,
               kMathF32N = (int)MrhsMath::F32N;
-constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's BF16 half tile (40 BF16)
+constexpr int kATileStride = 16 + 4; // floats per LDS row of a wave's X6 part tile (40 BF16)
 constexpr int kATile32Stride = 16;    // floats per LDS row of a wave's FP32 quarter tile (swizzled)
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-// the BF16 tile of a wave: 16 rows of 32 BF16 coefficients (8 block columns)
-// plus 8 of padding, in the same LDS as the FP32 quarter tile
+// an X6 part tile of a wave: 16 rows of 32 BF16 coefficients (8 block
+// columns) plus 8 of padding
 constexpr int kATile16Stride = 40;
+static_assert(16 * kATile16Stride * 2 <= 16 * kATileStride * 4, "an X6 part tile fits its LDS");
 constexpr int kATileBf16Stride = 32; // BF16 per LDS row of a wave's BF16 half tile (swizzled)
-static_assert(16 * kATile16Stride * 2 <= 16 * kATileStride * 4, "the BF16 tile fits the FP32 one");
 
 __device__ __forceinline__ uint16_t to_bf16_rne(float f)
 {
@@ -716,7 +718,7 @@ __device__ __forceinline__ void mrhs_load_bx(const uint16_t* __restrict__ btb, u
 constexpr int kX6Ahead = 2;
 
 // two workgroups per CU, i.e. W / 2 waves per SIMD: the register budget the
-// compiler must meet (80 VGPRs at 12 waves, 128 at 8)
+// compiler must meet (64 VGPRs at 16 waves, 128 at 8)
 template <int NW, int MATH, int NT>
 __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_waves(NT, (MrhsMath)MATH) / 2)
     mrhs_kernel(const uint32_t* __restrict__ stream, const void* __restrict__ btu, uint32_t k, float* __restrict__ Y,
@@ -730,8 +732,8 @@ __global__ void __launch_bounds__(64 * mrhs_waves(NT, (MrhsMath)MATH), mrhs_wave
     constexpr int NA = NARROW ? 1 : NT;
     __shared__ uint32_t lds[T * kStagedWords<NW>];
     __shared__ uint32_t tab[kSecEntries];
-    // the wave's A tile: FP32 halves (16 x 32, swizzled), BF16 halves, or
-    // three BF16 halves (one per part) for X6
+    // the wave's A tile: FP32 quarters (16 x 16, swizzled), BF16 halves
+    // (16 x 32, swizzled), or three BF16 halves (one per part) for X6
     __shared__ __align__(16) float atile[W][X6 ? 3 * 16 * kATileStride
                                               : (BF16U ? 16 * kATileBf16Stride / 2 : 16 * kATile32Stride)];
     uint32_t* row = lds + threadIdx.x;
