@@ -346,8 +346,8 @@ def test_fig11_pipeline_arithmetic():
     after = metrics.pipeline_latency(t_tr, t_comp, t_dec, ratio)
     assert before == pytest.approx(100.0)
     assert after == pytest.approx(53.28, abs=0.01)
-    assert 1 - after / before == pytest.approx(0.47, abs=0.01)       # "reduced by around 47 %"
-    assert t_dec / after == pytest.approx(0.52, abs=0.01)            # "decompressor ... 52 %"
+    assert 1 - after / before == pytest.approx(0.47, abs=0.01)       # Sec. 5.2: latency cut by about 47 %
+    assert t_dec / after == pytest.approx(0.52, abs=0.01)            # Sec. 5.2: decode is 52 % of the time
     # Table 1 period: transfer-bound before, decode+compute-bound after
     assert metrics.pipeline_period(t_tr, t_comp) == t_tr
     assert metrics.pipeline_period(t_tr, t_comp, t_dec, ratio) == pytest.approx(t_comp + t_dec)
